@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X Helmholtz hot path.
+
+One step = one pass of the whole path over the 128^3 layered workload
+(h = 12.5 m, 8 Hz, absorbing layer 15, velocity 1500-4500 m/s layers with 5 %
+correlated perturbations, 16 sources on the top interior plane, 32 x 32
+receivers): forward ML-GMRES solves of all 16 sources (complex64, FP64
+residual, rel. res. 1e-6), receiver sampling and misfit, adjoint solves of
+all 16 sources, and the gradient kernel -- misfit_gradient() through the C
+ABI.  `value` = Helmholtz solves per second over the timed steps (32 solves
+per step), inputs resident in HBM.
+
+Also measured in the same run:
+* the stencil kernel alone (helm_apply on the same grid with 16 right-hand
+  sides) timed with HIP events on the launch stream, reported against the
+  8 TB/s HBM peak with the algorithmic bytes 16*S + 4 per grid point;
+* the FP64 CPU oracle on a bounded sample of the same workload (rank 0).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = ("stencil GB/s (% HBM peak) + Helmholtz solves/sec, batched vs plain, "
+          "at rel.res 1e-6")
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--stencil-reps", type=int, default=50)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--nrec", type=int, default=32, help="receivers per axis")
+    return p.parse_args()
+
+
+def cpu_baseline(w, m32, src, rec, omega, target_s=0.0):
+    """Oracle timing on a bounded sample: outer FGMRES Arnoldi steps (one
+    V-cycle + one operator apply + modified Gram-Schmidt each) of one source
+    on the full grid, extrapolated to one solve with the GPU's mean outer
+    step count."""
+    from oracle import operators as ops
+    from oracle import mlgmres, fwi
+    g = ops.make_grid(w.n, w.h, w.npml, omega, w.v_ref)
+    hier = mlgmres.Hierarchy(g, m32, mlgmres.MLOptions())
+    q = fwi.point_source(g, tuple(src[0]))
+    A = hier.A(0)
+    t0 = time.perf_counter()
+    steps = 0
+    v = q / np.linalg.norm(q)
+    basis = [v]
+    while True:
+        z = hier.vcycle(0, v)
+        wv = A(z)
+        for b in basis:
+            wv = wv - np.vdot(b, wv) * b
+        v = wv / np.linalg.norm(wv)
+        basis.append(v)
+        steps += 1
+        if time.perf_counter() - t0 >= target_s or steps >= 1:
+            break
+    dt = (time.perf_counter() - t0) / steps
+    return dt, steps
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (one process per GPU; the "
+              "multi-GPU sharding over (source, frequency) pairs is not part of it). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1703_09268_amd as hx
+    import workloads
+
+    dev = torch.device("cuda:0")
+    w = workloads.c2_layered()
+    nsrc = len(w.src)
+    rec = workloads.surface_positions(w.n, w.npml, (args.nrec, args.nrec))
+    grid = hx.Grid(n=w.n, h=w.h, npml=w.npml, v_ref=w.v_ref, dtype="c64")
+    opts = hx.SolverOpts(tol=1e-6, max_cycles=30)
+    m_t = torch.tensor(w.m, dtype=torch.float32, device=dev)
+    # observed data: forward-modelled from a perturbed model (untimed input)
+    rng = np.random.default_rng(workloads.SEED_BASE + 2)
+    m_true = (w.m * (1.0 + 0.02 * workloads.gaussian_random_field(rng, w.n, 4.0)))
+    mt_t = torch.tensor(m_true, dtype=torch.float32, device=dev)
+    u_true = torch.empty((nsrc,) + w.n, dtype=torch.complex64, device=dev)
+    _, _, _ = hx.misfit_gradient(grid, mt_t, w.omega, w.src, rec,
+                                 torch.zeros((nsrc, len(rec)), dtype=torch.complex64, device=dev),
+                                 u_store=u_true, forward_only=True, opts=opts)
+    ridx = torch.tensor(rec.astype(np.int64), device=dev)
+    d_t = u_true[:, ridx[:, 0], ridx[:, 1], ridx[:, 2]].contiguous()
+    del u_true
+    grad = torch.empty(w.n, dtype=torch.float32, device=dev)
+
+    def step():
+        return hx.misfit_gradient(grid, m_t, w.omega, w.src, rec, d_t, grad=grad, opts=opts)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    fval = None
+    for _ in range(args.steps):
+        fval, _, inf = step()
+        infos.extend(inf)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    solves = args.steps * 2 * nsrc
+    sps = solves / elapsed
+    relres = [i.relres_fp64 for i in infos]
+    cycles = [i.cycles for i in infos]
+
+    # ---- stencil kernel alone: 16 right-hand sides, HIP events on the stream
+    S = nsrc
+    xs = [torch.randn((S,) + w.n, dtype=torch.complex64, device=dev) for _ in range(2)]
+    ys = [torch.empty_like(xs[0]) for _ in range(2)]
+    for i in range(3):
+        hx.helm_apply(grid, m_t, w.omega, xs[i % 2], out=ys[i % 2])
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for i in range(args.stencil_reps):
+        hx.helm_apply(grid, m_t, w.omega, xs[i % 2], out=ys[i % 2])
+    e1.record(stream)
+    e1.synchronize()
+    st_ms = e0.elapsed_time(e1) / args.stencil_reps
+    N = w.N
+    bytes_launch = (16 * S + 4) * N
+    gbs = bytes_launch / (st_ms * 1e-3) / 1e9
+    del xs, ys
+
+    out = {
+        "metric": METRIC,
+        "value": round(sps, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {
+            "workload": "128^3 layered+random, h=12.5 m, 8 Hz, 16 sources, "
+                        f"{args.nrec}x{args.nrec} receivers, misfit + gradient "
+                        "(16 forward + 16 adjoint ML-GMRES solves to rel.res 1e-6)",
+            "grid": list(w.n), "sources": nsrc, "receivers": int(len(rec)),
+            "solver": "FGMRES(5) + 3-grid V-cycle (3,5,3,5), complex64, FP64 outer residual",
+            "solves_per_step": 2 * nsrc,
+        },
+        "solve_stats": {
+            "max_relres_fp64": max(relres), "mean_outer_cycles": float(np.mean(cycles)),
+            "max_outer_cycles": int(max(cycles)), "misfit": fval,
+        },
+        "stencil": {
+            "kernel": "k_h7<float,...,64,4> (helm_apply, 16 rhs)",
+            "ms_per_launch": round(st_ms, 5), "GB_s": round(gbs, 1),
+            "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "bytes_per_point": f"16*{S}+4",
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+        },
+    }
+    if not args.no_cpu_baseline:
+        dt, nst = cpu_baseline(w, m_t.double().cpu().numpy(), w.src, rec, w.omega)
+        steps_per_solve = 5.0 * float(np.mean(cycles))
+        out["cpu_baseline"] = {
+            "value": round(1.0 / (dt * steps_per_solve), 6), "unit": "solves/s",
+            "cores": 1, "kind": "oracle",
+            "sample": f"{nst} outer FGMRES steps (V-cycle + apply + MGS) of one source on the "
+                      f"full 128^3 grid, {dt:.2f} s/step, scaled by {steps_per_solve:.1f} steps "
+                      "per solve (GPU mean)",
+        }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,210 @@
+/*
+ * helm.h -- C ABI of the MI355X (gfx950) frequency-domain 3D Helmholtz
+ * library: matrix-free operator apply, ML-GMRES-preconditioned solves and the
+ * adjoint-state least-squares misfit gradient.
+ *
+ * Problem (Da Silva & Herrmann, arXiv:1703.09268, Preamble, eqs. helmholtz
+ * and mainprob; Appendix A, the linear system L u + omega^2 A diag(m) u = q):
+ *
+ *   H(m) u = q,   H = L + omega^2 A diag(m),   m = 1/v^2  [s^2/m^2]
+ *
+ * on a rectangular grid that already includes the absorbing layer (the
+ * paper's extended domain Omega'), zero Dirichlet data outside the grid.
+ * L is the layer-stretched 7-point Laplacian (A = I), or the compact
+ * 27-point Laplacian on rows away from the layer with the 7-point stretched
+ * row inside it (A = 27-point mass distribution, real symmetric).
+ *
+ * Layer (the paper leaves the damping function open; this is the library's
+ * definition): per axis, with node coordinate t and
+ *   d(t) = max(0, npml - t, t - (n - 1 - npml)),
+ *   sigma(t) = sigma_max (d / npml)^2,
+ *   sigma_max = 3 v_ref ln(1/pml_R) / (2 npml h),
+ *   s(t) = 1 + i sigma(t) / omega,
+ * the derivative d/dx becomes (1/s) d/dx; the 7-point row is
+ *   sum_a cp_a (u[p+e_a] - u[p]) - cm_a (u[p] - u[p-e_a]),
+ *   cp = 1/(h^2 s(p) s(p+1/2)),  cm = 1/(h^2 s(p) s(p-1/2)).
+ *
+ * Data layout (all entry points)
+ *   * Grids are C-ordered [nx][ny][nz], z fastest, index (i*ny + j)*nz + k.
+ *   * Complex numbers are interleaved {re, im}; HELM_C64 = 2 x float,
+ *     HELM_C128 = 2 x double.  The model m is float for HELM_C64 and double
+ *     for HELM_C128.
+ *   * Several right-hand sides (nrhs) are stored one after the other:
+ *     element p of right-hand side r is at offset r*N + p, N = nx*ny*nz.
+ *   * Arrays marked "dev" are device pointers (hipMalloc or a torch tensor's
+ *     data_ptr on the current device); "host" marks host memory.
+ *
+ * Ownership: the caller owns every buffer it passes and keeps it alive until
+ * the work on `stream` has completed; the library never frees caller memory.
+ * The context owns a workspace pool (grown on demand, freed by
+ * helm_destroy).  `stream` is a hipStream_t (NULL = the null stream); all
+ * device work is enqueued on it.  A context is not thread-safe: use one per
+ * host thread.
+ *
+ * Errors: every entry point returns a helm_status; nothing throws or aborts
+ * across the ABI.  On an error return helm_last_error(ctx) describes it.
+ * Invalid arguments (null pointers, sizes < 3, npml >= n/2, omega <= 0,
+ * nrhs < 1, out-of-grid source or receiver nodes, unknown enums) return
+ * HELM_E_INVAL before any device work is enqueued.
+ */
+#ifndef HELM_H
+#define HELM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HELM_OK = 0,
+  HELM_NOT_CONVERGED = 1, /* tolerance not reached in max_cycles */
+  HELM_BREAKDOWN = 2,     /* non-finite residual (NaN / Inf input) */
+  HELM_E_INVAL = -1,
+  HELM_E_NOMEM = -2,
+  HELM_E_HIP = -3,
+  HELM_E_UNSUPPORTED = -4
+} helm_status;
+
+typedef enum { HELM_C64 = 0, HELM_C128 = 1 } helm_dtype;
+typedef enum { HELM_7PT = 0, HELM_27PT = 1 } helm_stencil;
+typedef enum { HELM_GMRES = 0, HELM_FGMRES_ML = 1 } helm_method;
+
+/* Grid, layer and discretisation of one Helmholtz operator. */
+typedef struct {
+  int32_t n[3];    /* nodes per axis, layer included (each >= 3)          */
+  double h;        /* grid spacing [m]                                     */
+  int32_t npml;    /* layer width in nodes on each face (0 = no layer)     */
+  double pml_R;    /* nominal reflection coefficient of the layer, (0, 1)  */
+  double v_ref;    /* reference velocity of the layer profile [m/s]        */
+  int32_t stencil; /* helm_stencil                                         */
+  int32_t dtype;   /* helm_dtype                                           */
+  double w27[7];   /* 27-point weights w1,w2,w3 (Laplacian) and wm1..wm4
+                      (mass: centre, 6 faces, 12 edges, 8 corners); used
+                      only with HELM_27PT; w1+w2+w3 = 1 and
+                      wm1+6wm2+12wm3+8wm4 = 1 are expected, not enforced   */
+} helm_grid;
+
+/* Solver options (paper, ML-GMRES section; defaults by helm_default_opts). */
+typedef struct {
+  int32_t method;     /* HELM_GMRES: restarted GMRES(restart) on H;
+                         HELM_FGMRES_ML: FGMRES(restart) preconditioned by
+                         the recursive multilevel V-cycle                   */
+  int32_t restart;    /* Krylov dimension of the outer solver (<= 32)      */
+  int32_t max_cycles; /* restart cycles of the outer solver                */
+  double tol;         /* target FP64 relative residual ||q - H u|| / ||q|| */
+  int32_t ks_o, ks_i; /* smoother GMRES: cycles, Krylov dimension          */
+  int32_t kc_o, kc_i; /* coarse (F)GMRES: cycles, Krylov dimension         */
+  int32_t levels;     /* number of grids (2..4)                            */
+  int32_t warm_start; /* 1: u holds the initial guess on entry             */
+} helm_solver_opts;
+
+/* Per right-hand-side result of a solve. */
+typedef struct {
+  int32_t status;     /* helm_status of this right-hand side              */
+  int32_t cycles;     /* outer restart cycles performed                    */
+  int32_t inner_its;  /* outer Arnoldi steps performed                     */
+  int32_t pad_;
+  int64_t matvecs;    /* fine-grid operator applications (incl. residuals) */
+  double relres_fp64; /* ||q - H u|| / ||q|| of the returned iterate, FP64 */
+} helm_solve_info;
+
+typedef struct helm_ctx helm_ctx;
+
+/* Create a context bound to HIP device `device` (hipSetDevice is called on
+ * every entry).  *ctx receives the handle.  Fails with HELM_E_HIP if the
+ * device does not exist. */
+helm_status helm_create(helm_ctx** ctx, int device);
+
+/* Synchronise the context's device and release the workspace. */
+helm_status helm_destroy(helm_ctx* ctx);
+
+/* Text of the last error on this context (static storage inside the
+ * context; empty string when none).  ctx may be NULL (global message). */
+const char* helm_last_error(const helm_ctx* ctx);
+
+/* Library version string. */
+const char* helm_version(void);
+
+/* Fill *o with the paper's settings: FGMRES(5) preconditioned by the
+ * 3-grid V-cycle with (ks_o, ks_i, kc_o, kc_i) = (3, 5, 3, 5), relative
+ * residual 1e-6 (paper, ML-GMRES section, preconditioner-performance
+ * experiment), max_cycles 50. */
+void helm_default_opts(helm_solver_opts* o);
+
+/* Device bytes the context's workspace needs for a solve with these
+ * arguments (0 if the arguments are invalid). */
+size_t helm_workspace_bytes(const helm_grid* g, const helm_solver_opts* o,
+                            int nrhs);
+
+/* y = H(m) x  (adjoint = 0)  or  y = H(m)^H x  (adjoint = 1) for nrhs
+ * right-hand sides sharing m and omega (the discrete operator of the
+ * Preamble; the paper's H*x and H'*x).
+ *   m     dev, N reals (float for C64, double for C128)
+ *   omega angular frequency 2 pi f [rad/s], > 0
+ *   x, y  dev, nrhs*N complex of g->dtype; must not overlap.
+ * Asynchronous on `stream`. */
+helm_status helm_apply(helm_ctx* ctx, const helm_grid* g, const void* m,
+                       double omega, int adjoint, int nrhs, const void* x,
+                       void* y, void* stream);
+
+/* Solve H(m) u = q (adjoint = 0) or H(m)^H u = q (adjoint = 1) for nrhs
+ * right-hand sides sharing m and omega (the paper's H\Q, all sources of one
+ * frequency as one block) with the solver in *o (NULL = defaults).
+ *   q     dev, nrhs*N complex of g->dtype
+ *   u     dev, nrhs*N complex of g->dtype; initial guess if o->warm_start,
+ *         otherwise ignored on entry; overwritten with the solution
+ *   info  host, nrhs entries (may be NULL)
+ * The outer iterate and its residual are kept in FP64 (mixed-precision
+ * refinement) for HELM_C64; inner Krylov work is in the grid's dtype.
+ * Returns HELM_OK when every right-hand side reached o->tol,
+ * HELM_NOT_CONVERGED if any did not (u still holds the best iterate),
+ * HELM_BREAKDOWN if a residual became non-finite.  Synchronises `stream`
+ * once per outer cycle (convergence test) and before returning. */
+helm_status helm_solve(helm_ctx* ctx, const helm_grid* g, const void* m,
+                       double omega, int adjoint, int nrhs, const void* q,
+                       void* u, const helm_solver_opts* o,
+                       helm_solve_info* info, void* stream);
+
+/* misfit_gradient flags */
+#define HELM_MG_FORWARD_ONLY 1 /* solve forward, return f; no gradient     */
+#define HELM_MG_REUSE_U 2      /* u_store already holds H^{-1} q_s         */
+#define HELM_MG_ACCUMULATE 4   /* g += gradient instead of g = gradient    */
+
+/* Least-squares misfit and its adjoint-state gradient for one frequency
+ * (paper, Listing of PDEfunc, case OBJ; Table derivstuff rows u, V, grad f;
+ * Appendix A, eq. dHadj):
+ *   q_s = amp_s e_{src_s} / h^3            (on-node point source)
+ *   u_s = H^{-1} q_s,   r_s = P_r u_s - d_s,   f = 1/2 sum_s ||r_s||^2
+ *   v_s = -H^{-H} P_r^T r_s
+ *   g   = sum_s Re(omega^2 conj(u_s) * (A^H v_s))   (real, N entries)
+ * Arguments:
+ *   m        dev, N reals (float for C64, double for C128)
+ *   nsrc     number of sources (>= 1), solved together as one block
+ *   src_idx  host int32 [nsrc][3] node indices (i, j, k)
+ *   src_amp  host double [nsrc][2] complex amplitudes (NULL = all 1)
+ *   nrec     number of receivers (>= 1); rec_idx host int32 [nrec][3]
+ *   d        dev, [nsrc][nrec] complex of g->dtype, observed data
+ *   f        host, receives the misfit (FP64 accumulation)
+ *   grad     dev, N reals (float for C64, double for C128); overwritten
+ *            (or accumulated into with HELM_MG_ACCUMULATE); may be NULL
+ *            with HELM_MG_FORWARD_ONLY
+ *   u_store  dev, [nsrc][N] complex of g->dtype or NULL: receives the
+ *            forward fields (or supplies them with HELM_MG_REUSE_U)
+ *   flags    HELM_MG_* bits
+ *   info     host, 2*nsrc entries (forward then adjoint solves) or NULL
+ * Returns the worst status of the solves. */
+helm_status misfit_gradient(helm_ctx* ctx, const helm_grid* g, const void* m,
+                            double omega, int nsrc, const int32_t* src_idx,
+                            const double* src_amp, int nrec,
+                            const int32_t* rec_idx, const void* d, double* f,
+                            void* grad, void* u_store, int flags,
+                            const helm_solver_opts* o, helm_solve_info* info,
+                            void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HELM_H */

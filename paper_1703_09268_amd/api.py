@@ -1,0 +1,242 @@
+"""Python binding of the C ABI (argument marshalling only).
+
+Every function checks tensor placement, dtype, shape and contiguity, then
+calls the entry point of the same name in ``libhelm.so`` on the current
+torch stream.  All arithmetic happens in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+class HelmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{L.STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+@dataclass
+class Grid:
+    """Mirror of ``helm_grid``: grid incl. absorbing layer, z fastest."""
+
+    n: Sequence[int]
+    h: float
+    npml: int
+    v_ref: float
+    pml_R: float = 1e-3
+    stencil: str = "7pt"  # "7pt" | "27pt"
+    dtype: str = "c64"  # "c64" | "c128"
+    w27: Sequence[float] = (1.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0)
+
+    @property
+    def N(self) -> int:
+        return int(self.n[0]) * int(self.n[1]) * int(self.n[2])
+
+    @property
+    def complex_dtype(self):
+        return torch.complex64 if self.dtype == "c64" else torch.complex128
+
+    @property
+    def real_dtype(self):
+        return torch.float32 if self.dtype == "c64" else torch.float64
+
+    def c_struct(self) -> L.helm_grid:
+        g = L.helm_grid()
+        for a in range(3):
+            g.n[a] = int(self.n[a])
+        g.h = float(self.h)
+        g.npml = int(self.npml)
+        g.pml_R = float(self.pml_R)
+        g.v_ref = float(self.v_ref)
+        g.stencil = {"7pt": L.HELM_7PT, "27pt": L.HELM_27PT}[self.stencil]
+        g.dtype = {"c64": L.HELM_C64, "c128": L.HELM_C128}[self.dtype]
+        for c in range(7):
+            g.w27[c] = float(self.w27[c])
+        return g
+
+
+@dataclass
+class SolverOpts:
+    """Mirror of ``helm_solver_opts``; defaults are the paper's settings."""
+
+    method: str = "fgmres_ml"  # "fgmres_ml" | "gmres"
+    restart: int = 5
+    max_cycles: int = 50
+    tol: float = 1e-6
+    ks_o: int = 3
+    ks_i: int = 5
+    kc_o: int = 3
+    kc_i: int = 5
+    levels: int = 3
+    warm_start: bool = False
+
+    def c_struct(self) -> L.helm_solver_opts:
+        o = L.helm_solver_opts()
+        o.method = {"gmres": L.HELM_GMRES, "fgmres_ml": L.HELM_FGMRES_ML}[self.method]
+        o.restart, o.max_cycles, o.tol = int(self.restart), int(self.max_cycles), float(self.tol)
+        o.ks_o, o.ks_i, o.kc_o, o.kc_i = int(self.ks_o), int(self.ks_i), int(self.kc_o), int(self.kc_i)
+        o.levels = int(self.levels)
+        o.warm_start = int(bool(self.warm_start))
+        return o
+
+
+@dataclass
+class SolveInfo:
+    status: int
+    cycles: int
+    inner_its: int
+    matvecs: int
+    relres_fp64: float
+
+    @property
+    def status_name(self):
+        return L.STATUS_NAMES.get(self.status, str(self.status))
+
+
+_ctx = {}
+
+
+def _context(device: int) -> C.c_void_p:
+    lib = L.load()
+    if device not in _ctx:
+        h = C.c_void_p()
+        st = lib.helm_create(C.byref(h), int(device))
+        if st != L.HELM_OK:
+            raise HelmError(st, lib.helm_last_error(None).decode())
+        _ctx[device] = h
+    return _ctx[device]
+
+
+def _check(ctx, st, allow=(L.HELM_OK,)):
+    if st not in allow:
+        raise HelmError(st, L.load().helm_last_error(ctx).decode())
+    return st
+
+
+def _dev_tensor(t: torch.Tensor, dtype, numel, name):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError(f"{name} must be a torch tensor on a GPU")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _nrhs(x: torch.Tensor, N: int) -> int:
+    if x.numel() % N != 0 or x.numel() == 0:
+        raise ValueError(f"array of {x.numel()} elements is not a whole number of grids of {N}")
+    return x.numel() // N
+
+
+def helm_apply(grid: Grid, m: torch.Tensor, omega: float, x: torch.Tensor,
+               adjoint: bool = False, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """y = H(m) x or H(m)^H x for x of shape (..., nx, ny, nz)."""
+    dev = x.device.index or 0
+    nrhs = _nrhs(x, grid.N)
+    if out is None:
+        out = torch.empty_like(x)
+    ctx = _context(dev)
+    g = grid.c_struct()
+    st = L.load().helm_apply(
+        ctx, C.byref(g), _dev_tensor(m, grid.real_dtype, grid.N, "m"), float(omega),
+        int(bool(adjoint)), nrhs, _dev_tensor(x, grid.complex_dtype, nrhs * grid.N, "x"),
+        _dev_tensor(out, grid.complex_dtype, nrhs * grid.N, "out"), _stream(dev))
+    _check(ctx, st)
+    return out
+
+
+def helm_solve(grid: Grid, m: torch.Tensor, omega: float, q: torch.Tensor,
+               adjoint: bool = False, opts: Optional[SolverOpts] = None,
+               u: Optional[torch.Tensor] = None, raise_on_failure: bool = True):
+    """Solve H u = q (or H^H u = q) for q of shape (..., nx, ny, nz).
+
+    Returns (u, [SolveInfo per right-hand side])."""
+    dev = q.device.index or 0
+    nrhs = _nrhs(q, grid.N)
+    opts = opts or SolverOpts()
+    if u is None:
+        if opts.warm_start:
+            raise ValueError("warm_start needs u")
+        u = torch.empty_like(q)
+    infos = (L.helm_solve_info * nrhs)()
+    ctx = _context(dev)
+    g, o = grid.c_struct(), opts.c_struct()
+    st = L.load().helm_solve(
+        ctx, C.byref(g), _dev_tensor(m, grid.real_dtype, grid.N, "m"), float(omega),
+        int(bool(adjoint)), nrhs, _dev_tensor(q, grid.complex_dtype, nrhs * grid.N, "q"),
+        _dev_tensor(u, grid.complex_dtype, nrhs * grid.N, "u"), C.byref(o), infos, _stream(dev))
+    allow = (L.HELM_OK,) if raise_on_failure else (L.HELM_OK, L.HELM_NOT_CONVERGED, L.HELM_BREAKDOWN)
+    _check(ctx, st, allow)
+    return u, [SolveInfo(i.status, i.cycles, i.inner_its, i.matvecs, i.relres_fp64) for i in infos]
+
+
+def _idx_array(pos, name, grid):
+    a = np.ascontiguousarray(np.asarray(pos, dtype=np.int32).reshape(-1, 3))
+    return a
+
+
+def misfit_gradient(grid: Grid, m: torch.Tensor, omega: float, src, rec, d: torch.Tensor,
+                    src_amp=None, grad: Optional[torch.Tensor] = None,
+                    u_store: Optional[torch.Tensor] = None, forward_only: bool = False,
+                    reuse_u: bool = False, accumulate: bool = False,
+                    opts: Optional[SolverOpts] = None, raise_on_failure: bool = True):
+    """Misfit f = 1/2 sum_s ||P_r u_s - d_s||^2 and its gradient w.r.t. m.
+
+    src, rec: (nsrc, 3) / (nrec, 3) integer node indices (host);
+    d: (nsrc, nrec) complex device tensor.  Returns (f, grad, infos)."""
+    dev = m.device.index or 0
+    src_a = _idx_array(src, "src", grid)
+    rec_a = _idx_array(rec, "rec", grid)
+    nsrc, nrec = len(src_a), len(rec_a)
+    amp_p = None
+    if src_amp is not None:
+        amp = np.ascontiguousarray(np.asarray(src_amp, np.complex128).reshape(nsrc))
+        amp_d = np.ascontiguousarray(np.stack([amp.real, amp.imag], axis=1).ravel())
+        amp_p = amp_d.ctypes.data_as(C.POINTER(C.c_double))
+    flags = (L.HELM_MG_FORWARD_ONLY if forward_only else 0) | \
+        (L.HELM_MG_REUSE_U if reuse_u else 0) | (L.HELM_MG_ACCUMULATE if accumulate else 0)
+    if grad is None and not forward_only:
+        grad = torch.empty(tuple(grid.n), dtype=grid.real_dtype, device=m.device)
+    opts = opts or SolverOpts()
+    infos = (L.helm_solve_info * (2 * nsrc))()
+    f = C.c_double(0.0)
+    ctx = _context(dev)
+    g, o = grid.c_struct(), opts.c_struct()
+    st = L.load().misfit_gradient(
+        ctx, C.byref(g), _dev_tensor(m, grid.real_dtype, grid.N, "m"), float(omega), nsrc,
+        src_a.ctypes.data_as(C.POINTER(C.c_int32)), amp_p, nrec,
+        rec_a.ctypes.data_as(C.POINTER(C.c_int32)),
+        _dev_tensor(d, grid.complex_dtype, nsrc * nrec, "d"), C.byref(f),
+        None if grad is None else _dev_tensor(grad, grid.real_dtype, grid.N, "grad"),
+        None if u_store is None else _dev_tensor(u_store, grid.complex_dtype, nsrc * grid.N, "u_store"),
+        flags, C.byref(o), infos, _stream(dev))
+    allow = (L.HELM_OK,) if raise_on_failure else (L.HELM_OK, L.HELM_NOT_CONVERGED, L.HELM_BREAKDOWN)
+    _check(ctx, st, allow)
+    nsolve = nsrc if (forward_only or reuse_u) else 2 * nsrc
+    first = nsrc if reuse_u else 0
+    inf = [SolveInfo(i.status, i.cycles, i.inner_its, i.matvecs, i.relres_fp64)
+           for i in list(infos)[first:first + nsolve]]
+    return f.value, grad, inf
+
+
+def version() -> str:
+    return L.load().helm_version().decode()
+
+
+def workspace_bytes(grid: Grid, opts: Optional[SolverOpts] = None, nrhs: int = 1) -> int:
+    g, o = grid.c_struct(), (opts or SolverOpts()).c_struct()
+    return int(L.load().helm_workspace_bytes(C.byref(g), C.byref(o), int(nrhs)))

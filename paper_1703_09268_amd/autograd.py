@@ -1,0 +1,47 @@
+"""Differentiable least-squares misfit f(m) behind ``torch.autograd.Function``.
+
+Forward: one multi-source forward solve (``misfit_gradient`` with
+HELM_MG_FORWARD_ONLY), keeping the fields u_s.  Backward: the adjoint solves
+and the hand-written gradient kernel (``misfit_gradient`` with
+HELM_MG_REUSE_U), g = sum_s Re(omega^2 conj(u_s) * A^H v_s) with
+v_s = -H^{-H} P_r^T (P_r u_s - d_s) (paper: Table derivstuff, rows V and
+grad f; Appendix A, eq. dHadj).  The map is real m -> real f, so there is no
+complex (Wirtinger) convention to choose.
+"""
+from __future__ import annotations
+
+import torch
+
+from .api import Grid, SolverOpts, misfit_gradient
+
+
+class HelmholtzMisfit(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, m: torch.Tensor, grid: Grid, omega: float, src, rec, d: torch.Tensor,
+                opts: SolverOpts = None):
+        m_c = m.detach().contiguous()
+        nsrc = len(src)
+        u_store = torch.empty((nsrc,) + tuple(int(a) for a in grid.n),
+                              dtype=grid.complex_dtype, device=m.device)
+        f, _, infos = misfit_gradient(grid, m_c, omega, src, rec, d, u_store=u_store,
+                                      forward_only=True, opts=opts)
+        ctx.save_for_backward(m_c)
+        ctx.u_store = u_store
+        ctx.args = (grid, omega, src, rec, d, opts)
+        ctx.forward_infos = infos
+        return torch.tensor(f, dtype=torch.float64, device=m.device)
+
+    @staticmethod
+    def backward(ctx, grad_f: torch.Tensor):
+        (m_c,) = ctx.saved_tensors
+        grid, omega, src, rec, d, opts = ctx.args
+        _, g, _ = misfit_gradient(grid, m_c, omega, src, rec, d, u_store=ctx.u_store,
+                                  reuse_u=True, opts=opts)
+        if not (grad_f.numel() == 1 and float(grad_f) == 1.0):
+            g = g * grad_f.to(g.dtype)
+        return g, None, None, None, None, None, None
+
+
+def helmholtz_misfit(m, grid, omega, src, rec, d, opts=None):
+    """f(m) = 1/2 sum_s ||P_r H(m)^{-1} q_s - d_s||^2, differentiable in m."""
+    return HelmholtzMisfit.apply(m, grid, omega, src, rec, d, opts)

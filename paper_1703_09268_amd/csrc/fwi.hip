@@ -1,0 +1,116 @@
+// Adjoint-state misfit / gradient kernels (arXiv:1703.09268, Listing of
+// PDEfunc case OBJ; Table derivstuff rows u, V, grad f; Appendix A eq.
+// dHadj):
+//   q_s = amp_s e_{src_s} / h^3                   (on-node point source)
+//   r_s = P_r u_s - d_s,  f = 1/2 sum_s ||r_s||^2  (FP64 accumulation)
+//   b_s = -P_r^T r_s                               (adjoint source)
+//   g   = sum_s Re(omega^2 conj(u_s) (A^H v_s))    (gradient w.r.t. real m)
+// Receivers that share a node are summed in a fixed order (node-sorted
+// receiver lists), so the adjoint source is deterministic.
+#pragma once
+
+#include "common.h"
+
+namespace helm {
+
+// q[s][p] = 0 except q[s][src_s] = amp_s / h^3
+template <typename T>
+__global__ __launch_bounds__(256) void k_point_sources(cx<T>* __restrict__ q, int64_t N,
+                                                       const int64_t* __restrict__ src_lin,
+                                                       const double2* __restrict__ amp, double inv_h3) {
+  const int s = blockIdx.y;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  const int64_t ps = src_lin[s];
+  const double2 a = amp[s];
+  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < N; p += stride) {
+    q[s * N + p] = (p == ps) ? mk<T>((T)(a.x * inv_h3), (T)(a.y * inv_h3)) : czero<T>();
+  }
+}
+
+// r[s][k] = u[s][rec_k] - d[s][k]; per-workgroup partial sum of |r|^2 in
+// part[s * gridDim.x + blk] (FP64).
+template <typename T>
+__global__ __launch_bounds__(256) void k_sample_residual(const cx<T>* __restrict__ u, int64_t N,
+                                                         const int64_t* __restrict__ rec_lin, int nrec,
+                                                         const cx<T>* __restrict__ d, cx<T>* __restrict__ res,
+                                                         double* __restrict__ part) {
+  __shared__ double red[16];
+  const int s = blockIdx.y;
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  double acc = 0.0;
+  if (k < nrec) {
+    const cx<T> uv = u[s * N + rec_lin[k]];
+    const cx<T> dv = d[(int64_t)s * nrec + k];
+    const cx<double> rr = mk<double>((double)uv.re - (double)dv.re, (double)uv.im - (double)dv.im);
+    res[(int64_t)s * nrec + k] = cast<T>(rr);
+    acc = rr.re * rr.re + rr.im * rr.im;
+  }
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) part[(int64_t)s * gridDim.x + blockIdx.x] = t;
+}
+
+// b[s] = -P_r^T r[s]: one lane per distinct receiver node, summing that node's
+// receivers (node_ptr/node_rec: CSR over distinct nodes, ascending).  b must
+// be zero beforehand.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adjoint_source(cx<T>* __restrict__ b, int64_t N,
+                                                        const int64_t* __restrict__ node_lin,
+                                                        const int* __restrict__ node_ptr,
+                                                        const int* __restrict__ node_rec, int nnode,
+                                                        const cx<T>* __restrict__ res, int nrec) {
+  const int s = blockIdx.y;
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= nnode) return;
+  cx<double> acc = czero<double>();
+  for (int e = node_ptr[q]; e < node_ptr[q + 1]; ++e)
+    acc = acc + cast<double>(res[(int64_t)s * nrec + node_rec[e]]);
+  b[s * N + node_lin[q]] = cast<T>(mk<double>(-acc.re, -acc.im));
+}
+
+// g[p] (+)= sum_s Re(omega^2 conj(u_s[p]) (A v_s)[p]) with A = I (7-point)
+// or the 27-point mass distribution (real symmetric, A^H = A).
+template <typename T, typename TG, bool MASS27>
+__global__ __launch_bounds__(256) void k_gradient(const cx<T>* __restrict__ u, const cx<T>* __restrict__ v,
+                                                  int nsrc, int nx, int ny, int nz, double w2,
+                                                  double mw0, double mw1, double mw2, double mw3,
+                                                  TG* __restrict__ g, bool accumulate) {
+  const int64_t N = (int64_t)nx * ny * nz;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < N; p += stride) {
+    double acc = 0.0;
+    int i = 0, j = 0, k = 0;
+    if (MASS27) {
+      k = (int)(p % nz);
+      j = (int)((p / nz) % ny);
+      i = (int)(p / ((int64_t)ny * nz));
+    }
+    for (int s = 0; s < nsrc; ++s) {
+      const cx<T> us = u[s * N + p];
+      cx<double> av;
+      if (!MASS27) {
+        av = cast<double>(v[s * N + p]);
+      } else {
+        const double mw[4] = {mw0, mw1, mw2, mw3};
+        av = czero<double>();
+        for (int di = -1; di <= 1; ++di) {
+          if (i + di < 0 || i + di >= nx) continue;
+          for (int dj = -1; dj <= 1; ++dj) {
+            if (j + dj < 0 || j + dj >= ny) continue;
+            for (int dk = -1; dk <= 1; ++dk) {
+              if (k + dk < 0 || k + dk >= nz) continue;
+              const int cls = (di != 0) + (dj != 0) + (dk != 0);
+              const cx<double> vq = cast<double>(v[s * N + p + (int64_t)di * ny * nz + (int64_t)dj * nz + dk]);
+              av = av + mw[cls] * vq;
+            }
+          }
+        }
+      }
+      // Re(conj(u) * av)
+      acc += (double)us.re * av.re + (double)us.im * av.im;
+    }
+    const double val = w2 * acc;
+    g[p] = accumulate ? (TG)((double)g[p] + val) : (TG)val;
+  }
+}
+
+}  // namespace helm

@@ -1,0 +1,396 @@
+// C ABI of the Helmholtz library (declared in include/helm.h).  Everything
+// below the ABI is C++/HIP; no exception crosses it.  This translation unit
+// includes the kernel and runtime sources so the library builds as one
+// gfx950 code object.
+#include "../../include/helm.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "fwi.hip"
+#include "solver.hip"
+
+struct helm_ctx {
+  int device = 0;
+  std::string err;
+  helm::DevBuf fwi_buf;  // sources / fields scratch of misfit_gradient
+  helm::DevBuf fwi_small;
+  // layer tables of the last operator applied by helm_apply, reused while the
+  // grid and omega are unchanged (then an apply is one asynchronous launch)
+  std::unique_ptr<helm::Level> apply_level;
+  helm_grid apply_grid;
+  double apply_omega = 0.0;
+};
+
+namespace {
+
+std::string g_global_err;
+
+helm_status fail(helm_ctx* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  else g_global_err = msg;
+  return (helm_status)code;
+}
+
+template <typename F>
+helm_status guarded(helm_ctx* ctx, F&& f) {
+  if (!ctx) return fail(nullptr, HELM_E_INVAL, "null context");
+  try {
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return fail(ctx, HELM_E_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    ctx->err.clear();
+    return f();
+  } catch (const helm::Error& e) {
+    (void)hipGetLastError();  // do not leave a sticky error for the caller's next HIP call
+    return fail(ctx, e.code, e.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(ctx, HELM_E_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(ctx, HELM_E_HIP, "unexpected C++ exception");
+  }
+}
+
+void check_grid(const helm_grid* g) {
+  HELM_REQUIRE(g != nullptr, "null grid");
+  for (int a = 0; a < 3; ++a) HELM_REQUIRE(g->n[a] >= 3, "grid sizes must be >= 3");
+  HELM_REQUIRE((int64_t)g->n[0] * g->n[1] * g->n[2] < ((int64_t)1 << 40), "grid too large");
+  HELM_REQUIRE(g->h > 0.0 && std::isfinite(g->h), "grid spacing must be positive");
+  HELM_REQUIRE(g->npml >= 0, "npml must be >= 0");
+  for (int a = 0; a < 3; ++a) HELM_REQUIRE(2 * g->npml < g->n[a], "npml must be < n/2 on every axis");
+  if (g->npml > 0) {
+    HELM_REQUIRE(g->pml_R > 0.0 && g->pml_R < 1.0, "pml_R must be in (0, 1)");
+    HELM_REQUIRE(g->v_ref > 0.0 && std::isfinite(g->v_ref), "v_ref must be positive");
+  }
+  HELM_REQUIRE(g->stencil == HELM_7PT || g->stencil == HELM_27PT, "unknown stencil");
+  HELM_REQUIRE(g->dtype == HELM_C64 || g->dtype == HELM_C128, "unknown dtype");
+  if (g->stencil == HELM_27PT)
+    for (int c = 0; c < 7; ++c) HELM_REQUIRE(std::isfinite(g->w27[c]), "27-point weights must be finite");
+}
+
+helm::GridSpec spec_of(const helm_grid* g) {
+  helm::GridSpec s;
+  for (int a = 0; a < 3; ++a) s.n[a] = g->n[a];
+  s.h = g->h;
+  s.npml = g->npml;
+  s.R = g->npml > 0 ? g->pml_R : 0.5;
+  s.vref = g->npml > 0 ? g->v_ref : 1.0;
+  s.stencil = g->stencil;
+  for (int c = 0; c < 7; ++c) s.w27[c] = g->w27[c];
+  return s;
+}
+
+helm::SolveOpts opts_of(const helm_solver_opts* o) {
+  helm_solver_opts d;
+  helm_default_opts(&d);
+  if (!o) o = &d;
+  helm::SolveOpts s;
+  HELM_REQUIRE(o->method == HELM_GMRES || o->method == HELM_FGMRES_ML, "unknown solver method");
+  HELM_REQUIRE(o->restart >= 1 && o->restart <= helm::KMAX, "restart must be in 1..32");
+  HELM_REQUIRE(o->max_cycles >= 0, "max_cycles must be >= 0");
+  HELM_REQUIRE(o->tol > 0.0, "tol must be > 0");
+  if (o->method == HELM_FGMRES_ML) {
+    HELM_REQUIRE(o->levels >= 2 && o->levels <= 4, "levels must be in 2..4");
+    HELM_REQUIRE(o->ks_o >= 1 && o->kc_o >= 1, "smoother / coarse cycles must be >= 1");
+    HELM_REQUIRE(o->ks_i >= 1 && o->ks_i <= helm::KMAX && o->kc_i >= 1 && o->kc_i <= helm::KMAX,
+                 "smoother / coarse Krylov dimensions must be in 1..32");
+  }
+  s.method = o->method;
+  s.restart = o->restart;
+  s.max_cycles = o->max_cycles;
+  s.tol = o->tol;
+  s.ks_o = o->ks_o;
+  s.ks_i = o->ks_i;
+  s.kc_o = o->kc_o;
+  s.kc_i = o->kc_i;
+  s.levels = o->levels;
+  s.warm_start = o->warm_start;
+  return s;
+}
+
+void check_coarse_sizes(const helm_grid* g, const helm::SolveOpts& o) {
+  if (o.method != HELM_FGMRES_ML) return;
+  int n[3] = {g->n[0], g->n[1], g->n[2]};
+  for (int l = 1; l < o.levels; ++l)
+    for (int a = 0; a < 3; ++a) {
+      n[a] = n[a] / 2 + 1;
+      HELM_REQUIRE(n[a] >= 3, "grid too small for the requested number of levels");
+    }
+}
+
+void to_info(const helm::SolveInfo& s, helm_solve_info* o) {
+  o->status = s.status;
+  o->cycles = s.cycles;
+  o->inner_its = s.inner_its;
+  o->pad_ = 0;
+  o->matvecs = s.matvecs;
+  o->relres_fp64 = s.relres;
+}
+
+template <typename T>
+helm_status solve_t(const helm_grid* g, const void* m, double omega, int adjoint, int nrhs, const void* q,
+                    void* u, const helm::SolveOpts& o, helm_solve_info* info, hipStream_t st) {
+  helm::Solver<T> S(spec_of(g), (const T*)m, omega, nrhs, o, st);
+  std::vector<helm::SolveInfo> inf(nrhs);
+  const int worst = S.solve(adjoint, (const helm::cx<T>*)q, (helm::cx<T>*)u, inf.data());
+  if (info)
+    for (int r = 0; r < nrhs; ++r) to_info(inf[r], info + r);
+  return (helm_status)worst;
+}
+
+// misfit + gradient for one frequency, element type T
+template <typename T>
+helm_status misfit_gradient_t(helm_ctx* ctx, const helm_grid* g, const void* m, double omega, int nsrc,
+                              const int32_t* src_idx, const double* src_amp, int nrec, const int32_t* rec_idx,
+                              const void* d, double* f, void* grad, void* u_store, int flags,
+                              const helm::SolveOpts& o, helm_solve_info* info, hipStream_t st) {
+  using namespace helm;
+  const int64_t N = (int64_t)g->n[0] * g->n[1] * g->n[2];
+  const int64_t plane = (int64_t)g->n[1] * g->n[2];
+  auto lin = [&](const int32_t* p) { return (int64_t)p[0] * plane + (int64_t)p[1] * g->n[2] + p[2]; };
+  // host index tables
+  std::vector<int64_t> src_lin(nsrc), rec_lin(nrec);
+  std::vector<double2> amp(nsrc);
+  for (int s = 0; s < nsrc; ++s) {
+    src_lin[s] = lin(src_idx + 3 * s);
+    amp[s] = src_amp ? make_double2(src_amp[2 * s], src_amp[2 * s + 1]) : make_double2(1.0, 0.0);
+  }
+  for (int k = 0; k < nrec; ++k) rec_lin[k] = lin(rec_idx + 3 * k);
+  // distinct receiver nodes, ascending, each with its receivers in order
+  std::vector<int> order(nrec);
+  for (int k = 0; k < nrec; ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return rec_lin[a] < rec_lin[b]; });
+  std::vector<int64_t> node_lin;
+  std::vector<int> node_ptr, node_rec(nrec);
+  for (int e = 0; e < nrec; ++e) {
+    const int k = order[e];
+    if (node_lin.empty() || node_lin.back() != rec_lin[k]) {
+      node_lin.push_back(rec_lin[k]);
+      node_ptr.push_back(e);
+    }
+    node_rec[e] = k;
+  }
+  node_ptr.push_back(nrec);
+  const int nnode = (int)node_lin.size();
+  // device scratch: U (if no u_store), B/Q, V, residuals, tables
+  const size_t fbytes = (size_t)nsrc * N * sizeof(cx<T>);
+  const bool own_u = (u_store == nullptr);
+  ctx->fwi_buf.ensure(fbytes * (own_u ? 3 : 2));
+  char* base = (char*)ctx->fwi_buf.p;
+  cx<T>* U = own_u ? (cx<T>*)(base + 2 * fbytes) : (cx<T>*)u_store;
+  cx<T>* Q = (cx<T>*)base;
+  cx<T>* V = (cx<T>*)(base + fbytes);
+  const int rblk = (int)ceil_div(nrec, 256);
+  auto r256 = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t small = r256(nsrc * sizeof(int64_t)) + r256(nrec * sizeof(int64_t)) +
+                       r256(nsrc * sizeof(double2)) + r256((size_t)nsrc * nrec * sizeof(cx<T>)) +
+                       r256((size_t)nsrc * rblk * sizeof(double)) + r256(nnode * sizeof(int64_t)) +
+                       r256((nnode + 1) * sizeof(int)) + r256(nrec * sizeof(int));
+  ctx->fwi_small.ensure(small);
+  char* sp = (char*)ctx->fwi_small.p;
+  char* const sp_end = sp + small;
+  auto carve = [&](size_t b) {
+    char* p = sp;
+    sp += r256(b);
+    if (sp > sp_end) throw Error{-3, "internal: misfit scratch layout overflow"};
+    return (void*)p;
+  };
+  int64_t* d_src = (int64_t*)carve(nsrc * sizeof(int64_t));
+  int64_t* d_rec = (int64_t*)carve(nrec * sizeof(int64_t));
+  double2* d_amp = (double2*)carve(nsrc * sizeof(double2));
+  cx<T>* d_res = (cx<T>*)carve((size_t)nsrc * nrec * sizeof(cx<T>));
+  double* d_part = (double*)carve((size_t)nsrc * rblk * sizeof(double));
+  int64_t* d_node = (int64_t*)carve(nnode * sizeof(int64_t));
+  int* d_nptr = (int*)carve((nnode + 1) * sizeof(int));
+  int* d_nrec = (int*)carve(nrec * sizeof(int));
+  HELM_HIP_CHECK(hipMemcpyAsync(d_src, src_lin.data(), nsrc * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  HELM_HIP_CHECK(hipMemcpyAsync(d_rec, rec_lin.data(), nrec * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  HELM_HIP_CHECK(hipMemcpyAsync(d_amp, amp.data(), nsrc * sizeof(double2), hipMemcpyHostToDevice, st));
+  HELM_HIP_CHECK(hipMemcpyAsync(d_node, node_lin.data(), nnode * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  HELM_HIP_CHECK(hipMemcpyAsync(d_nptr, node_ptr.data(), (nnode + 1) * sizeof(int), hipMemcpyHostToDevice, st));
+  HELM_HIP_CHECK(hipMemcpyAsync(d_nrec, node_rec.data(), nrec * sizeof(int), hipMemcpyHostToDevice, st));
+
+  helm::Solver<T> S(spec_of(g), (const T*)m, omega, nsrc, o, st);
+  std::vector<helm::SolveInfo> inf(nsrc);
+  int worst = 0;
+  if (!(flags & HELM_MG_REUSE_U)) {
+    const double inv_h3 = 1.0 / (g->h * g->h * g->h);
+    hipLaunchKernelGGL((k_point_sources<T>), dim3(vec_blocks(N), nsrc), dim3(256), 0, st, Q, N,
+                       (const int64_t*)d_src, (const double2*)d_amp, inv_h3);
+    worst = std::max(worst, S.solve(0, Q, U, inf.data()));
+    if (info)
+      for (int s = 0; s < nsrc; ++s) to_info(inf[s], info + s);
+  }
+  hipLaunchKernelGGL((k_sample_residual<T>), dim3(rblk, nsrc), dim3(256), 0, st, (const cx<T>*)U, N,
+                     (const int64_t*)d_rec, nrec, (const cx<T>*)d, d_res, d_part);
+  std::vector<double> hpart((size_t)nsrc * rblk);
+  HELM_HIP_CHECK(hipMemcpyAsync(hpart.data(), d_part, hpart.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HELM_HIP_CHECK(hipStreamSynchronize(st));
+  double fsum = 0.0;
+  for (size_t i = 0; i < hpart.size(); ++i) fsum += hpart[i];
+  *f = 0.5 * fsum;
+  if (flags & HELM_MG_FORWARD_ONLY) return (helm_status)worst;
+  // adjoint sources b_s = -P_r^T r_s, then H^H v_s = b_s
+  hipLaunchKernelGGL((k_zero<T>), dim3(vec_blocks(N), nsrc), dim3(256), 0, st, Q, N, (const int*)nullptr);
+  hipLaunchKernelGGL((k_adjoint_source<T>), dim3(ceil_div(nnode, 256), nsrc), dim3(256), 0, st, Q, N,
+                     (const int64_t*)d_node, (const int*)d_nptr, (const int*)d_nrec, nnode,
+                     (const cx<T>*)d_res, nrec);
+  worst = std::max(worst, S.solve(1, Q, V, inf.data()));
+  if (info)
+    for (int s = 0; s < nsrc; ++s) to_info(inf[s], info + nsrc + s);
+  // gradient
+  const bool acc = (flags & HELM_MG_ACCUMULATE) != 0;
+  const double w2 = omega * omega;
+  const unsigned gb = std::min<unsigned>(4096, ceil_div(N, 256));
+  if (g->stencil == HELM_27PT)
+    hipLaunchKernelGGL((k_gradient<T, T, true>), dim3(gb), dim3(256), 0, st, (const cx<T>*)U, (const cx<T>*)V,
+                       nsrc, g->n[0], g->n[1], g->n[2], w2, g->w27[3], g->w27[4], g->w27[5], g->w27[6],
+                       (T*)grad, acc);
+  else
+    hipLaunchKernelGGL((k_gradient<T, T, false>), dim3(gb), dim3(256), 0, st, (const cx<T>*)U,
+                       (const cx<T>*)V, nsrc, g->n[0], g->n[1], g->n[2], w2, 1.0, 0.0, 0.0, 0.0, (T*)grad, acc);
+  HELM_HIP_CHECK(hipGetLastError());
+  HELM_HIP_CHECK(hipStreamSynchronize(st));
+  return (helm_status)worst;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* helm_version(void) { return "helm-gfx950 0.1"; }
+
+helm_status helm_create(helm_ctx** ctx, int device) {
+  if (!ctx) return fail(nullptr, HELM_E_INVAL, "null output pointer");
+  *ctx = nullptr;
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || device < 0 || device >= count)
+    return fail(nullptr, HELM_E_HIP, "no such HIP device");
+  helm_ctx* c = new (std::nothrow) helm_ctx();
+  if (!c) return fail(nullptr, HELM_E_NOMEM, "out of host memory");
+  c->device = device;
+  *ctx = c;
+  return HELM_OK;
+}
+
+helm_status helm_destroy(helm_ctx* ctx) {
+  if (!ctx) return HELM_OK;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  delete ctx;
+  return HELM_OK;
+}
+
+const char* helm_last_error(const helm_ctx* ctx) { return ctx ? ctx->err.c_str() : g_global_err.c_str(); }
+
+void helm_default_opts(helm_solver_opts* o) {
+  if (!o) return;
+  o->method = HELM_FGMRES_ML;
+  o->restart = 5;
+  o->max_cycles = 50;
+  o->tol = 1e-6;
+  o->ks_o = 3;
+  o->ks_i = 5;
+  o->kc_o = 3;
+  o->kc_i = 5;
+  o->levels = 3;
+  o->warm_start = 0;
+}
+
+size_t helm_workspace_bytes(const helm_grid* g, const helm_solver_opts* o, int nrhs) {
+  try {
+    check_grid(g);
+    if (nrhs < 1) return 0;
+    const helm::SolveOpts so = opts_of(o);
+    return g->dtype == HELM_C64 ? helm::Solver<float>::workspace_bytes(spec_of(g), so, nrhs)
+                                : helm::Solver<double>::workspace_bytes(spec_of(g), so, nrhs);
+  } catch (...) {
+    return 0;
+  }
+}
+
+helm_status helm_apply(helm_ctx* ctx, const helm_grid* g, const void* m, double omega, int adjoint, int nrhs,
+                       const void* x, void* y, void* stream) {
+  return guarded(ctx, [&]() -> helm_status {
+    check_grid(g);
+    HELM_REQUIRE(m && x && y, "null device pointer");
+    HELM_REQUIRE(omega > 0.0 && std::isfinite(omega), "omega must be positive");
+    HELM_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+    HELM_REQUIRE(x != y, "x and y must not overlap");
+    hipStream_t st = (hipStream_t)stream;
+    if (!ctx->apply_level || std::memcmp(&ctx->apply_grid, g, sizeof(helm_grid)) != 0 ||
+        ctx->apply_omega != omega) {
+      // rebuilding frees the previous tables: finish work that may use them
+      if (ctx->apply_level) HELM_HIP_CHECK(hipDeviceSynchronize());
+      ctx->apply_level.reset(new helm::Level());
+      helm::GridSpec s = spec_of(g);
+      init_level(s, *ctx->apply_level, s.n, s.h, 1, omega, st);
+      std::memcpy(&ctx->apply_grid, g, sizeof(helm_grid));
+      ctx->apply_omega = omega;
+    }
+    const helm::Level& L = *ctx->apply_level;
+    if (g->dtype == HELM_C64)
+      helm::launch_h<float, float, float, float, float, false, false>(
+          L, adjoint ? 1 : 0, nrhs, (const helm::cx<float>*)x, nullptr, (const float*)m,
+          (const helm::cx<float>*)nullptr, nullptr, (helm::cx<float>*)y, nullptr, nullptr, st);
+    else
+      helm::launch_h<double, double, double, double, double, false, false>(
+          L, adjoint ? 1 : 0, nrhs, (const helm::cx<double>*)x, nullptr, (const double*)m,
+          (const helm::cx<double>*)nullptr, nullptr, (helm::cx<double>*)y, nullptr, nullptr, st);
+    HELM_HIP_CHECK(hipGetLastError());
+    return HELM_OK;
+  });
+}
+
+helm_status helm_solve(helm_ctx* ctx, const helm_grid* g, const void* m, double omega, int adjoint, int nrhs,
+                       const void* q, void* u, const helm_solver_opts* o, helm_solve_info* info, void* stream) {
+  return guarded(ctx, [&]() -> helm_status {
+    check_grid(g);
+    HELM_REQUIRE(m && q && u, "null device pointer");
+    HELM_REQUIRE(omega > 0.0 && std::isfinite(omega), "omega must be positive");
+    HELM_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+    const helm::SolveOpts so = opts_of(o);
+    check_coarse_sizes(g, so);
+    hipStream_t st = (hipStream_t)stream;
+    if (g->dtype == HELM_C64) return solve_t<float>(g, m, omega, adjoint ? 1 : 0, nrhs, q, u, so, info, st);
+    return solve_t<double>(g, m, omega, adjoint ? 1 : 0, nrhs, q, u, so, info, st);
+  });
+}
+
+helm_status misfit_gradient(helm_ctx* ctx, const helm_grid* g, const void* m, double omega, int nsrc,
+                            const int32_t* src_idx, const double* src_amp, int nrec, const int32_t* rec_idx,
+                            const void* d, double* f, void* grad, void* u_store, int flags,
+                            const helm_solver_opts* o, helm_solve_info* info, void* stream) {
+  return guarded(ctx, [&]() -> helm_status {
+    check_grid(g);
+    HELM_REQUIRE(m && d && f, "null pointer argument");
+    HELM_REQUIRE(omega > 0.0 && std::isfinite(omega), "omega must be positive");
+    HELM_REQUIRE(nsrc >= 1 && nrec >= 1, "nsrc and nrec must be >= 1");
+    HELM_REQUIRE(src_idx && rec_idx, "null source / receiver index array");
+    HELM_REQUIRE((flags & HELM_MG_FORWARD_ONLY) || grad, "null gradient");
+    HELM_REQUIRE(!(flags & HELM_MG_REUSE_U) || u_store, "HELM_MG_REUSE_U needs u_store");
+    HELM_REQUIRE((flags & ~7) == 0, "unknown flag bits");
+    for (int s = 0; s < nsrc; ++s)
+      for (int a = 0; a < 3; ++a)
+        HELM_REQUIRE(src_idx[3 * s + a] >= 0 && src_idx[3 * s + a] < g->n[a], "source outside the grid");
+    for (int k = 0; k < nrec; ++k)
+      for (int a = 0; a < 3; ++a)
+        HELM_REQUIRE(rec_idx[3 * k + a] >= 0 && rec_idx[3 * k + a] < g->n[a], "receiver outside the grid");
+    const helm::SolveOpts so = opts_of(o);
+    check_coarse_sizes(g, so);
+    hipStream_t st = (hipStream_t)stream;
+    if (g->dtype == HELM_C64)
+      return misfit_gradient_t<float>(ctx, g, m, omega, nsrc, src_idx, src_amp, nrec, rec_idx, d, f, grad,
+                                      u_store, flags, so, info, st);
+    return misfit_gradient_t<double>(ctx, g, m, omega, nsrc, src_idx, src_amp, nrec, rec_idx, d, f, grad,
+                                     u_store, flags, so, info, st);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,152 @@
+"""GPU parity of helm_solve against the FP64 oracle: exact discrete solutions
+(sparse LU / tight GMRES), FP64 residual certificates evaluated with the
+oracle's operator, adjoint solves, several right-hand sides, and the failure
+paths (not converged, non-finite input, zero right-hand side)."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1703_09268_amd as hx
+import workloads
+from oracle import operators as ops
+from oracle import fwi, krylov
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def _setup(w, dtype):
+    rdt = torch.float32 if dtype == "c64" else torch.float64
+    cdt = torch.complex64 if dtype == "c64" else torch.complex128
+    m_t = torch.tensor(w.m, dtype=rdt, device=DEV)
+    m_used = m_t.cpu().numpy().astype(np.float64)
+    g = ops.make_grid(w.n, w.h, w.npml, w.omega, w.v_ref)
+    grid = hx.Grid(n=w.n, h=w.h, npml=w.npml, v_ref=w.v_ref, dtype=dtype,
+                   stencil=w.stencil, w27=w.w27)
+    return grid, g, m_t, m_used, cdt
+
+
+def _sources(g, src, cdt):
+    q = np.stack([fwi.point_source(g, p) for p in src])
+    return q, torch.tensor(q, dtype=cdt, device=DEV)
+
+
+def _relres(g, m, u, q, adjoint=False, stencil="7pt", w27=None):
+    r = q - ops.apply(g, m, u, adjoint=adjoint, stencil=stencil, w27=w27)
+    return np.linalg.norm(r) / np.linalg.norm(q)
+
+
+def test_gmres20_c128_small_config():
+    """32^3, complex128, GMRES(20) to 1e-6 (the smallest configuration):
+    certificate by the oracle's operator and solution parity at a tightened
+    tolerance against SuperLU."""
+    print("case gmres20 c128 32^3", flush=True)
+    w = workloads.c1_small()
+    grid, g, m_t, m_used, cdt = _setup(w, "c128")
+    q, q_t = _sources(g, w.src, cdt)
+    opts = hx.SolverOpts(method="gmres", restart=20, max_cycles=400, tol=1e-6)
+    u_t, info = hx.helm_solve(grid, m_t, w.omega, q_t, opts=opts)
+    u = u_t.cpu().numpy()
+    assert info[0].status == 0 and info[0].relres_fp64 <= 1e-6
+    rr = _relres(g, m_used, u[0], q[0])
+    assert rr <= 1.01e-6
+    assert abs(rr - info[0].relres_fp64) <= 1e-3 * rr
+    # tightened tolerance vs the exact discrete solution
+    opts.tol = 1e-11
+    u_t, info = hx.helm_solve(grid, m_t, w.omega, q_t, opts=opts)
+    ue = fwi.LUSolver(g, m_used)(q[0])
+    u = u_t.cpu().numpy()[0]
+    assert np.linalg.norm(u - ue) <= 1e-8 * np.linalg.norm(ue)
+
+
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_mlgmres_c64_matches_exact_solution(adjoint):
+    """ML-GMRES (FGMRES(5), 3 grids, (3,5,3,5)) in complex64 with the FP64
+    outer iterate: 3 sources on a ragged layered grid; certificate <= tol
+    by the oracle's operator; at tol 1e-8 the solution matches SuperLU to 1e-5."""
+    print(f"case mlgmres c64 adj={adjoint}", flush=True)
+    w = workloads.layered_random_workload((36, 30, 41), 20.0, 6, 6.0, nsrc_xy=(3, 1),
+                                          seed=11)
+    grid, g, m_t, m_used, cdt = _setup(w, "c64")
+    q, q_t = _sources(g, w.src, cdt)
+    opts = hx.SolverOpts(tol=1e-6)
+    u_t, info = hx.helm_solve(grid, m_t, w.omega, q_t, adjoint=adjoint, opts=opts)
+    u = u_t.cpu().numpy().astype(np.complex128)
+    for s in range(len(w.src)):
+        assert info[s].status == 0, info[s]
+        assert info[s].cycles <= 6
+        # the returned complex64 field: certificate with slack for its rounding
+        assert _relres(g, m_used, u[s], q[s], adjoint) <= 2e-6
+    opts = hx.SolverOpts(tol=1e-8, max_cycles=60)
+    u_t, info = hx.helm_solve(grid, m_t, w.omega, q_t, adjoint=adjoint, opts=opts)
+    u = u_t.cpu().numpy().astype(np.complex128)
+    lu = fwi.LUSolver(g, m_used)
+    for s in range(len(w.src)):
+        ue = lu(q[s], adjoint)
+        assert np.linalg.norm(u[s] - ue) <= 1e-5 * np.linalg.norm(ue)
+
+
+def test_mlgmres_27pt_matches_exact_solution():
+    print("case mlgmres 27pt", flush=True)
+    w = workloads.layered_random_workload((30, 28, 33), 20.0, 5, 6.0, nsrc_xy=(2, 1),
+                                          seed=12)
+    w.stencil = "27pt"
+    w.w27 = workloads.W27_DEFAULT
+    grid, g, m_t, m_used, cdt = _setup(w, "c64")
+    q, q_t = _sources(g, w.src, cdt)
+    u_t, info = hx.helm_solve(grid, m_t, w.omega, q_t, opts=hx.SolverOpts(tol=1e-8, max_cycles=60))
+    u = u_t.cpu().numpy().astype(np.complex128)
+    lu = fwi.LUSolver(g, m_used, "27pt", w.w27)
+    for s in range(len(w.src)):
+        assert info[s].status == 0
+        ue = lu(q[s])
+        assert np.linalg.norm(u[s] - ue) <= 1e-5 * np.linalg.norm(ue)
+
+
+def test_mlgmres_outer_cycles_constant_model():
+    """Behaviour of the paper's preconditioner table (constant velocity, layer
+    of one wavelength, 8 ppw): 2-3 outer cycles at n_lambda = 5 (57^3)."""
+    ppw, nl, v0, f = 8, 5, 2000.0, 5.0
+    n = nl * ppw + 1 + 2 * ppw
+    w = workloads.constant_workload((n, n, n), v0 / (f * ppw), ppw, f, v0=v0, dtype="c64")
+    grid, g, m_t, m_used, cdt = _setup(w, "c64")
+    q, q_t = _sources(g, w.src, cdt)
+    u_t, info = hx.helm_solve(grid, m_t, w.omega, q_t)
+    assert info[0].status == 0 and 1 <= info[0].cycles <= 4
+    u = u_t.cpu().numpy().astype(np.complex128)[0]
+    assert _relres(g, m_used, u, q[0]) <= 2e-6
+
+
+def test_failure_paths_not_converged_nan_zero():
+    """max_cycles = 1 -> HELM_NOT_CONVERGED with the best iterate; a NaN in
+    one right-hand side flags only that one; a zero right-hand side gives
+    u = 0 and status OK."""
+    w = workloads.layered_random_workload((24, 24, 24), 20.0, 4, 6.0, nsrc_xy=(2, 2),
+                                          seed=13)
+    grid, g, m_t, m_used, cdt = _setup(w, "c64")
+    q, q_t = _sources(g, w.src, cdt)
+    u_t, info = hx.helm_solve(grid, m_t, w.omega, q_t, opts=hx.SolverOpts(max_cycles=1),
+                              raise_on_failure=False)
+    assert all(i.status == 1 for i in info)
+    assert all(np.isfinite(i.relres_fp64) and i.relres_fp64 < 1.0 for i in info)
+    q_t[1, 3, 3, 3] = float("nan")
+    q_t[2].zero_()
+    u_t, info = hx.helm_solve(grid, m_t, w.omega, q_t, raise_on_failure=False)
+    assert info[0].status == 0 and info[3].status == 0
+    assert info[1].status == 2
+    assert info[2].status == 0 and info[2].relres_fp64 == 0.0
+    assert torch.count_nonzero(u_t[2]).item() == 0
+    u = u_t.cpu().numpy().astype(np.complex128)
+    assert _relres(g, m_used, u[3], q[3]) <= 2e-6
+    with pytest.raises(hx.HelmError):
+        hx.helm_solve(grid, m_t, w.omega, q_t)
+
+
+def test_warm_start_from_solution_stops_immediately():
+    w = workloads.layered_random_workload((24, 26, 28), 20.0, 4, 6.0, nsrc_xy=(1, 1), seed=14)
+    grid, g, m_t, m_used, cdt = _setup(w, "c64")
+    q, q_t = _sources(g, w.src, cdt)
+    u_t, info = hx.helm_solve(grid, m_t, w.omega, q_t, opts=hx.SolverOpts(tol=1e-7))
+    u2, info2 = hx.helm_solve(grid, m_t, w.omega, q_t, u=u_t.clone(),
+                              opts=hx.SolverOpts(tol=1e-5, warm_start=True))
+    assert info2[0].cycles == 0 and info2[0].status == 0
