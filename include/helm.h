@@ -171,6 +171,8 @@ helm_status helm_solve(helm_ctx* ctx, const helm_grid* g, const void* m,
 #define HELM_MG_FORWARD_ONLY 1 /* solve forward, return f; no gradient     */
 #define HELM_MG_REUSE_U 2      /* u_store already holds H^{-1} q_s         */
 #define HELM_MG_ACCUMULATE 4   /* g += gradient instead of g = gradient    */
+#define HELM_MG_U_FP64 8       /* u_store holds complex128 fields (the FP64
+                                  outer iterates) even for HELM_C64 grids   */
 
 /* Least-squares misfit and its adjoint-state gradient for one frequency
  * (paper, Listing of PDEfunc, case OBJ; Table derivstuff rows u, V, grad f;
@@ -179,6 +181,10 @@ helm_status helm_solve(helm_ctx* ctx, const helm_grid* g, const void* m,
  *   u_s = H^{-1} q_s,   r_s = P_r u_s - d_s,   f = 1/2 sum_s ||r_s||^2
  *   v_s = -H^{-H} P_r^T r_s
  *   g   = sum_s Re(omega^2 conj(u_s) * (A^H v_s))   (real, N entries)
+ * The receiver residual is formed from the FP64 outer iterate of the
+ * forward solve (or from u_store with HELM_MG_REUSE_U; store the fields with
+ * HELM_MG_U_FP64 to keep that residual accurate when r is much smaller than
+ * u at the receivers).
  * Arguments:
  *   m        dev, N reals (float for C64, double for C128)
  *   nsrc     number of sources (>= 1), solved together as one block
@@ -190,8 +196,9 @@ helm_status helm_solve(helm_ctx* ctx, const helm_grid* g, const void* m,
  *   grad     dev, N reals (float for C64, double for C128); overwritten
  *            (or accumulated into with HELM_MG_ACCUMULATE); may be NULL
  *            with HELM_MG_FORWARD_ONLY
- *   u_store  dev, [nsrc][N] complex of g->dtype or NULL: receives the
- *            forward fields (or supplies them with HELM_MG_REUSE_U)
+ *   u_store  dev, [nsrc][N] complex of g->dtype (complex128 with
+ *            HELM_MG_U_FP64) or NULL: receives the forward fields (or
+ *            supplies them with HELM_MG_REUSE_U)
  *   flags    HELM_MG_* bits
  *   info     host, 2*nsrc entries (forward then adjoint solves) or NULL
  * Returns the worst status of the solves. */

@@ -26,6 +26,7 @@ HELM_GMRES, HELM_FGMRES_ML = 0, 1
 HELM_MG_FORWARD_ONLY = 1
 HELM_MG_REUSE_U = 2
 HELM_MG_ACCUMULATE = 4
+HELM_MG_U_FP64 = 8
 
 STATUS_NAMES = {
     HELM_OK: "HELM_OK",

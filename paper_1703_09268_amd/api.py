@@ -192,12 +192,14 @@ def _idx_array(pos, name, grid):
 def misfit_gradient(grid: Grid, m: torch.Tensor, omega: float, src, rec, d: torch.Tensor,
                     src_amp=None, grad: Optional[torch.Tensor] = None,
                     u_store: Optional[torch.Tensor] = None, forward_only: bool = False,
-                    reuse_u: bool = False, accumulate: bool = False,
+                    reuse_u: bool = False, accumulate: bool = False, u_fp64: bool = False,
                     opts: Optional[SolverOpts] = None, raise_on_failure: bool = True):
     """Misfit f = 1/2 sum_s ||P_r u_s - d_s||^2 and its gradient w.r.t. m.
 
     src, rec: (nsrc, 3) / (nrec, 3) integer node indices (host);
-    d: (nsrc, nrec) complex device tensor.  Returns (f, grad, infos)."""
+    d: (nsrc, nrec) complex device tensor.  u_store (optional) receives or,
+    with reuse_u, supplies the forward fields; with u_fp64 it is complex128
+    (the FP64 outer iterates).  Returns (f, grad, infos)."""
     dev = m.device.index or 0
     src_a = _idx_array(src, "src", grid)
     rec_a = _idx_array(rec, "rec", grid)
@@ -208,7 +210,9 @@ def misfit_gradient(grid: Grid, m: torch.Tensor, omega: float, src, rec, d: torc
         amp_d = np.ascontiguousarray(np.stack([amp.real, amp.imag], axis=1).ravel())
         amp_p = amp_d.ctypes.data_as(C.POINTER(C.c_double))
     flags = (L.HELM_MG_FORWARD_ONLY if forward_only else 0) | \
-        (L.HELM_MG_REUSE_U if reuse_u else 0) | (L.HELM_MG_ACCUMULATE if accumulate else 0)
+        (L.HELM_MG_REUSE_U if reuse_u else 0) | (L.HELM_MG_ACCUMULATE if accumulate else 0) | \
+        (L.HELM_MG_U_FP64 if u_fp64 else 0)
+    u_dtype = torch.complex128 if u_fp64 else grid.complex_dtype
     if grad is None and not forward_only:
         grad = torch.empty(tuple(grid.n), dtype=grid.real_dtype, device=m.device)
     opts = opts or SolverOpts()
@@ -222,7 +226,7 @@ def misfit_gradient(grid: Grid, m: torch.Tensor, omega: float, src, rec, d: torc
         rec_a.ctypes.data_as(C.POINTER(C.c_int32)),
         _dev_tensor(d, grid.complex_dtype, nsrc * nrec, "d"), C.byref(f),
         None if grad is None else _dev_tensor(grad, grid.real_dtype, grid.N, "grad"),
-        None if u_store is None else _dev_tensor(u_store, grid.complex_dtype, nsrc * grid.N, "u_store"),
+        None if u_store is None else _dev_tensor(u_store, u_dtype, nsrc * grid.N, "u_store"),
         flags, C.byref(o), infos, _stream(dev))
     allow = (L.HELM_OK,) if raise_on_failure else (L.HELM_OK, L.HELM_NOT_CONVERGED, L.HELM_BREAKDOWN)
     _check(ctx, st, allow)

@@ -1,7 +1,9 @@
 """Differentiable least-squares misfit f(m) behind ``torch.autograd.Function``.
 
 Forward: one multi-source forward solve (``misfit_gradient`` with
-HELM_MG_FORWARD_ONLY), keeping the fields u_s.  Backward: the adjoint solves
+HELM_MG_FORWARD_ONLY), keeping the fields u_s as their FP64 outer iterates
+(HELM_MG_U_FP64), so the receiver residual formed again in backward is as
+accurate as the one formed inside a single misfit_gradient call.  Backward: the adjoint solves
 and the hand-written gradient kernel (``misfit_gradient`` with
 HELM_MG_REUSE_U), g = sum_s Re(omega^2 conj(u_s) * A^H v_s) with
 v_s = -H^{-H} P_r^T (P_r u_s - d_s) (paper: Table derivstuff, rows V and
@@ -22,9 +24,9 @@ class HelmholtzMisfit(torch.autograd.Function):
         m_c = m.detach().contiguous()
         nsrc = len(src)
         u_store = torch.empty((nsrc,) + tuple(int(a) for a in grid.n),
-                              dtype=grid.complex_dtype, device=m.device)
+                              dtype=torch.complex128, device=m.device)
         f, _, infos = misfit_gradient(grid, m_c, omega, src, rec, d, u_store=u_store,
-                                      forward_only=True, opts=opts)
+                                      forward_only=True, u_fp64=True, opts=opts)
         ctx.save_for_backward(m_c)
         ctx.u_store = u_store
         ctx.args = (grid, omega, src, rec, d, opts)
@@ -36,7 +38,7 @@ class HelmholtzMisfit(torch.autograd.Function):
         (m_c,) = ctx.saved_tensors
         grid, omega, src, rec, d, opts = ctx.args
         _, g, _ = misfit_gradient(grid, m_c, omega, src, rec, d, u_store=ctx.u_store,
-                                  reuse_u=True, opts=opts)
+                                  reuse_u=True, u_fp64=True, opts=opts)
         if not (grad_f.numel() == 1 and float(grad_f) == 1.0):
             g = g * grad_f.to(g.dtype)
         return g, None, None, None, None, None, None

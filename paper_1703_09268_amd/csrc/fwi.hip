@@ -28,9 +28,11 @@ __global__ __launch_bounds__(256) void k_point_sources(cx<T>* __restrict__ q, in
 }
 
 // r[s][k] = u[s][rec_k] - d[s][k]; per-workgroup partial sum of |r|^2 in
-// part[s * gridDim.x + blk] (FP64).
-template <typename T>
-__global__ __launch_bounds__(256) void k_sample_residual(const cx<T>* __restrict__ u, int64_t N,
+// part[s * gridDim.x + blk] (FP64).  u may be the FP64 outer iterate of the
+// solve (TU = double): the residual is a small difference of two fields, so
+// it is formed before the fields are rounded to the storage precision.
+template <typename TU, typename T>
+__global__ __launch_bounds__(256) void k_sample_residual(const cx<TU>* __restrict__ u, int64_t N,
                                                          const int64_t* __restrict__ rec_lin, int nrec,
                                                          const cx<T>* __restrict__ d, cx<T>* __restrict__ res,
                                                          double* __restrict__ part) {
@@ -39,7 +41,7 @@ __global__ __launch_bounds__(256) void k_sample_residual(const cx<T>* __restrict
   const int k = blockIdx.x * 256 + threadIdx.x;
   double acc = 0.0;
   if (k < nrec) {
-    const cx<T> uv = u[s * N + rec_lin[k]];
+    const cx<TU> uv = u[s * N + rec_lin[k]];
     const cx<T> dv = d[(int64_t)s * nrec + k];
     const cx<double> rr = mk<double>((double)uv.re - (double)dv.re, (double)uv.im - (double)dv.im);
     res[(int64_t)s * nrec + k] = cast<T>(rr);
@@ -69,8 +71,8 @@ __global__ __launch_bounds__(256) void k_adjoint_source(cx<T>* __restrict__ b, i
 
 // g[p] (+)= sum_s Re(omega^2 conj(u_s[p]) (A v_s)[p]) with A = I (7-point)
 // or the 27-point mass distribution (real symmetric, A^H = A).
-template <typename T, typename TG, bool MASS27>
-__global__ __launch_bounds__(256) void k_gradient(const cx<T>* __restrict__ u, const cx<T>* __restrict__ v,
+template <typename TU, typename T, typename TG, bool MASS27>
+__global__ __launch_bounds__(256) void k_gradient(const cx<TU>* __restrict__ u, const cx<T>* __restrict__ v,
                                                   int nsrc, int nx, int ny, int nz, double w2,
                                                   double mw0, double mw1, double mw2, double mw3,
                                                   TG* __restrict__ g, bool accumulate) {
@@ -85,7 +87,7 @@ __global__ __launch_bounds__(256) void k_gradient(const cx<T>* __restrict__ u, c
       i = (int)(p / ((int64_t)ny * nz));
     }
     for (int s = 0; s < nsrc; ++s) {
-      const cx<T> us = u[s * N + p];
+      const cx<TU> us = u[s * N + p];
       cx<double> av;
       if (!MASS27) {
         av = cast<double>(v[s * N + p]);

@@ -177,9 +177,11 @@ helm_status misfit_gradient_t(helm_ctx* ctx, const helm_grid* g, const void* m, 
   }
   node_ptr.push_back(nrec);
   const int nnode = (int)node_lin.size();
-  // device scratch: U (if no u_store), B/Q, V, residuals, tables
+  // device scratch: Q (sources, then adjoint sources), V, and U when the
+  // forward fields are not written to the caller's u_store in the dtype
+  const bool u64 = (flags & HELM_MG_U_FP64) != 0 && sizeof(T) == 4;
   const size_t fbytes = (size_t)nsrc * N * sizeof(cx<T>);
-  const bool own_u = (u_store == nullptr);
+  const bool own_u = (u_store == nullptr) || u64;
   ctx->fwi_buf.ensure(fbytes * (own_u ? 3 : 2));
   char* base = (char*)ctx->fwi_buf.p;
   cx<T>* U = own_u ? (cx<T>*)(base + 2 * fbytes) : (cx<T>*)u_store;
@@ -218,16 +220,27 @@ helm_status misfit_gradient_t(helm_ctx* ctx, const helm_grid* g, const void* m, 
   helm::Solver<T> S(spec_of(g), (const T*)m, omega, nsrc, o, st);
   std::vector<helm::SolveInfo> inf(nsrc);
   int worst = 0;
-  if (!(flags & HELM_MG_REUSE_U)) {
+  const bool reuse = (flags & HELM_MG_REUSE_U) != 0;
+  if (!reuse) {
     const double inv_h3 = 1.0 / (g->h * g->h * g->h);
     hipLaunchKernelGGL((k_point_sources<T>), dim3(vec_blocks(N), nsrc), dim3(256), 0, st, Q, N,
                        (const int64_t*)d_src, (const double2*)d_amp, inv_h3);
     worst = std::max(worst, S.solve(0, Q, U, inf.data()));
     if (info)
       for (int s = 0; s < nsrc; ++s) to_info(inf[s], info + s);
+    if (u64)  // keep the FP64 iterates as the stored fields
+      hipLaunchKernelGGL((k_convert<double, double>), dim3(vec_blocks(N) * 4), dim3(256), 0, st,
+                         S.iterate(), (cx<double>*)u_store, N * nsrc);
+    hipLaunchKernelGGL((k_sample_residual<double, T>), dim3(rblk, nsrc), dim3(256), 0, st, S.iterate(), N,
+                       (const int64_t*)d_rec, nrec, (const cx<T>*)d, d_res, d_part);
+  } else if (u64) {
+    hipLaunchKernelGGL((k_sample_residual<double, T>), dim3(rblk, nsrc), dim3(256), 0, st,
+                       (const cx<double>*)u_store, N, (const int64_t*)d_rec, nrec, (const cx<T>*)d, d_res,
+                       d_part);
+  } else {
+    hipLaunchKernelGGL((k_sample_residual<T, T>), dim3(rblk, nsrc), dim3(256), 0, st, (const cx<T>*)U, N,
+                       (const int64_t*)d_rec, nrec, (const cx<T>*)d, d_res, d_part);
   }
-  hipLaunchKernelGGL((k_sample_residual<T>), dim3(rblk, nsrc), dim3(256), 0, st, (const cx<T>*)U, N,
-                     (const int64_t*)d_rec, nrec, (const cx<T>*)d, d_res, d_part);
   std::vector<double> hpart((size_t)nsrc * rblk);
   HELM_HIP_CHECK(hipMemcpyAsync(hpart.data(), d_part, hpart.size() * sizeof(double), hipMemcpyDeviceToHost, st));
   HELM_HIP_CHECK(hipStreamSynchronize(st));
@@ -247,13 +260,20 @@ helm_status misfit_gradient_t(helm_ctx* ctx, const helm_grid* g, const void* m, 
   const bool acc = (flags & HELM_MG_ACCUMULATE) != 0;
   const double w2 = omega * omega;
   const unsigned gb = std::min<unsigned>(4096, ceil_div(N, 256));
-  if (g->stencil == HELM_27PT)
-    hipLaunchKernelGGL((k_gradient<T, T, true>), dim3(gb), dim3(256), 0, st, (const cx<T>*)U, (const cx<T>*)V,
-                       nsrc, g->n[0], g->n[1], g->n[2], w2, g->w27[3], g->w27[4], g->w27[5], g->w27[6],
-                       (T*)grad, acc);
-  else
-    hipLaunchKernelGGL((k_gradient<T, T, false>), dim3(gb), dim3(256), 0, st, (const cx<T>*)U,
-                       (const cx<T>*)V, nsrc, g->n[0], g->n[1], g->n[2], w2, 1.0, 0.0, 0.0, 0.0, (T*)grad, acc);
+  const double mw[4] = {g->stencil == HELM_27PT ? g->w27[3] : 1.0, g->stencil == HELM_27PT ? g->w27[4] : 0.0,
+                        g->stencil == HELM_27PT ? g->w27[5] : 0.0, g->stencil == HELM_27PT ? g->w27[6] : 0.0};
+#define HELM_GRAD(TU, UPTR, M27)                                                                        \
+  hipLaunchKernelGGL((k_gradient<TU, T, T, M27>), dim3(gb), dim3(256), 0, st, (const cx<TU>*)(UPTR),     \
+                     (const cx<T>*)V, nsrc, g->n[0], g->n[1], g->n[2], w2, mw[0], mw[1], mw[2], mw[3],  \
+                     (T*)grad, acc)
+  if (u64) {
+    if (g->stencil == HELM_27PT) HELM_GRAD(double, u_store, true);
+    else HELM_GRAD(double, u_store, false);
+  } else {
+    if (g->stencil == HELM_27PT) HELM_GRAD(T, U, true);
+    else HELM_GRAD(T, U, false);
+  }
+#undef HELM_GRAD
   HELM_HIP_CHECK(hipGetLastError());
   HELM_HIP_CHECK(hipStreamSynchronize(st));
   return (helm_status)worst;
@@ -375,7 +395,7 @@ helm_status misfit_gradient(helm_ctx* ctx, const helm_grid* g, const void* m, do
     HELM_REQUIRE(src_idx && rec_idx, "null source / receiver index array");
     HELM_REQUIRE((flags & HELM_MG_FORWARD_ONLY) || grad, "null gradient");
     HELM_REQUIRE(!(flags & HELM_MG_REUSE_U) || u_store, "HELM_MG_REUSE_U needs u_store");
-    HELM_REQUIRE((flags & ~7) == 0, "unknown flag bits");
+    HELM_REQUIRE((flags & ~15) == 0, "unknown flag bits");
     for (int s = 0; s < nsrc; ++s)
       for (int a = 0; a < 3; ++a)
         HELM_REQUIRE(src_idx[3 * s + a] >= 0 && src_idx[3 * s + a] < g->n[a], "source outside the grid");

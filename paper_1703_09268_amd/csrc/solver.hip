@@ -102,6 +102,8 @@ class Solver {
   }
 
   const Level& level(int l) const { return *levels_[l]; }
+  // FP64 outer iterates of the last solve ([nrhs][N]); valid until the next solve
+  const cx<double>* iterate() const { return X_; }
   int64_t fine_matvecs() const { return fine_mv_; }
 
   // ---- plain operator application -------------------------------------
