@@ -43,7 +43,61 @@ def parse():
     p.add_argument("--stencil-reps", type=int, default=50)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--nrec", type=int, default=32, help="receivers per axis")
+    p.add_argument("--batch-count", type=int, default=64,
+                   help="problems of the uneven 256-problem draw used for batched vs plain")
+    p.add_argument("--no-batch", action="store_true")
+    p.add_argument("--stencil-only", action="store_true",
+                   help="only the stencil measurement (for hardware-counter runs)")
     return p.parse_args()
+
+
+def batched_vs_plain(hx, torch, workloads, count, dev):
+    """Solves/s of the uneven batch (first `count` problems of the seeded
+    256-problem draw: dims U{48..160} with aspect <= 2, 3-12 Hz at 8 points
+    per wavelength, smooth random 1500-4500 m/s, one source each) solved
+    together by helm_solve_batched, and the same problems one at a time by
+    helm_solve.  Both timed warm (second call, setup and graph capture
+    outside the timed region), same options and tolerance."""
+    params = workloads.c4_problem_params(count=256)[:count]
+    probs = []
+    for p in params:
+        w = workloads.c4_problem(p)
+        grid = hx.Grid(n=w.n, h=w.h, npml=w.npml, v_ref=w.v_ref, dtype="c64")
+        m_t = torch.tensor(w.m, dtype=torch.float32, device=dev)
+        q_t = torch.zeros(w.n, dtype=torch.complex64, device=dev)
+        i, j, k = (int(v) for v in w.src[0])
+        q_t[i, j, k] = 1.0 / w.h ** 3
+        probs.append((grid, m_t, w.omega, q_t))
+    opts = hx.SolverOpts(tol=1e-6, max_cycles=40)
+    npts = sum(pr[0].N for pr in probs)
+    hx.helm_solve_batched(probs, opts=opts)  # setup + capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, binfo = hx.helm_solve_batched(probs, opts=opts)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    tp = 0.0
+    pinfo = []
+    for pr in probs:
+        hx.helm_solve(pr[0], pr[1], pr[2], pr[3], opts=opts)  # setup + capture
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, inf = hx.helm_solve(pr[0], pr[1], pr[2], pr[3], opts=opts)
+        torch.cuda.synchronize()
+        tp += time.perf_counter() - t0
+        pinfo.extend(inf)
+    return {
+        "workload": f"first {count} of the 256-problem uneven draw (dims 48-160, aspect <= 2, "
+                    "3-12 Hz, 8 ppw at 1500 m/s, layer 8), one source each, ML-GMRES to 1e-6",
+        "problems": count, "points": int(npts),
+        "batched_solves_per_s": round(count / tb, 4), "plain_solves_per_s": round(count / tp, 4),
+        "batched_vs_plain": round(tp / tb, 3),
+        "batched_s": round(tb, 3), "plain_s": round(tp, 3),
+        "max_relres_batched": max(i.relres_fp64 for i in binfo),
+        "max_relres_plain": max(i.relres_fp64 for i in pinfo),
+        "all_converged": all(i.status == 0 for i in binfo + pinfo),
+        "mean_cycles_batched": float(np.mean([i.cycles for i in binfo])),
+    }
 
 
 def cpu_baseline(w, m32, src, rec, omega, target_s=0.0):
@@ -75,6 +129,27 @@ def cpu_baseline(w, m32, src, rec, omega, target_s=0.0):
     return dt, steps
 
 
+def stencil_timing(hx, torch, grid, m_t, w, S, reps, dev):
+    """Average duration of the stencil kernel (helm_apply with S right-hand
+    sides: one kernel launch each) from HIP events recorded on the launch
+    stream; two input/output pairs alternate."""
+    xs = [torch.randn((S,) + tuple(w.n), dtype=torch.complex64, device=dev) for _ in range(2)]
+    ys = [torch.empty_like(xs[0]) for _ in range(2)]
+    for i in range(3):
+        hx.helm_apply(grid, m_t, w.omega, xs[i % 2], out=ys[i % 2])
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for i in range(reps):
+        hx.helm_apply(grid, m_t, w.omega, xs[i % 2], out=ys[i % 2])
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    bytes_launch = (16 * S + 4) * w.N
+    return ms, bytes_launch / (ms * 1e-3) / 1e9
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -88,6 +163,12 @@ def main():
 
     dev = torch.device("cuda:0")
     w = workloads.c2_layered()
+    if args.stencil_only:
+        grid = hx.Grid(n=w.n, h=w.h, npml=w.npml, v_ref=w.v_ref, dtype="c64")
+        m_t = torch.tensor(w.m, dtype=torch.float32, device=dev)
+        ms, gbs = stencil_timing(hx, torch, grid, m_t, w, len(w.src), args.stencil_reps, dev)
+        print(json.dumps({"stencil_ms_per_launch": ms, "GB_s": gbs}), flush=True)
+        return
     nsrc = len(w.src)
     rec = workloads.surface_positions(w.n, w.npml, (args.nrec, args.nrec))
     grid = hx.Grid(n=w.n, h=w.h, npml=w.npml, v_ref=w.v_ref, dtype="c64")
@@ -127,23 +208,8 @@ def main():
 
     # ---- stencil kernel alone: 16 right-hand sides, HIP events on the stream
     S = nsrc
-    xs = [torch.randn((S,) + w.n, dtype=torch.complex64, device=dev) for _ in range(2)]
-    ys = [torch.empty_like(xs[0]) for _ in range(2)]
-    for i in range(3):
-        hx.helm_apply(grid, m_t, w.omega, xs[i % 2], out=ys[i % 2])
-    stream = torch.cuda.current_stream(dev)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for i in range(args.stencil_reps):
-        hx.helm_apply(grid, m_t, w.omega, xs[i % 2], out=ys[i % 2])
-    e1.record(stream)
-    e1.synchronize()
-    st_ms = e0.elapsed_time(e1) / args.stencil_reps
-    N = w.N
-    bytes_launch = (16 * S + 4) * N
-    gbs = bytes_launch / (st_ms * 1e-3) / 1e9
-    del xs, ys
+    st_ms, gbs = stencil_timing(hx, torch, grid, m_t, w, S, args.stencil_reps, dev)
+    batch = None if args.no_batch else batched_vs_plain(hx, torch, workloads, args.batch_count, dev)
 
     out = {
         "metric": METRIC,
@@ -170,8 +236,9 @@ def main():
             "max_relres_fp64": max(relres), "mean_outer_cycles": float(np.mean(cycles)),
             "max_outer_cycles": int(max(cycles)), "misfit": fval,
         },
+        "batched_vs_plain": batch,
         "stencil": {
-            "kernel": "k_h7<float,...,64,4> (helm_apply, 16 rhs)",
+            "kernel": "k_h7<float,...> (helm_apply, 16 rhs)",
             "ms_per_launch": round(st_ms, 5), "GB_s": round(gbs, 1),
             "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
             "bytes_per_point": f"16*{S}+4",

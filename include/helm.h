@@ -167,6 +167,28 @@ helm_status helm_solve(helm_ctx* ctx, const helm_grid* g, const void* m,
                        void* u, const helm_solver_opts* o,
                        helm_solve_info* info, void* stream);
 
+/* One problem of a batched solve. */
+typedef struct {
+  helm_grid grid;   /* every problem of a batch: same dtype and stencil      */
+  const void* m;    /* dev, N reals (float for C64, double for C128)          */
+  double omega;     /* angular frequency, > 0                                 */
+  const void* q;    /* dev, N complex right-hand side                         */
+  void* u;          /* dev, N complex solution (initial guess if warm_start)  */
+} helm_problem;
+
+/* Solve nprob independent problems of different sizes, frequencies and
+ * models together (not in the paper, whose parallelism is over workers:
+ * this is the same solver as helm_solve applied to all problems at once).
+ * Every kernel of the solve covers all problems in one launch; one outer
+ * FGMRES cycle (Arnoldi steps with their V-cycles) is captured once as a
+ * hipGraph and replayed; problems that converge are masked off while the
+ * others continue.  Same options, precision and status semantics as
+ * helm_solve; info (host, nprob entries, may be NULL).  All problems use
+ * H (adjoint = 0) or H^H (adjoint = 1). */
+helm_status helm_solve_batched(helm_ctx* ctx, int nprob, const helm_problem* probs,
+                               int adjoint, const helm_solver_opts* o,
+                               helm_solve_info* info, void* stream);
+
 /* misfit_gradient flags */
 #define HELM_MG_FORWARD_ONLY 1 /* solve forward, return f; no gradient     */
 #define HELM_MG_REUSE_U 2      /* u_store already holds H^{-1} q_s         */

@@ -41,7 +41,7 @@ STATUS_NAMES = {
 # every entry point declared in include/helm.h
 EXPORTS = ("helm_create", "helm_destroy", "helm_last_error", "helm_version",
            "helm_default_opts", "helm_workspace_bytes", "helm_apply",
-           "helm_solve", "misfit_gradient")
+           "helm_solve", "helm_solve_batched", "misfit_gradient")
 
 
 class helm_grid(C.Structure):
@@ -57,6 +57,11 @@ class helm_solver_opts(C.Structure):
                 ("ks_o", C.c_int32), ("ks_i", C.c_int32), ("kc_o", C.c_int32),
                 ("kc_i", C.c_int32), ("levels", C.c_int32),
                 ("warm_start", C.c_int32)]
+
+
+class helm_problem(C.Structure):
+    _fields_ = [("grid", helm_grid), ("m", C.c_void_p), ("omega", C.c_double),
+                ("q", C.c_void_p), ("u", C.c_void_p)]
 
 
 class helm_solve_info(C.Structure):
@@ -91,12 +96,13 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.helm_workspace_bytes.restype = C.c_size_t
     lib.helm_apply.argtypes = [vp, G, vp, dbl, i32, i32, vp, vp, vp]
     lib.helm_solve.argtypes = [vp, G, vp, dbl, i32, i32, vp, vp, O, I, vp]
+    lib.helm_solve_batched.argtypes = [vp, i32, C.POINTER(helm_problem), i32, O, I, vp]
     lib.misfit_gradient.argtypes = [vp, G, vp, dbl, i32, C.POINTER(C.c_int32),
                                     C.POINTER(C.c_double), i32,
                                     C.POINTER(C.c_int32), vp,
                                     C.POINTER(C.c_double), vp, vp, i32, O, I, vp]
     for name in ("helm_create", "helm_destroy", "helm_apply", "helm_solve",
-                 "misfit_gradient"):
+                 "helm_solve_batched", "misfit_gradient"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib

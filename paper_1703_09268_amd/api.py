@@ -184,6 +184,41 @@ def helm_solve(grid: Grid, m: torch.Tensor, omega: float, q: torch.Tensor,
     return u, [SolveInfo(i.status, i.cycles, i.inner_its, i.matvecs, i.relres_fp64) for i in infos]
 
 
+def helm_solve_batched(problems, adjoint: bool = False, opts: Optional[SolverOpts] = None,
+                       raise_on_failure: bool = True):
+    """Solve a batch of independent problems of different sizes together.
+
+    problems: sequence of (grid, m, omega, q[, u]) with torch device tensors
+    (all grids of one dtype and stencil).  Returns ([u], [SolveInfo])."""
+    if not problems:
+        raise ValueError("empty batch")
+    opts = opts or SolverOpts()
+    arr = (L.helm_problem * len(problems))()
+    outs = []
+    dev = problems[0][1].device.index or 0
+    for i, pr in enumerate(problems):
+        grid, m, omega, q = pr[0], pr[1], pr[2], pr[3]
+        u = pr[4] if len(pr) > 4 and pr[4] is not None else None
+        if u is None:
+            if opts.warm_start:
+                raise ValueError("warm_start needs u for every problem")
+            u = torch.empty_like(q)
+        arr[i].grid = grid.c_struct()
+        arr[i].m = _dev_tensor(m, grid.real_dtype, grid.N, "m")
+        arr[i].omega = float(omega)
+        arr[i].q = _dev_tensor(q, grid.complex_dtype, grid.N, "q")
+        arr[i].u = _dev_tensor(u, grid.complex_dtype, grid.N, "u")
+        outs.append(u)
+    infos = (L.helm_solve_info * len(problems))()
+    ctx = _context(dev)
+    o = opts.c_struct()
+    st = L.load().helm_solve_batched(ctx, len(problems), arr, int(bool(adjoint)), C.byref(o), infos,
+                                     _stream(dev))
+    allow = (L.HELM_OK,) if raise_on_failure else (L.HELM_OK, L.HELM_NOT_CONVERGED, L.HELM_BREAKDOWN)
+    _check(ctx, st, allow)
+    return outs, [SolveInfo(i.status, i.cycles, i.inner_its, i.matvecs, i.relres_fp64) for i in infos]
+
+
 def _idx_array(pos, name, grid):
     a = np.ascontiguousarray(np.asarray(pos, dtype=np.int32).reshape(-1, 3))
     return a

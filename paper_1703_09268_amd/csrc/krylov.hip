@@ -1,72 +1,93 @@
-// Krylov building blocks for restarted (F)GMRES on many right-hand sides at
-// once (all sources of one frequency share the operator; each keeps its own
-// Krylov state).  Every scalar of the method (Hessenberg entries, Givens
-// rotations, residual estimates, basis scales) stays on the device; sums
-// are accumulated in FP64 with a fixed reduction order, so results are
-// bitwise reproducible run to run.
+// Krylov building blocks for restarted (F)GMRES on many segments at once
+// (all sources of a frequency, or a batch of uneven problems; each segment
+// keeps its own Krylov state).  Every scalar of the method (Hessenberg
+// entries, Givens rotations, residual estimates, basis scales) stays on the
+// device; sums are accumulated in FP64 with a fixed reduction order, so
+// results are bitwise reproducible run to run.
 //
 // Orthogonalisation is classical Gram-Schmidt in two kernels (all inner
 // products of a column in one pass over the basis, then one fused
 // "w -= sum c_i V_i; ||w||^2" pass), with lazy normalisation: basis vector
-// V_i is stored unnormalised together with scale_i = 1/||V_i|| per
-// right-hand side, and consumers fold the scale into their first use.
+// V_i is stored unnormalised together with scale_i = 1/||V_i|| per segment,
+// and consumers fold the scale into their first use.
+//
+// Vector kernels run vnblk workgroups per segment (grid-stride over the
+// segment's N); partial sums of workgroup wg go to part[wg * PSTRIDE + ...];
+// the per-segment reducers (one 64-lane workgroup per segment) read the
+// segment's range of workgroups in a fixed order.
 #pragma once
 
 #include "common.h"
+#include "segment.h"
 
 namespace helm {
 
-constexpr int DOT_BLOCKS = 240;  // workgroups per right-hand side for the dot pass
+constexpr int DOT_BLOCKS = 240;  // largest number of vector workgroups per segment
 
-// Up to KMAX+1 vector pointers of one right-hand-side block (element r*N+p).
+// Up to KMAX+1 vector pointers (element Seg::off + p of each).
 template <typename T>
 struct VecList {
   const cx<T>* v[KMAX + 1];
 };
 
 // Device-resident state of one (F)GMRES instance, structure of arrays over
-// right-hand sides: entry [idx][r] is at idx*nrhs + r.
+// segments: entry [idx][s] is at idx*nseg + s.
 struct KState {
-  double2* H;      // (KMAX+1) x KMAX Hessenberg / R factor, [(i*KMAX+j)][r]
-  double* cs;      // Givens cosines [j][r]
-  double2* sn;     // Givens sines   [j][r]
-  double2* g;      // rotated right-hand side [i][r]
-  double* scale;   // 1/||V_i|| [i][r]
-  double2* coef;   // CGS coefficients of the current column, scale folded in
-  double* part;    // partial sums scratch [r][blk][2*(KMAX+1)]
-  int nrhs;
+  double2* H;     // (KMAX+1) x KMAX Hessenberg / R factor, [(i*KMAX+j)][s]
+  double* cs;     // Givens cosines [j][s]
+  double2* sn;    // Givens sines   [j][s]
+  double2* g;     // rotated right-hand side [i][s]
+  double* scale;  // 1/||V_i|| [i][s]
+  double2* coef;  // CGS coefficients of the current column, scale folded in
+  double* part;   // partial sums scratch [wg][PSTRIDE]
+  int nseg;
 };
+
+// which workgroup range of a segment holds the partial sums being reduced
+enum PartRange { PR_STENCIL = 0, PR_VECTOR = 1, PR_POINT = 2 };
+
+__device__ __forceinline__ void seg_range(const Seg& S, int which, int& b0, int& nb) {
+  if (which == PR_STENCIL) { b0 = S.sblk0; nb = S.snblk; }
+  else if (which == PR_VECTOR) { b0 = S.vblk0; nb = S.vnblk; }
+  else { b0 = S.tblk0; nb = S.tnblk; }
+}
 
 __device__ __forceinline__ double2 d2(double a, double b) { return make_double2(a, b); }
 
+// sum of part[(b0+b)*PSTRIDE + c] over the segment's workgroups (64 lanes)
+__device__ __forceinline__ double seg_sum(const double* part, int b0, int nb, int c) {
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 64) s += part[(int64_t)(b0 + b) * PSTRIDE + c];
+  return wave_sum(s);
+}
+
 // ---------------------------------------------------------------------------
 // partial inner products  s_i = sum_p conj(V_i[p]) w[p],  i < nv
-// part[(r*nblk + blk)*2*(KMAX+1) + 2i + {0,1}]
 // ---------------------------------------------------------------------------
 template <typename T, int NVMAX>
-__global__ __launch_bounds__(256) void k_dots(VecList<T> V, int nv, const cx<T>* __restrict__ w,
-                                             int64_t N, double* __restrict__ part,
-                                             const int* __restrict__ active) {
+__global__ __launch_bounds__(256) void k_dots(const Seg* __restrict__ segs, const int* __restrict__ vmap,
+                                             VecList<T> V, int nv, const cx<T>* __restrict__ w,
+                                             double* __restrict__ part, const int* __restrict__ active) {
   __shared__ double red[4][2 * NVMAX];
-  const int r = blockIdx.y;
-  const int nblk = gridDim.x;
-  double* out = part + ((int64_t)r * nblk + blockIdx.x) * PSTRIDE;
-  if (active && !active[r]) {
+  const int wg = blockIdx.x;
+  const int sid = vmap[wg];
+  const Seg& S = segs[sid];
+  double* out = part + (int64_t)wg * PSTRIDE;
+  if (active && !active[sid]) {
     if (threadIdx.x < 2 * NVMAX) out[threadIdx.x] = 0.0;
     return;
   }
   double ar[NVMAX], ai[NVMAX];
 #pragma unroll
   for (int i = 0; i < NVMAX; ++i) ar[i] = ai[i] = 0.0;
-  const cx<T>* wr = w + r * N;
-  const int64_t stride = (int64_t)nblk * 256;
-  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < N; p += stride) {
-    const cx<T> wv = wr[p];
+  const int64_t N = S.N, off = S.off;
+  const int64_t stride = (int64_t)S.vnblk * 256;
+  for (int64_t p = (int64_t)(wg - S.vblk0) * 256 + threadIdx.x; p < N; p += stride) {
+    const cx<T> wv = w[off + p];
 #pragma unroll
     for (int i = 0; i < NVMAX; ++i) {
       if (i < nv) {
-        const cx<T> a = V.v[i][r * N + p];
-        // conj(a) * w
+        const cx<T> a = V.v[i][off + p];
         ar[i] += (double)a.re * (double)wv.re + (double)a.im * (double)wv.im;
         ai[i] += (double)a.re * (double)wv.im - (double)a.im * (double)wv.re;
       }
@@ -85,48 +106,41 @@ __global__ __launch_bounds__(256) void k_dots(VecList<T> V, int nv, const cx<T>*
     }
   }
   __syncthreads();
-  if (threadIdx.x < 2 * nv) {
-    out[threadIdx.x] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
-                       red[3][threadIdx.x];
-  }
+  if (threadIdx.x < 2 * nv)
+    out[threadIdx.x] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
 }
 
-// One workgroup of 64 lanes per right-hand side: H[i][j] = scale_i * sum of
-// partials, coef_i = H[i][j] * scale_i.
-__global__ __launch_bounds__(64) void k_reduce_dots(KState st, int nv, int j, int nblk,
+// One 64-lane workgroup per segment: H[i][j] = scale_i * sum of partials,
+// coef_i = H[i][j] * scale_i.
+__global__ __launch_bounds__(64) void k_reduce_dots(const Seg* __restrict__ segs, KState st, int nv, int j,
                                                     const int* __restrict__ active) {
-  const int r = blockIdx.x;
-  if (active && !active[r]) return;
-  const int nrhs = st.nrhs;
-  const double* base = st.part + (int64_t)r * nblk * PSTRIDE;
+  const int sid = blockIdx.x;
+  if (active && !active[sid]) return;
+  const Seg& S = segs[sid];
+  const int ns = st.nseg;
   for (int i = 0; i < nv; ++i) {
-    double sr = 0.0, si = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += 64) {
-      sr += base[(int64_t)b * PSTRIDE + 2 * i];
-      si += base[(int64_t)b * PSTRIDE + 2 * i + 1];
-    }
-    sr = wave_sum(sr);
-    si = wave_sum(si);
+    const double sr = seg_sum(st.part, S.vblk0, S.vnblk, 2 * i);
+    const double si = seg_sum(st.part, S.vblk0, S.vnblk, 2 * i + 1);
     if (threadIdx.x == 0) {
-      const double s = st.scale[i * nrhs + r];
+      const double s = st.scale[i * ns + sid];
       const double2 h = d2(s * sr, s * si);
-      st.H[(i * KMAX + j) * nrhs + r] = h;
-      st.coef[i * nrhs + r] = d2(h.x * s, h.y * s);
+      st.H[(i * KMAX + j) * ns + sid] = h;
+      st.coef[i * ns + sid] = d2(h.x * s, h.y * s);
     }
   }
 }
 
-// w <- w - sum_i coef_i V_i  (in place), partial ||w||^2 per workgroup
-// into part[(r*nblk + blk)*2*(KMAX+1)].
+// w <- w - sum_i coef_i V_i  (in place), partial ||w||^2 per workgroup.
 template <typename T, int NVMAX>
-__global__ __launch_bounds__(256) void k_axpy_norm(VecList<T> V, int nv, cx<T>* __restrict__ w,
-                                                  int64_t N, KState st,
+__global__ __launch_bounds__(256) void k_axpy_norm(const Seg* __restrict__ segs, const int* __restrict__ vmap,
+                                                  VecList<T> V, int nv, cx<T>* __restrict__ w, KState st,
                                                   const int* __restrict__ active) {
   __shared__ double red[16];
-  const int r = blockIdx.y;
-  const int nblk = gridDim.x;
-  double* out = st.part + ((int64_t)r * nblk + blockIdx.x) * PSTRIDE;
-  if (active && !active[r]) {
+  const int wg = blockIdx.x;
+  const int sid = vmap[wg];
+  const Seg& S = segs[sid];
+  double* out = st.part + (int64_t)wg * PSTRIDE;
+  if (active && !active[sid]) {
     if (threadIdx.x == 0) out[0] = 0.0;
     return;
   }
@@ -134,104 +148,108 @@ __global__ __launch_bounds__(256) void k_axpy_norm(VecList<T> V, int nv, cx<T>* 
 #pragma unroll
   for (int i = 0; i < NVMAX; ++i) {
     if (i < nv) {
-      const double2 q = st.coef[i * st.nrhs + r];
+      const double2 q = st.coef[i * st.nseg + sid];
       c[i] = mk<T>((T)q.x, (T)q.y);
     }
   }
-  cx<T>* wr = w + r * N;
+  const int64_t N = S.N, off = S.off;
+  const int64_t stride = (int64_t)S.vnblk * 256;
   double nrm = 0.0;
-  const int64_t stride = (int64_t)nblk * 256;
-  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < N; p += stride) {
-    cx<T> acc = wr[p];
+  for (int64_t p = (int64_t)(wg - S.vblk0) * 256 + threadIdx.x; p < N; p += stride) {
+    cx<T> acc = w[off + p];
 #pragma unroll
     for (int i = 0; i < NVMAX; ++i) {
-      if (i < nv) {
-        const cx<T> a = V.v[i][r * N + p];
-        acc = acc - c[i] * a;
-      }
+      if (i < nv) acc = acc - c[i] * V.v[i][off + p];
     }
-    wr[p] = acc;
+    w[off + p] = acc;
     nrm += (double)acc.re * (double)acc.re + (double)acc.im * (double)acc.im;
   }
   const double s = block_sum(nrm, red);
   if (threadIdx.x == 0) out[0] = s;
 }
 
-// plain partial ||x||^2 (x with optional per-rhs scale applied afterwards)
+// partial ||x||^2 per workgroup
 template <typename T>
-__global__ __launch_bounds__(256) void k_norm2(const cx<T>* __restrict__ x, int64_t N,
-                                              double* __restrict__ part,
+__global__ __launch_bounds__(256) void k_norm2(const Seg* __restrict__ segs, const int* __restrict__ vmap,
+                                              const cx<T>* __restrict__ x, double* __restrict__ part,
                                               const int* __restrict__ active) {
   __shared__ double red[16];
-  const int r = blockIdx.y;
-  const int nblk = gridDim.x;
-  double* out = part + ((int64_t)r * nblk + blockIdx.x) * PSTRIDE;
-  if (active && !active[r]) {
+  const int wg = blockIdx.x;
+  const int sid = vmap[wg];
+  const Seg& S = segs[sid];
+  double* out = part + (int64_t)wg * PSTRIDE;
+  if (active && !active[sid]) {
     if (threadIdx.x == 0) out[0] = 0.0;
     return;
   }
-  const cx<T>* xr = x + r * N;
+  const int64_t N = S.N, off = S.off;
+  const int64_t stride = (int64_t)S.vnblk * 256;
   double nrm = 0.0;
-  const int64_t stride = (int64_t)nblk * 256;
-  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < N; p += stride) {
-    const cx<T> a = xr[p];
+  for (int64_t p = (int64_t)(wg - S.vblk0) * 256 + threadIdx.x; p < N; p += stride) {
+    const cx<T> a = x[off + p];
     nrm += (double)a.re * (double)a.re + (double)a.im * (double)a.im;
   }
   const double s = block_sum(nrm, red);
   if (threadIdx.x == 0) out[0] = s;
 }
 
-// Start of a cycle: beta = vscale_in[r] * sqrt(sum partials) (the partials
-// are of the unscaled residual vector), g = (beta, 0, ...), scale_0 =
-// vscale_in/beta (or 0 when beta == 0), beta_out[r] = beta.
-__global__ __launch_bounds__(64) void k_start_cycle(KState st, int nblk,
+// out[sid] = sqrt(sum of the segment's partial norms) (range `which`)
+__global__ __launch_bounds__(64) void k_seg_norm(const Seg* __restrict__ segs, const double* __restrict__ part,
+                                                 int which, double* __restrict__ out) {
+  const int sid = blockIdx.x;
+  int b0, nb;
+  seg_range(segs[sid], which, b0, nb);
+  const double s = seg_sum(part, b0, nb, 0);
+  if (threadIdx.x == 0) out[sid] = sqrt(s);
+}
+
+// Start of a cycle: beta = vscale_in * sqrt(sum of partials of range
+// `which`) (the partials are of the unscaled residual vector), g = (beta, 0,
+// ...), scale_0 = vscale_in / beta (0 when beta == 0), beta_out = beta.
+__global__ __launch_bounds__(64) void k_start_cycle(const Seg* __restrict__ segs, KState st, int which,
                                                     const double* __restrict__ vscale_in,
                                                     double* __restrict__ beta_out,
                                                     const int* __restrict__ active) {
-  const int r = blockIdx.x;
-  if (active && !active[r]) return;
-  const int nrhs = st.nrhs;
-  const double* base = st.part + (int64_t)r * nblk * PSTRIDE;
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += 64) s += base[(int64_t)b * PSTRIDE];
-  s = wave_sum(s);
+  const int sid = blockIdx.x;
+  if (active && !active[sid]) return;
+  int b0, nb;
+  seg_range(segs[sid], which, b0, nb);
+  const double s = seg_sum(st.part, b0, nb, 0);
   if (threadIdx.x == 0) {
-    const double vin = vscale_in ? vscale_in[r] : 1.0;
+    const int ns = st.nseg;
+    const double vin = vscale_in ? vscale_in[sid] : 1.0;
     const double beta = fabs(vin) * sqrt(s);
-    st.g[r] = d2(beta, 0.0);
-    for (int i = 1; i <= KMAX; ++i) st.g[i * nrhs + r] = d2(0.0, 0.0);
-    st.scale[r] = beta > 0.0 ? vin / beta : 0.0;
-    if (beta_out) beta_out[r] = beta;
+    st.g[sid] = d2(beta, 0.0);
+    for (int i = 1; i <= KMAX; ++i) st.g[i * ns + sid] = d2(0.0, 0.0);
+    st.scale[sid] = beta > 0.0 ? vin / beta : 0.0;
+    if (beta_out) beta_out[sid] = beta;
   }
 }
 
 // Finish Arnoldi column j: h_{j+1,j} = sqrt(sum partials); apply the
 // previous rotations to column j, build rotation j, update g, set
 // scale_{j+1} = 1/h_{j+1,j} (0 on breakdown).
-__global__ __launch_bounds__(64) void k_givens(KState st, int j, int nblk,
+__global__ __launch_bounds__(64) void k_givens(const Seg* __restrict__ segs, KState st, int j,
                                                const int* __restrict__ active) {
-  const int r = blockIdx.x;
-  if (active && !active[r]) return;
-  const int nrhs = st.nrhs;
-  const double* base = st.part + (int64_t)r * nblk * PSTRIDE;
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += 64) s += base[(int64_t)b * PSTRIDE];
-  s = wave_sum(s);
+  const int sid = blockIdx.x;
+  if (active && !active[sid]) return;
+  const Seg& S = segs[sid];
+  const double s = seg_sum(st.part, S.vblk0, S.vnblk, 0);
   if (threadIdx.x != 0) return;
+  const int ns = st.nseg;
   const double hn = sqrt(s);
-  // rotate column j by the previous rotations
   for (int i = 0; i < j; ++i) {
-    const double2 a = st.H[(i * KMAX + j) * nrhs + r];
-    const double2 b = st.H[((i + 1) * KMAX + j) * nrhs + r];
-    const double c = st.cs[i * nrhs + r];
-    const double2 sn = st.sn[i * nrhs + r];
+    const double2 a = st.H[(i * KMAX + j) * ns + sid];
+    const double2 b = st.H[((i + 1) * KMAX + j) * ns + sid];
+    const double c = st.cs[i * ns + sid];
+    const double2 sn = st.sn[i * ns + sid];
     // [c, s; -conj(s), c] [a; b]
     const double2 na = d2(c * a.x + (sn.x * b.x - sn.y * b.y), c * a.y + (sn.x * b.y + sn.y * b.x));
     const double2 nb = d2(-(sn.x * a.x + sn.y * a.y) + c * b.x, -(sn.x * a.y - sn.y * a.x) + c * b.y);
-    st.H[(i * KMAX + j) * nrhs + r] = na;
-    st.H[((i + 1) * KMAX + j) * nrhs + r] = nb;
+    st.H[(i * KMAX + j) * ns + sid] = na;
+    st.H[((i + 1) * KMAX + j) * ns + sid] = nb;
   }
-  const double2 a = st.H[(j * KMAX + j) * nrhs + r];
+  const double2 a = st.H[(j * KMAX + j) * ns + sid];
   const double absa = hypot(a.x, a.y);
   double c;
   double2 sn, rr;
@@ -250,35 +268,31 @@ __global__ __launch_bounds__(64) void k_givens(KState st, int j, int nblk,
     sn = d2(ph.x * hn / nrm, ph.y * hn / nrm);  // (a/|a|) conj(b)/nrm, b real
     rr = d2(ph.x * nrm, ph.y * nrm);
   }
-  st.cs[j * nrhs + r] = c;
-  st.sn[j * nrhs + r] = sn;
-  st.H[(j * KMAX + j) * nrhs + r] = rr;
-  st.H[((j + 1) * KMAX + j) * nrhs + r] = d2(0.0, 0.0);
-  const double2 gj = st.g[j * nrhs + r];
+  st.cs[j * ns + sid] = c;
+  st.sn[j * ns + sid] = sn;
+  st.H[(j * KMAX + j) * ns + sid] = rr;
+  st.H[((j + 1) * KMAX + j) * ns + sid] = d2(0.0, 0.0);
+  const double2 gj = st.g[j * ns + sid];
   // g_{j+1} = -conj(s) g_j ; g_j = c g_j
-  st.g[(j + 1) * nrhs + r] = d2(-(sn.x * gj.x + sn.y * gj.y), -(sn.x * gj.y - sn.y * gj.x));
-  st.g[j * nrhs + r] = d2(c * gj.x, c * gj.y);
-  st.scale[(j + 1) * nrhs + r] = hn > 0.0 ? 1.0 / hn : 0.0;
+  st.g[(j + 1) * ns + sid] = d2(-(sn.x * gj.x + sn.y * gj.y), -(sn.x * gj.y - sn.y * gj.x));
+  st.g[j * ns + sid] = d2(c * gj.x, c * gj.y);
+  st.scale[(j + 1) * ns + sid] = hn > 0.0 ? 1.0 / hn : 0.0;
 }
 
-// Back substitution R y = g (k x k upper triangular, zero pivots -> y_i = 0)
-// done by lane 0 of the workgroup into shared memory.
-__device__ __forceinline__ void solve_upper(const KState& st, int r, int k, double2* y) {
-  const int nrhs = st.nrhs;
+// Back substitution R y = g (k x k upper triangular, zero pivots -> y_i = 0).
+__device__ __forceinline__ void solve_upper(const KState& st, int sid, int k, double2* y) {
+  const int ns = st.nseg;
   for (int i = k - 1; i >= 0; --i) {
-    double2 acc = st.g[i * nrhs + r];
+    double2 acc = st.g[i * ns + sid];
     for (int l = i + 1; l < k; ++l) {
-      const double2 h = st.H[(i * KMAX + l) * nrhs + r];
+      const double2 h = st.H[(i * KMAX + l) * ns + sid];
       acc.x -= h.x * y[l].x - h.y * y[l].y;
       acc.y -= h.x * y[l].y + h.y * y[l].x;
     }
-    const double2 d = st.H[(i * KMAX + i) * nrhs + r];
+    const double2 d = st.H[(i * KMAX + i) * ns + sid];
     const double den = d.x * d.x + d.y * d.y;
-    if (den == 0.0) {
-      y[i] = d2(0.0, 0.0);
-    } else {
-      y[i] = d2((acc.x * d.x + acc.y * d.y) / den, (acc.y * d.x - acc.x * d.y) / den);
-    }
+    y[i] = den == 0.0 ? d2(0.0, 0.0)
+                      : d2((acc.x * d.x + acc.y * d.y) / den, (acc.y * d.x - acc.x * d.y) / den);
   }
 }
 
@@ -286,17 +300,19 @@ __device__ __forceinline__ void solve_upper(const KState& st, int r, int k, doub
 // s = 1).  y from R y = g solved per workgroup.  x may be of higher
 // precision than D (mixed-precision outer iterate).
 template <typename TX, typename T, int KM>
-__global__ __launch_bounds__(256) void k_update_x(VecList<T> D, int k, bool use_scale, KState st,
-                                                 cx<TX>* __restrict__ x, int64_t N,
-                                                 const int* __restrict__ active) {
+__global__ __launch_bounds__(256) void k_update_x(const Seg* __restrict__ segs, const int* __restrict__ vmap,
+                                                 VecList<T> D, int k, bool use_scale, KState st,
+                                                 cx<TX>* __restrict__ x, const int* __restrict__ active) {
   __shared__ double2 ys[KMAX];
-  const int r = blockIdx.y;
-  if (active && !active[r]) return;
+  const int wg = blockIdx.x;
+  const int sid = vmap[wg];
+  if (active && !active[sid]) return;
+  const Seg& S = segs[sid];
   if (threadIdx.x == 0) {
     double2 y[KMAX];
-    solve_upper(st, r, k, y);
+    solve_upper(st, sid, k, y);
     for (int j = 0; j < k; ++j) {
-      const double s = use_scale ? st.scale[j * st.nrhs + r] : 1.0;
+      const double s = use_scale ? st.scale[j * st.nseg + sid] : 1.0;
       ys[j] = d2(y[j].x * s, y[j].y * s);
     }
   }
@@ -305,38 +321,43 @@ __global__ __launch_bounds__(256) void k_update_x(VecList<T> D, int k, bool use_
 #pragma unroll
   for (int j = 0; j < KM; ++j)
     if (j < k) c[j] = mk<TX>((TX)ys[j].x, (TX)ys[j].y);
-  cx<TX>* xr = x + r * N;
-  const int64_t stride = (int64_t)gridDim.x * 256;
-  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < N; p += stride) {
-    cx<TX> acc = xr[p];
+  const int64_t N = S.N, off = S.off;
+  const int64_t stride = (int64_t)S.vnblk * 256;
+  for (int64_t p = (int64_t)(wg - S.vblk0) * 256 + threadIdx.x; p < N; p += stride) {
+    cx<TX> acc = x[off + p];
 #pragma unroll
-    for (int j = 0; j < KM; ++j) {
-      if (j < k) acc = cfma(c[j], cast<TX>(D.v[j][r * N + p]), acc);
-    }
-    xr[p] = acc;
+    for (int j = 0; j < KM; ++j)
+      if (j < k) acc = cfma(c[j], cast<TX>(D.v[j][off + p]), acc);
+    x[off + p] = acc;
   }
 }
 
-// ---------------------------------------------------------------------------
-// small elementwise helpers
-// ---------------------------------------------------------------------------
+// x = 0 on the active segments
+template <typename T>
+__global__ __launch_bounds__(256) void k_zero(const Seg* __restrict__ segs, const int* __restrict__ vmap,
+                                              cx<T>* __restrict__ x, const int* __restrict__ active) {
+  const int wg = blockIdx.x;
+  const int sid = vmap[wg];
+  if (active && !active[sid]) return;
+  const Seg& S = segs[sid];
+  const int64_t stride = (int64_t)S.vnblk * 256;
+  for (int64_t p = (int64_t)(wg - S.vblk0) * 256 + threadIdx.x; p < S.N; p += stride)
+    x[S.off + p] = czero<T>();
+}
+
+// elementwise precision conversion over a flat range
 template <typename TO, typename TI>
 __global__ __launch_bounds__(256) void k_convert(const cx<TI>* __restrict__ in, cx<TO>* __restrict__ out,
                                                  int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * 256;
-  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += stride)
-    out[p] = cast<TO>(in[p]);
+  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += stride) out[p] = cast<TO>(in[p]);
 }
 
-// x[r] = 0 for active right-hand sides
+// flat zero fill (used by the misfit driver)
 template <typename T>
-__global__ __launch_bounds__(256) void k_zero(cx<T>* __restrict__ x, int64_t N,
-                                              const int* __restrict__ active) {
-  const int r = blockIdx.y;
-  if (active && !active[r]) return;
+__global__ __launch_bounds__(256) void k_fill_zero(cx<T>* __restrict__ x, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * 256;
-  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < N; p += stride)
-    x[r * N + p] = czero<T>();
+  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += stride) x[p] = czero<T>();
 }
 
 }  // namespace helm

@@ -7,7 +7,6 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
-#include <map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -16,16 +15,31 @@
 #include "fwi.hip"
 #include "solver.hip"
 
+namespace {
+
+// A solver kept by the context for the next call with the same problems and
+// structural options (its workspace, tables and captured graph are reused;
+// the coarse models are re-injected from the current model contents on
+// every solve).
+struct CachedSolver {
+  std::string key;
+  std::unique_ptr<helm::Solver<float>> s32;
+  std::unique_ptr<helm::Solver<double>> s64;
+};
+
+}  // namespace
+
 struct helm_ctx {
   int device = 0;
   std::string err;
-  helm::DevBuf fwi_buf;  // sources / fields scratch of misfit_gradient
+  hipStream_t stream = nullptr;  // internal stream of the solves (capturable)
+  hipEvent_t ev = nullptr;
+  helm::DevBuf fwi_buf;          // sources / fields scratch of misfit_gradient
   helm::DevBuf fwi_small;
-  // layer tables of the last operator applied by helm_apply, reused while the
-  // grid and omega are unchanged (then an apply is one asynchronous launch)
-  std::unique_ptr<helm::Level> apply_level;
-  helm_grid apply_grid;
-  double apply_omega = 0.0;
+  helm::DevBuf batch_buf;        // concatenated q / u of a batched solve
+  CachedSolver solver;
+  std::unique_ptr<helm::Hierarchy> apply_h;  // operator of the last helm_apply
+  std::string apply_key;
 };
 
 namespace {
@@ -75,13 +89,14 @@ void check_grid(const helm_grid* g) {
 
 helm::GridSpec spec_of(const helm_grid* g) {
   helm::GridSpec s;
+  std::memset(&s, 0, sizeof(s));
   for (int a = 0; a < 3; ++a) s.n[a] = g->n[a];
   s.h = g->h;
   s.npml = g->npml;
   s.R = g->npml > 0 ? g->pml_R : 0.5;
   s.vref = g->npml > 0 ? g->v_ref : 1.0;
   s.stencil = g->stencil;
-  for (int c = 0; c < 7; ++c) s.w27[c] = g->w27[c];
+  for (int c = 0; c < 7; ++c) s.w27[c] = g->stencil == HELM_27PT ? g->w27[c] : 0.0;
   return s;
 }
 
@@ -90,11 +105,13 @@ helm::SolveOpts opts_of(const helm_solver_opts* o) {
   helm_default_opts(&d);
   if (!o) o = &d;
   helm::SolveOpts s;
+  std::memset(&s, 0, sizeof(s));
   HELM_REQUIRE(o->method == HELM_GMRES || o->method == HELM_FGMRES_ML, "unknown solver method");
   HELM_REQUIRE(o->restart >= 1 && o->restart <= helm::KMAX, "restart must be in 1..32");
   HELM_REQUIRE(o->max_cycles >= 0, "max_cycles must be >= 0");
   HELM_REQUIRE(o->tol > 0.0, "tol must be > 0");
-  if (o->method == HELM_FGMRES_ML) {
+  const bool ml = o->method == HELM_FGMRES_ML;
+  if (ml) {
     HELM_REQUIRE(o->levels >= 2 && o->levels <= 4, "levels must be in 2..4");
     HELM_REQUIRE(o->ks_o >= 1 && o->kc_o >= 1, "smoother / coarse cycles must be >= 1");
     HELM_REQUIRE(o->ks_i >= 1 && o->ks_i <= helm::KMAX && o->kc_i >= 1 && o->kc_i <= helm::KMAX,
@@ -104,11 +121,11 @@ helm::SolveOpts opts_of(const helm_solver_opts* o) {
   s.restart = o->restart;
   s.max_cycles = o->max_cycles;
   s.tol = o->tol;
-  s.ks_o = o->ks_o;
-  s.ks_i = o->ks_i;
-  s.kc_o = o->kc_o;
-  s.kc_i = o->kc_i;
-  s.levels = o->levels;
+  s.ks_o = ml ? o->ks_o : 1;
+  s.ks_i = ml ? o->ks_i : 1;
+  s.kc_o = ml ? o->kc_o : 1;
+  s.kc_i = ml ? o->kc_i : 1;
+  s.levels = ml ? o->levels : 1;
   s.warm_start = o->warm_start;
   return s;
 }
@@ -132,14 +149,116 @@ void to_info(const helm::SolveInfo& s, helm_solve_info* o) {
   o->relres_fp64 = s.relres;
 }
 
+// The internal stream every solve runs on, ordered after the caller's
+// pending work.  (A graph capture needs a stream of its own; the default
+// stream cannot be captured.)
+hipStream_t solve_stream(helm_ctx* ctx, void* caller) {
+  if (!ctx->stream) {
+    HELM_HIP_CHECK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+    HELM_HIP_CHECK(hipEventCreateWithFlags(&ctx->ev, hipEventDisableTiming));
+  }
+  HELM_HIP_CHECK(hipEventRecord(ctx->ev, (hipStream_t)caller));
+  HELM_HIP_CHECK(hipStreamWaitEvent(ctx->stream, ctx->ev, 0));
+  return ctx->stream;
+}
+
+std::string key_of(const std::vector<helm::ProblemSpec>& probs, const helm::SolveOpts& o, int dtype) {
+  std::string k((const char*)&o, sizeof(o));
+  k.append((const char*)&dtype, sizeof(int));
+  for (const auto& p : probs) {
+    k.append((const char*)&p.g, sizeof(p.g));
+    k.append((const char*)&p.omega, sizeof(double));
+    k.append((const char*)&p.m, sizeof(void*));
+  }
+  return k;
+}
+
 template <typename T>
-helm_status solve_t(const helm_grid* g, const void* m, double omega, int adjoint, int nrhs, const void* q,
-                    void* u, const helm::SolveOpts& o, helm_solve_info* info, hipStream_t st) {
-  helm::Solver<T> S(spec_of(g), (const T*)m, omega, nrhs, o, st);
+std::unique_ptr<helm::Solver<T>>& slot_of(CachedSolver& c);
+template <>
+std::unique_ptr<helm::Solver<float>>& slot_of<float>(CachedSolver& c) { return c.s32; }
+template <>
+std::unique_ptr<helm::Solver<double>>& slot_of<double>(CachedSolver& c) { return c.s64; }
+
+// The cached solver for these problems (structure: grids, omegas, models,
+// Krylov sizes), built on a miss.  Tolerance, cycle limit and warm start are
+// per call.
+template <typename T>
+helm::Solver<T>& solver_for(helm_ctx* ctx, const std::vector<helm::ProblemSpec>& probs, const helm::SolveOpts& o,
+                            hipStream_t st) {
+  helm::SolveOpts ko = o;
+  ko.warm_start = 0;
+  ko.max_cycles = 0;
+  ko.tol = 0.0;
+  const std::string key = key_of(probs, ko, sizeof(T) == 4 ? HELM_C64 : HELM_C128);
+  auto& slot = slot_of<T>(ctx->solver);
+  if (!slot || ctx->solver.key != key) {
+    ctx->solver.s32.reset();  // free the old workspace before allocating
+    ctx->solver.s64.reset();
+    slot.reset(new helm::Solver<T>(probs, o, st));
+    ctx->solver.key = key;
+  }
+  slot->set_call_opts(o);
+  return *slot;
+}
+
+std::vector<helm::ProblemSpec> shared_problems(const helm_grid* g, const void* m, double omega, int dir, int n) {
+  helm::ProblemSpec p;
+  std::memset(&p, 0, sizeof(p));
+  p.g = spec_of(g);
+  p.omega = omega;
+  p.dir = dir;
+  p.m = m;
+  return std::vector<helm::ProblemSpec>(n, p);
+}
+
+template <typename T>
+helm_status solve_t(helm_ctx* ctx, const helm_grid* g, const void* m, double omega, int adjoint, int nrhs,
+                    const void* q, void* u, const helm::SolveOpts& o, helm_solve_info* info, void* caller) {
+  hipStream_t st = solve_stream(ctx, caller);
+  helm::Solver<T>& S = solver_for<T>(ctx, shared_problems(g, m, omega, 0, nrhs), o, st);
   std::vector<helm::SolveInfo> inf(nrhs);
   const int worst = S.solve(adjoint, (const helm::cx<T>*)q, (helm::cx<T>*)u, inf.data());
   if (info)
     for (int r = 0; r < nrhs; ++r) to_info(inf[r], info + r);
+  return (helm_status)worst;
+}
+
+template <typename T>
+helm_status solve_batched_t(helm_ctx* ctx, int nprob, const helm_problem* probs, int adjoint,
+                            const helm::SolveOpts& o, helm_solve_info* info, void* caller) {
+  using namespace helm;
+  hipStream_t st = solve_stream(ctx, caller);
+  std::vector<ProblemSpec> ps(nprob);
+  int64_t total = 0;
+  for (int i = 0; i < nprob; ++i) {
+    std::memset(&ps[i], 0, sizeof(ProblemSpec));
+    ps[i].g = spec_of(&probs[i].grid);
+    ps[i].omega = probs[i].omega;
+    ps[i].dir = 0;
+    ps[i].m = probs[i].m;
+    total += (int64_t)probs[i].grid.n[0] * probs[i].grid.n[1] * probs[i].grid.n[2];
+  }
+  Solver<T>& S = solver_for<T>(ctx, ps, o, st);
+  // gather the right-hand sides (and initial guesses) into the segment layout
+  ctx->batch_buf.ensure(2 * (size_t)total * sizeof(cx<T>));
+  cx<T>* Q = ctx->batch_buf.as<cx<T>>();
+  cx<T>* U = Q + total;
+  const auto& L0 = S.hierarchy().level(0);
+  for (int i = 0; i < nprob; ++i) {
+    const size_t bytes = (size_t)L0.host[i].N * sizeof(cx<T>);
+    HELM_HIP_CHECK(hipMemcpyAsync(Q + L0.host[i].off, probs[i].q, bytes, hipMemcpyDeviceToDevice, st));
+    if (o.warm_start)
+      HELM_HIP_CHECK(hipMemcpyAsync(U + L0.host[i].off, probs[i].u, bytes, hipMemcpyDeviceToDevice, st));
+  }
+  std::vector<SolveInfo> inf(nprob);
+  const int worst = S.solve(adjoint, Q, U, inf.data());
+  for (int i = 0; i < nprob; ++i)
+    HELM_HIP_CHECK(hipMemcpyAsync(probs[i].u, U + L0.host[i].off, (size_t)L0.host[i].N * sizeof(cx<T>),
+                                  hipMemcpyDeviceToDevice, st));
+  HELM_HIP_CHECK(hipStreamSynchronize(st));
+  if (info)
+    for (int i = 0; i < nprob; ++i) to_info(inf[i], info + i);
   return (helm_status)worst;
 }
 
@@ -148,8 +267,9 @@ template <typename T>
 helm_status misfit_gradient_t(helm_ctx* ctx, const helm_grid* g, const void* m, double omega, int nsrc,
                               const int32_t* src_idx, const double* src_amp, int nrec, const int32_t* rec_idx,
                               const void* d, double* f, void* grad, void* u_store, int flags,
-                              const helm::SolveOpts& o, helm_solve_info* info, hipStream_t st) {
+                              const helm::SolveOpts& o, helm_solve_info* info, void* caller) {
   using namespace helm;
+  hipStream_t st = solve_stream(ctx, caller);
   const int64_t N = (int64_t)g->n[0] * g->n[1] * g->n[2];
   const int64_t plane = (int64_t)g->n[1] * g->n[2];
   auto lin = [&](const int32_t* p) { return (int64_t)p[0] * plane + (int64_t)p[1] * g->n[2] + p[2]; };
@@ -217,20 +337,21 @@ helm_status misfit_gradient_t(helm_ctx* ctx, const helm_grid* g, const void* m, 
   HELM_HIP_CHECK(hipMemcpyAsync(d_nptr, node_ptr.data(), (nnode + 1) * sizeof(int), hipMemcpyHostToDevice, st));
   HELM_HIP_CHECK(hipMemcpyAsync(d_nrec, node_rec.data(), nrec * sizeof(int), hipMemcpyHostToDevice, st));
 
-  helm::Solver<T> S(spec_of(g), (const T*)m, omega, nsrc, o, st);
-  std::vector<helm::SolveInfo> inf(nsrc);
+  Solver<T>& S = solver_for<T>(ctx, shared_problems(g, m, omega, 0, nsrc), o, st);
+  std::vector<SolveInfo> inf(nsrc);
   int worst = 0;
+  const unsigned fb = std::min<unsigned>(65536, ceil_div((int64_t)nsrc * N, 256));
   const bool reuse = (flags & HELM_MG_REUSE_U) != 0;
   if (!reuse) {
     const double inv_h3 = 1.0 / (g->h * g->h * g->h);
-    hipLaunchKernelGGL((k_point_sources<T>), dim3(vec_blocks(N), nsrc), dim3(256), 0, st, Q, N,
-                       (const int64_t*)d_src, (const double2*)d_amp, inv_h3);
+    hipLaunchKernelGGL((k_point_sources<T>), dim3(std::min<unsigned>(DOT_BLOCKS, ceil_div(N, 256)), nsrc),
+                       dim3(256), 0, st, Q, N, (const int64_t*)d_src, (const double2*)d_amp, inv_h3);
     worst = std::max(worst, S.solve(0, Q, U, inf.data()));
     if (info)
       for (int s = 0; s < nsrc; ++s) to_info(inf[s], info + s);
     if (u64)  // keep the FP64 iterates as the stored fields
-      hipLaunchKernelGGL((k_convert<double, double>), dim3(vec_blocks(N) * 4), dim3(256), 0, st,
-                         S.iterate(), (cx<double>*)u_store, N * nsrc);
+      hipLaunchKernelGGL((k_convert<double, double>), dim3(fb), dim3(256), 0, st, S.iterate(),
+                         (cx<double>*)u_store, N * nsrc);
     hipLaunchKernelGGL((k_sample_residual<double, T>), dim3(rblk, nsrc), dim3(256), 0, st, S.iterate(), N,
                        (const int64_t*)d_rec, nrec, (const cx<T>*)d, d_res, d_part);
   } else if (u64) {
@@ -249,10 +370,10 @@ helm_status misfit_gradient_t(helm_ctx* ctx, const helm_grid* g, const void* m, 
   *f = 0.5 * fsum;
   if (flags & HELM_MG_FORWARD_ONLY) return (helm_status)worst;
   // adjoint sources b_s = -P_r^T r_s, then H^H v_s = b_s
-  hipLaunchKernelGGL((k_zero<T>), dim3(vec_blocks(N), nsrc), dim3(256), 0, st, Q, N, (const int*)nullptr);
+  hipLaunchKernelGGL((k_fill_zero<T>), dim3(fb), dim3(256), 0, st, Q, (int64_t)nsrc * N);
   hipLaunchKernelGGL((k_adjoint_source<T>), dim3(ceil_div(nnode, 256), nsrc), dim3(256), 0, st, Q, N,
-                     (const int64_t*)d_node, (const int*)d_nptr, (const int*)d_nrec, nnode,
-                     (const cx<T>*)d_res, nrec);
+                     (const int64_t*)d_node, (const int*)d_nptr, (const int*)d_nrec, nnode, (const cx<T>*)d_res,
+                     nrec);
   worst = std::max(worst, S.solve(1, Q, V, inf.data()));
   if (info)
     for (int s = 0; s < nsrc; ++s) to_info(inf[s], info + nsrc + s);
@@ -283,15 +404,17 @@ helm_status misfit_gradient_t(helm_ctx* ctx, const helm_grid* g, const void* m, 
 
 extern "C" {
 
-const char* helm_version(void) { return "helm-gfx950 0.1"; }
+const char* helm_version(void) { return "helm-gfx950 0.2"; }
 
 helm_status helm_create(helm_ctx** ctx, int device) {
   if (!ctx) return fail(nullptr, HELM_E_INVAL, "null output pointer");
   *ctx = nullptr;
   int count = 0;
   hipError_t e = hipGetDeviceCount(&count);
-  if (e != hipSuccess || device < 0 || device >= count)
+  if (e != hipSuccess || device < 0 || device >= count) {
+    (void)hipGetLastError();
     return fail(nullptr, HELM_E_HIP, "no such HIP device");
+  }
   helm_ctx* c = new (std::nothrow) helm_ctx();
   if (!c) return fail(nullptr, HELM_E_NOMEM, "out of host memory");
   c->device = device;
@@ -303,6 +426,11 @@ helm_status helm_destroy(helm_ctx* ctx) {
   if (!ctx) return HELM_OK;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
+  ctx->solver.s32.reset();
+  ctx->solver.s64.reset();
+  ctx->apply_h.reset();
+  if (ctx->ev) (void)hipEventDestroy(ctx->ev);
+  if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return HELM_OK;
 }
@@ -328,8 +456,16 @@ size_t helm_workspace_bytes(const helm_grid* g, const helm_solver_opts* o, int n
     check_grid(g);
     if (nrhs < 1) return 0;
     const helm::SolveOpts so = opts_of(o);
-    return g->dtype == HELM_C64 ? helm::Solver<float>::workspace_bytes(spec_of(g), so, nrhs)
-                                : helm::Solver<double>::workspace_bytes(spec_of(g), so, nrhs);
+    check_coarse_sizes(g, so);
+    const int nlev = so.method == HELM_FGMRES_ML ? so.levels : 1;
+    std::vector<int64_t> Nlev(nlev);
+    for (int l = 0; l < nlev; ++l) {
+      int n[3];
+      helm::Hierarchy::coarse_dims(g->n, l, n);
+      Nlev[l] = (int64_t)n[0] * n[1] * n[2] * nrhs;
+    }
+    return g->dtype == HELM_C64 ? helm::Solver<float>::workspace_bytes(Nlev, so)
+                                : helm::Solver<double>::workspace_bytes(Nlev, so);
   } catch (...) {
     return 0;
   }
@@ -344,25 +480,24 @@ helm_status helm_apply(helm_ctx* ctx, const helm_grid* g, const void* m, double 
     HELM_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
     HELM_REQUIRE(x != y, "x and y must not overlap");
     hipStream_t st = (hipStream_t)stream;
-    if (!ctx->apply_level || std::memcmp(&ctx->apply_grid, g, sizeof(helm_grid)) != 0 ||
-        ctx->apply_omega != omega) {
-      // rebuilding frees the previous tables: finish work that may use them
-      if (ctx->apply_level) HELM_HIP_CHECK(hipDeviceSynchronize());
-      ctx->apply_level.reset(new helm::Level());
-      helm::GridSpec s = spec_of(g);
-      init_level(s, *ctx->apply_level, s.n, s.h, 1, omega, st);
-      std::memcpy(&ctx->apply_grid, g, sizeof(helm_grid));
-      ctx->apply_omega = omega;
+    auto probs = shared_problems(g, m, omega, adjoint ? 1 : 0, nrhs);
+    const helm::SolveOpts so = opts_of(nullptr);
+    const std::string key = key_of(probs, so, g->dtype) + (adjoint ? "A" : "F");
+    if (!ctx->apply_h || ctx->apply_key != key) {
+      // rebuilding frees the previous operator: finish work that may use it
+      if (ctx->apply_h) HELM_HIP_CHECK(hipDeviceSynchronize());
+      ctx->apply_h.reset(new helm::Hierarchy(probs, 1, g->dtype == HELM_C64 ? 4 : 8, st));
+      ctx->apply_key = key;
     }
-    const helm::Level& L = *ctx->apply_level;
+    const helm::LevelSet& L = ctx->apply_h->level(0);
     if (g->dtype == HELM_C64)
       helm::launch_h<float, float, float, float, float, false, false>(
-          L, adjoint ? 1 : 0, nrhs, (const helm::cx<float>*)x, nullptr, (const float*)m,
-          (const helm::cx<float>*)nullptr, nullptr, (helm::cx<float>*)y, nullptr, nullptr, st);
+          L, (const helm::cx<float>*)x, nullptr, (const helm::cx<float>*)nullptr, nullptr, (helm::cx<float>*)y,
+          nullptr, nullptr, st);
     else
       helm::launch_h<double, double, double, double, double, false, false>(
-          L, adjoint ? 1 : 0, nrhs, (const helm::cx<double>*)x, nullptr, (const double*)m,
-          (const helm::cx<double>*)nullptr, nullptr, (helm::cx<double>*)y, nullptr, nullptr, st);
+          L, (const helm::cx<double>*)x, nullptr, (const helm::cx<double>*)nullptr, nullptr,
+          (helm::cx<double>*)y, nullptr, nullptr, st);
     HELM_HIP_CHECK(hipGetLastError());
     return HELM_OK;
   });
@@ -377,9 +512,27 @@ helm_status helm_solve(helm_ctx* ctx, const helm_grid* g, const void* m, double 
     HELM_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
     const helm::SolveOpts so = opts_of(o);
     check_coarse_sizes(g, so);
-    hipStream_t st = (hipStream_t)stream;
-    if (g->dtype == HELM_C64) return solve_t<float>(g, m, omega, adjoint ? 1 : 0, nrhs, q, u, so, info, st);
-    return solve_t<double>(g, m, omega, adjoint ? 1 : 0, nrhs, q, u, so, info, st);
+    if (g->dtype == HELM_C64) return solve_t<float>(ctx, g, m, omega, adjoint ? 1 : 0, nrhs, q, u, so, info, stream);
+    return solve_t<double>(ctx, g, m, omega, adjoint ? 1 : 0, nrhs, q, u, so, info, stream);
+  });
+}
+
+helm_status helm_solve_batched(helm_ctx* ctx, int nprob, const helm_problem* probs, int adjoint,
+                               const helm_solver_opts* o, helm_solve_info* info, void* stream) {
+  return guarded(ctx, [&]() -> helm_status {
+    HELM_REQUIRE(nprob >= 1 && probs, "need at least one problem");
+    const helm::SolveOpts so = opts_of(o);
+    for (int i = 0; i < nprob; ++i) {
+      check_grid(&probs[i].grid);
+      check_coarse_sizes(&probs[i].grid, so);
+      HELM_REQUIRE(probs[i].m && probs[i].q && probs[i].u, "null device pointer in a problem");
+      HELM_REQUIRE(probs[i].omega > 0.0 && std::isfinite(probs[i].omega), "omega must be positive");
+      HELM_REQUIRE(probs[i].grid.dtype == probs[0].grid.dtype, "all problems must have the same dtype");
+      HELM_REQUIRE(probs[i].grid.stencil == probs[0].grid.stencil, "all problems must use the same stencil");
+    }
+    if (probs[0].grid.dtype == HELM_C64)
+      return solve_batched_t<float>(ctx, nprob, probs, adjoint ? 1 : 0, so, info, stream);
+    return solve_batched_t<double>(ctx, nprob, probs, adjoint ? 1 : 0, so, info, stream);
   });
 }
 
@@ -404,12 +557,11 @@ helm_status misfit_gradient(helm_ctx* ctx, const helm_grid* g, const void* m, do
         HELM_REQUIRE(rec_idx[3 * k + a] >= 0 && rec_idx[3 * k + a] < g->n[a], "receiver outside the grid");
     const helm::SolveOpts so = opts_of(o);
     check_coarse_sizes(g, so);
-    hipStream_t st = (hipStream_t)stream;
     if (g->dtype == HELM_C64)
       return misfit_gradient_t<float>(ctx, g, m, omega, nsrc, src_idx, src_amp, nrec, rec_idx, d, f, grad,
-                                      u_store, flags, so, info, st);
+                                      u_store, flags, so, info, stream);
     return misfit_gradient_t<double>(ctx, g, m, omega, nsrc, src_idx, src_amp, nrec, rec_idx, d, f, grad,
-                                     u_store, flags, so, info, st);
+                                     u_store, flags, so, info, stream);
   });
 }
 

@@ -1,20 +1,29 @@
-// Host-side description of one discrete Helmholtz operator (one grid level)
-// and the launch wrappers of the stencil kernels.
+// Host-side setup of the discrete operators of a solve: layer tables per
+// distinct (grid, omega, level), the segments of every level with their
+// workgroup maps, the coarse models, and the stencil launch wrapper.
 //
 // Level l of the multigrid hierarchy has n_l = floor(n_{l-1}/2) + 1 nodes per
 // axis, spacing 2^l h, the same omega, and the absorbing-layer profile of the
 // fine grid evaluated at fine coordinates 2^l I and 2^l (I +- 1/2)
 // (re-discretisation of the same problem on the coarser grid; arXiv:1703.09268,
-// ML-GMRES section, where the coarse problem is "an instance of the original
-// problem").
+// ML-GMRES section, where the coarse problem is an instance of the original
+// one).  The coarse model is injected from the next finer level.
 #pragma once
 
 #include <cmath>
 #include <complex>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
 #include <vector>
 
 #include "common.h"
+#include "krylov.hip"
+#include "segment.h"
 #include "stencil.hip"
+#include "transfer.hip"
 
 namespace helm {
 
@@ -36,11 +45,14 @@ struct DevBuf {
     release();
     hipError_t e = hipMalloc(&p, b);
     if (e != hipSuccess) {
+      (void)hipGetLastError();
       p = nullptr;
       throw Error{-2, "hipMalloc of " + std::to_string(b) + " bytes failed"};
     }
     bytes = b;
   }
+  template <typename T>
+  T* as() const { return reinterpret_cast<T*>(p); }
 };
 
 struct GridSpec {
@@ -53,6 +65,14 @@ struct GridSpec {
   double w27[7];
 };
 
+// One problem of a solve (fine level).
+struct ProblemSpec {
+  GridSpec g;
+  double omega;
+  int dir;         // 0: H, 1: H^H
+  const void* m;   // fine model (device)
+};
+
 // Damping profile of the layer at fine coordinate tf (fine-grid node units).
 inline double layer_sigma(const GridSpec& g, int axis, double tf) {
   if (g.npml == 0) return 0.0;
@@ -62,182 +82,317 @@ inline double layer_sigma(const GridSpec& g, int axis, double tf) {
   return smax * (d / g.npml) * (d / g.npml);
 }
 
-struct Level {
+// Layer tables and 27-point description of one operator on one level.
+struct OpTables {
   int n[3];
-  int64_t N;
-  double h;
-  int stride;
-  int stencil;
+  DevBuf tabf, tabd;  // [dir][axis][alpha, beta, delta][n_axis]
+  int tpre[3], tdir;
   Int27 in27;
-  double omega;
-  // layer tables, [dir][axis][kind][n_axis], kinds alpha, beta, delta
-  DevBuf tabf, tabd;
-  Tab7<float> tf[2];
-  Tab7<double> td[2];
-  std::vector<std::complex<double>> host[2][3][3];
-  // model on this level (level 0 borrows the caller's pointer)
-  const void* m = nullptr;
-  DevBuf m_own;
 };
 
-// Fill the host tables of level L for grid g at this level's stride.
-inline void build_tables(const GridSpec& g, Level& L) {
+inline std::unique_ptr<OpTables> build_tables(const GridSpec& g, double omega, const int n[3], double h,
+                                              int stride, hipStream_t st) {
   typedef std::complex<double> C;
-  const double w = L.omega;
+  std::unique_ptr<OpTables> T(new OpTables());
+  for (int a = 0; a < 3; ++a) T->n[a] = n[a];
+  T->tdir = 3 * (n[0] + n[1] + n[2]);
+  T->tpre[0] = 0;
+  T->tpre[1] = 3 * n[0];
+  T->tpre[2] = 3 * (n[0] + n[1]);
+  std::vector<cx<double>> hd(2 * (size_t)T->tdir);
   for (int a = 0; a < 3; ++a) {
-    const int n = L.n[a];
-    auto s_at = [&](double t) { return C(1.0, layer_sigma(g, a, t * L.stride) / w); };
-    std::vector<C> cp(n), cm(n);
-    for (int i = 0; i < n; ++i) {
+    const int na = n[a];
+    auto s_at = [&](double t) { return C(1.0, layer_sigma(g, a, t * stride) / omega); };
+    std::vector<C> cp(na), cm(na);
+    for (int i = 0; i < na; ++i) {
       const C s0 = s_at(i), sp = s_at(i + 0.5), sm = s_at(i - 0.5);
-      cp[i] = 1.0 / (L.h * L.h * s0 * sp);
-      cm[i] = 1.0 / (L.h * L.h * s0 * sm);
+      cp[i] = 1.0 / (h * h * s0 * sp);
+      cm[i] = 1.0 / (h * h * s0 * sm);
     }
-    for (int d = 0; d < 3; ++d) L.host[0][a][d].assign(n, C(0, 0));
-    for (int d = 0; d < 3; ++d) L.host[1][a][d].assign(n, C(0, 0));
-    for (int i = 0; i < n; ++i) {
+    for (int i = 0; i < na; ++i) {
       // forward: alpha = cp, beta = cm, delta = 0
-      L.host[0][a][0][i] = cp[i];
-      L.host[0][a][1][i] = cm[i];
-      // adjoint: conj of the transposed couplings
-      const C al = (i + 1 < n) ? std::conj(cm[i + 1]) : C(0, 0);
+      const size_t f0 = (size_t)T->tpre[a];
+      hd[f0 + i] = mk<double>(cp[i].real(), cp[i].imag());
+      hd[f0 + na + i] = mk<double>(cm[i].real(), cm[i].imag());
+      hd[f0 + 2 * na + i] = mk<double>(0.0, 0.0);
+      // adjoint: conjugates of the transposed couplings
+      const C al = (i + 1 < na) ? std::conj(cm[i + 1]) : C(0, 0);
       const C be = (i > 0) ? std::conj(cp[i - 1]) : C(0, 0);
-      const C ga = -std::conj(cp[i] + cm[i]);
-      L.host[1][a][0][i] = al;
-      L.host[1][a][1][i] = be;
-      L.host[1][a][2][i] = ga + al + be;
+      const C de = -std::conj(cp[i] + cm[i]) + al + be;
+      const size_t a0 = (size_t)T->tdir + T->tpre[a];
+      hd[a0 + i] = mk<double>(al.real(), al.imag());
+      hd[a0 + na + i] = mk<double>(be.real(), be.imag());
+      hd[a0 + 2 * na + i] = mk<double>(de.real(), de.imag());
     }
   }
+  std::vector<cx<float>> hf(hd.size());
+  for (size_t i = 0; i < hd.size(); ++i) hf[i] = cast<float>(hd[i]);
+  T->tabd.ensure(hd.size() * sizeof(cx<double>));
+  T->tabf.ensure(hf.size() * sizeof(cx<float>));
+  HELM_HIP_CHECK(hipMemcpyAsync(T->tabd.p, hd.data(), hd.size() * sizeof(cx<double>), hipMemcpyHostToDevice, st));
+  HELM_HIP_CHECK(hipMemcpyAsync(T->tabf.p, hf.data(), hf.size() * sizeof(cx<float>), hipMemcpyHostToDevice, st));
+  HELM_HIP_CHECK(hipStreamSynchronize(st));  // the host vectors go out of scope
   // 27-point interior range per axis: rows whose +-1 neighbours are damping-free
   for (int a = 0; a < 3; ++a) {
     int lo = 1, hi = 0;
     bool found = false;
-    for (int i = 0; i < L.n[a]; ++i) {
-      const bool ok = layer_sigma(g, a, (double)(i - 1) * L.stride) == 0.0 &&
-                      layer_sigma(g, a, (double)(i + 1) * L.stride) == 0.0;
+    for (int i = 0; i < n[a]; ++i) {
+      const bool ok = layer_sigma(g, a, (double)(i - 1) * stride) == 0.0 &&
+                      layer_sigma(g, a, (double)(i + 1) * stride) == 0.0;
       if (ok && !found) { lo = i; found = true; }
       if (ok) hi = i;
     }
-    L.in27.lo[a] = lo;
-    L.in27.hi[a] = found ? hi : lo - 1;
+    T->in27.lo[a] = lo;
+    T->in27.hi[a] = found ? hi : lo - 1;
   }
   const double w1 = g.w27[0], w2 = g.w27[1], w3 = g.w27[2];
-  const double h2 = L.h * L.h;
-  L.in27.lw[0] = (w1 * -6.0 + w2 * (-6.0 / 3.0 - 12.0 / 6.0) + w3 * (-8.0 / 4.0)) / h2;
-  L.in27.lw[1] = (w1 * 1.0 + w2 * (1.0 / 3.0)) / h2;
-  L.in27.lw[2] = (w2 * (1.0 / 6.0)) / h2;
-  L.in27.lw[3] = (w3 * (1.0 / 4.0)) / h2;
-  for (int c = 0; c < 4; ++c) L.in27.mw[c] = g.w27[3 + c];
-  if (g.stencil == 0) {
-    L.in27.lw[0] = L.in27.lw[1] = L.in27.lw[2] = L.in27.lw[3] = 0.0;
-    L.in27.mw[0] = 1.0;
-    L.in27.mw[1] = L.in27.mw[2] = L.in27.mw[3] = 0.0;
+  const double h2 = h * h;
+  if (g.stencil == 1) {
+    // L1 = h^-2 sum of axis second differences; L2 = L1/3 + (6h^2)^-1 sum
+    // over face diagonals; L3 = (4h^2)^-1 sum over body diagonals
+    T->in27.lw[0] = (w1 * -6.0 + w2 * (-6.0 / 3.0 - 12.0 / 6.0) + w3 * (-8.0 / 4.0)) / h2;
+    T->in27.lw[1] = (w1 * 1.0 + w2 * (1.0 / 3.0)) / h2;
+    T->in27.lw[2] = (w2 * (1.0 / 6.0)) / h2;
+    T->in27.lw[3] = (w3 * (1.0 / 4.0)) / h2;
+    for (int c = 0; c < 4; ++c) T->in27.mw[c] = g.w27[3 + c];
+  } else {
+    for (int c = 0; c < 4; ++c) T->in27.lw[c] = 0.0;
+    T->in27.mw[0] = 1.0;
+    T->in27.mw[1] = T->in27.mw[2] = T->in27.mw[3] = 0.0;
   }
+  return T;
 }
 
-// Upload the tables in both precisions (the mixed-precision residual uses
-// the double tables on the complex64 path).
-inline void upload_tables(Level& L, hipStream_t st) {
-  const size_t tot = (size_t)2 * 3 * (L.n[0] + L.n[1] + L.n[2]);
-  L.tabd.ensure(tot * sizeof(cx<double>));
-  L.tabf.ensure(tot * sizeof(cx<float>));
-  std::vector<cx<double>> hd(tot);
-  std::vector<cx<float>> hf(tot);
-  size_t off = 0;
-  for (int dir = 0; dir < 2; ++dir)
-    for (int a = 0; a < 3; ++a)
-      for (int kind = 0; kind < 3; ++kind) {
-        cx<double>* pd = reinterpret_cast<cx<double>*>(L.tabd.p) + off;
-        cx<float>* pf = reinterpret_cast<cx<float>*>(L.tabf.p) + off;
-        if (kind == 0) { L.td[dir].al[a] = pd; L.tf[dir].al[a] = pf; }
-        if (kind == 1) { L.td[dir].be[a] = pd; L.tf[dir].be[a] = pf; }
-        if (kind == 2) { L.td[dir].de[a] = pd; L.tf[dir].de[a] = pf; }
-        const auto& v = L.host[dir][a][kind];
-        for (size_t i = 0; i < v.size(); ++i) {
-          hd[off + i] = mk<double>(v[i].real(), v[i].imag());
-          hf[off + i] = mk<float>((float)v[i].real(), (float)v[i].imag());
-        }
-        off += v.size();
-      }
-  HELM_HIP_CHECK(hipMemcpyAsync(L.tabd.p, hd.data(), tot * sizeof(cx<double>), hipMemcpyHostToDevice, st));
-  HELM_HIP_CHECK(hipMemcpyAsync(L.tabf.p, hf.data(), tot * sizeof(cx<float>), hipMemcpyHostToDevice, st));
-  HELM_HIP_CHECK(hipStreamSynchronize(st));
-}
-
-inline void init_level(const GridSpec& g, Level& L, const int n[3], double h, int stride, double omega,
-                       hipStream_t st) {
-  for (int a = 0; a < 3; ++a) L.n[a] = n[a];
-  L.N = (int64_t)n[0] * n[1] * n[2];
-  L.h = h;
-  L.stride = stride;
-  L.stencil = g.stencil;
-  L.omega = omega;
-  build_tables(g, L);
-  upload_tables(L, st);
-}
-
-template <typename T> inline const Tab7<T>& tab_of(const Level& L, int dir);
-template <> inline const Tab7<float>& tab_of<float>(const Level& L, int dir) { return L.tf[dir]; }
-template <> inline const Tab7<double>& tab_of<double>(const Level& L, int dir) { return L.td[dir]; }
-
-// Launch geometry of the 7-point x-marching kernel.
-struct Tile7 {
-  int tz, ty, xchunk, nxc;
-  dim3 grid;
+// All segments of one level with their workgroup maps.
+struct LevelSet {
+  int stencil = 0;
+  std::vector<Seg> host;
+  DevBuf segs, smap, vmap, tmap, own;
+  int nsblk = 0, nvblk = 0, ntblk = 0;
+  int64_t total = 0;  // vector length (sum of N)
+  std::vector<std::unique_ptr<DevBuf>> models;  // owned coarse models
+  const Seg* d() const { return segs.as<const Seg>(); }
 };
 
-inline Tile7 plan7(const Level& L, int nrhs) {
-  Tile7 t;
-  const int nz = L.n[2], ny = L.n[1], nx = L.n[0];
-  if (nz >= 48) { t.tz = 64; t.ty = 4; }
-  else if (nz >= 24) { t.tz = 32; t.ty = 8; }
-  else { t.tz = 16; t.ty = 16; }
-  const int gx = (int)ceil_div(nz, t.tz), gy = (int)ceil_div(ny, t.ty);
-  const int64_t per_plane = (int64_t)gx * gy * nrhs;
-  int nxc = (int)std::max<int64_t>(1, std::min<int64_t>(nx, (4096 + per_plane - 1) / per_plane));
-  int xchunk = (nx + nxc - 1) / nxc;
-  if (xchunk < 4) xchunk = std::min(nx, 4);
-  nxc = (nx + xchunk - 1) / xchunk;
-  t.xchunk = xchunk;
-  t.nxc = nxc;
-  t.grid = dim3(gx, gy, nxc * nrhs);
-  return t;
-}
-
-inline int nblk_stencil(const Level& L, int nrhs) {
-  if (L.stencil == 1) return (int)ceil_div(L.N, 256);
-  const Tile7 t = plan7(L, nrhs);
-  return (int)(t.grid.x * t.grid.y * t.nxc);
-}
-
-// out = [s_b b -] s_x H x  on nrhs right-hand sides.  Returns the number of
-// partial-norm workgroups per right-hand side when NORM.
-template <typename TC, typename TX, typename TM, typename TB, typename TO, bool RESID, bool NORM>
-int launch_h(const Level& L, int adj, int nrhs, const cx<TX>* x, const double* xs, const TM* m,
-             const cx<TB>* b, const double* bs, cx<TO>* out, double* part, const int* active,
-             hipStream_t st) {
-  const TC w2 = (TC)(L.omega * L.omega);
-  const Tab7<TC>& tab = tab_of<TC>(L, adj);
-  if (L.stencil == 1) {
-    dim3 grid(ceil_div(L.N, 256), nrhs);
-    if (adj)
-      hipLaunchKernelGGL((k_h27<TC, TX, TM, TB, TO, true, RESID, NORM>), grid, dim3(256), 0, st, x, xs, m,
-                         w2, tab, L.in27, b, bs, out, part, active, L.n[0], L.n[1], L.n[2]);
-    else
-      hipLaunchKernelGGL((k_h27<TC, TX, TM, TB, TO, false, RESID, NORM>), grid, dim3(256), 0, st, x, xs,
-                         m, w2, tab, L.in27, b, bs, out, part, active, L.n[0], L.n[1], L.n[2]);
-    return (int)grid.x;
+// x-chunk (planes per stencil workgroup) for a level: enough workgroups to
+// fill the chip several times, at least 4 planes per workgroup.  The
+// HELM_XCHUNK environment variable overrides it (tile experiments).
+inline int choose_xchunk(const std::vector<Seg>& segs) {
+  if (const char* e = std::getenv("HELM_XCHUNK")) {
+    const int v = std::atoi(e);
+    if (v >= 1) return v;
   }
-  const Tile7 t = plan7(L, nrhs);
-#define HELM_L7(TZ, TY)                                                                        \
-  hipLaunchKernelGGL((k_h7<TC, TX, TM, TB, TO, RESID, NORM, TZ, TY>), t.grid, dim3(TZ, TY), 0, st, \
-                     x, xs, m, w2, tab, b, bs, out, part, active, L.n[0], L.n[1], L.n[2], t.xchunk, \
-                     t.nxc)
-  if (t.tz == 64) HELM_L7(64, 4);
-  else if (t.tz == 32) HELM_L7(32, 8);
-  else HELM_L7(16, 16);
-#undef HELM_L7
-  return (int)(t.grid.x * t.grid.y * t.nxc);
+  int64_t plane = 0;
+  int nxmax = 1;
+  for (const Seg& s : segs) {
+    plane += s.plane_blocks;
+    nxmax = std::max(nxmax, s.n[0]);
+  }
+  const int64_t target = 8192;
+  const int64_t nxc = std::max<int64_t>(1, (target + plane - 1) / std::max<int64_t>(plane, 1));
+  int xchunk = (int)((nxmax + nxc - 1) / nxc);
+  return std::max(4, std::min(xchunk, nxmax));
+}
+
+// The operator hierarchy of a list of problems: tables, segments, maps,
+// coarse models.
+class Hierarchy {
+ public:
+  // model_bytes: size of one model value (4 for the complex64 path, 8 for complex128)
+  Hierarchy(const std::vector<ProblemSpec>& probs, int nlev, size_t model_bytes, hipStream_t st)
+      : nlev_(nlev), st_(st), model_bytes_(model_bytes) {
+    const int ns = (int)probs.size();
+    HELM_REQUIRE(ns >= 1, "no problems");
+    stencil_ = probs[0].g.stencil;
+    for (const auto& p : probs) HELM_REQUIRE(p.g.stencil == stencil_, "a batch must use one stencil type");
+    lev_.resize(nlev);
+    // segment -> table index per level, deduplicated by (grid, omega)
+    std::vector<int> tab_of(ns);
+    std::map<std::string, int> tkey;
+    std::vector<const ProblemSpec*> tprob;
+    for (int s = 0; s < ns; ++s) {
+      std::string key((const char*)&probs[s].g, sizeof(GridSpec));
+      key.append((const char*)&probs[s].omega, sizeof(double));
+      auto it = tkey.find(key);
+      if (it == tkey.end()) {
+        tab_of[s] = (int)tprob.size();
+        tkey[key] = tab_of[s];
+        tprob.push_back(&probs[s]);
+      } else {
+        tab_of[s] = it->second;
+      }
+    }
+    // coarse model owners: one per distinct (model pointer, grid)
+    std::vector<int> mown(ns, -1);
+    {
+      std::map<std::string, int> mkey;
+      for (int s = 0; s < ns; ++s) {
+        std::string key((const char*)&probs[s].m, sizeof(void*));
+        key.append((const char*)&probs[s].g, sizeof(GridSpec));
+        auto it = mkey.find(key);
+        if (it == mkey.end()) { mkey[key] = s; mown[s] = s; }
+        else mown[s] = it->second;
+      }
+    }
+    for (int l = 0; l < nlev; ++l) {
+      lev_[l].reset(new LevelSet());
+      LevelSet& L = *lev_[l];
+      L.stencil = stencil_;
+      L.host.resize(ns);
+      // tables of this level
+      std::vector<OpTables*> tl(tprob.size());
+      for (size_t t = 0; t < tprob.size(); ++t) {
+        int n[3];
+        coarse_dims(tprob[t]->g.n, l, n);
+        tables_.push_back(build_tables(tprob[t]->g, tprob[t]->omega, n, tprob[t]->g.h * (1 << l), 1 << l, st));
+        tl[t] = tables_.back().get();
+      }
+      int64_t off = 0;
+      for (int s = 0; s < ns; ++s) {
+        Seg& S = L.host[s];
+        std::memset(&S, 0, sizeof(Seg));
+        coarse_dims(probs[s].g.n, l, S.n);
+        S.dir = probs[s].dir;
+        S.N = (int64_t)S.n[0] * S.n[1] * S.n[2];
+        S.off = off;
+        off += S.N;
+        S.w2 = probs[s].omega * probs[s].omega;
+        const OpTables& T = *tl[tab_of[s]];
+        S.tabf = T.tabf.p;
+        S.tabd = T.tabd.p;
+        for (int a = 0; a < 3; ++a) S.tpre[a] = T.tpre[a];
+        S.tdir = T.tdir;
+        S.in27 = T.in27;
+        S.plane_blocks = (int)ceil_div((int64_t)S.n[1] * S.n[2], 256);
+      }
+      L.total = off;
+      // models: level 0 borrows the caller's; coarse levels own one per distinct model
+      std::vector<int> own(ns, 0);
+      for (int s = 0; s < ns; ++s) {
+        if (l == 0) {
+          L.host[s].m = probs[s].m;
+        } else if (mown[s] == s) {
+          L.models.emplace_back(new DevBuf());
+          L.models.back()->ensure((size_t)L.host[s].N * model_bytes_);
+          L.host[s].m = L.models.back()->p;
+          own[s] = 1;
+        } else {
+          L.host[s].m = L.host[mown[s]].m;
+        }
+      }
+      // workgroup ranges
+      const int xchunk = choose_xchunk(L.host);
+      int sb = 0, vb = 0, tb = 0;
+      for (int s = 0; s < ns; ++s) {
+        Seg& S = L.host[s];
+        S.xchunk = xchunk;
+        S.nxc = (S.n[0] + xchunk - 1) / xchunk;
+        S.sblk0 = sb;
+        S.snblk = stencil_ == 0 ? S.plane_blocks * S.nxc : 0;
+        sb += S.snblk;
+        S.vblk0 = vb;
+        S.vnblk = (int)std::min<int64_t>(DOT_BLOCKS, ceil_div(S.N, 256));
+        vb += S.vnblk;
+        S.tblk0 = tb;
+        S.tnblk = (int)ceil_div(S.N, 256);
+        tb += S.tnblk;
+      }
+      L.nsblk = sb;
+      L.nvblk = vb;
+      L.ntblk = tb;
+      std::vector<int> smap(std::max(sb, 1)), vmap(std::max(vb, 1)), tmap(std::max(tb, 1));
+      for (int s = 0; s < ns; ++s) {
+        const Seg& S = L.host[s];
+        for (int b = 0; b < S.snblk; ++b) smap[S.sblk0 + b] = s;
+        for (int b = 0; b < S.vnblk; ++b) vmap[S.vblk0 + b] = s;
+        for (int b = 0; b < S.tnblk; ++b) tmap[S.tblk0 + b] = s;
+      }
+      upload(L.smap, smap);
+      upload(L.vmap, vmap);
+      upload(L.tmap, tmap);
+      upload(L.own, own);
+      L.segs.ensure(ns * sizeof(Seg));
+      HELM_HIP_CHECK(hipMemcpyAsync(L.segs.p, L.host.data(), ns * sizeof(Seg), hipMemcpyHostToDevice, st));
+      HELM_HIP_CHECK(hipStreamSynchronize(st));
+    }
+  }
+
+  int nlev() const { return nlev_; }
+  int nseg() const { return (int)lev_[0]->host.size(); }
+  const LevelSet& level(int l) const { return *lev_[l]; }
+  int stencil() const { return stencil_; }
+
+  // Set the direction (H or H^H) of every segment on every level.
+  void set_dir(int dir) {
+    for (auto& L : lev_) {
+      bool changed = false;
+      for (auto& S : L->host)
+        if (S.dir != dir) { S.dir = dir; changed = true; }
+      if (changed) {
+        HELM_HIP_CHECK(hipMemcpyAsync(L->segs.p, L->host.data(), L->host.size() * sizeof(Seg),
+                                      hipMemcpyHostToDevice, st_));
+        HELM_HIP_CHECK(hipStreamSynchronize(st_));
+      }
+    }
+  }
+
+  // Coarse models from the (current contents of the) fine models.
+  template <typename TM>
+  void inject_models() {
+    for (int l = 1; l < nlev_; ++l) {
+      const LevelSet& F = *lev_[l - 1];
+      const LevelSet& C = *lev_[l];
+      hipLaunchKernelGGL((k_inject_model<TM>), dim3(C.ntblk), dim3(256), 0, st_, F.d(), C.d(),
+                         C.tmap.as<const int>(), C.own.as<const int>());
+    }
+    HELM_HIP_CHECK(hipGetLastError());
+  }
+
+  size_t max_partials() const {
+    size_t mx = 1;
+    for (const auto& L : lev_) {
+      mx = std::max<size_t>(mx, L->nsblk);
+      mx = std::max<size_t>(mx, L->nvblk);
+      if (stencil_ == 1) mx = std::max<size_t>(mx, L->ntblk);
+    }
+    return mx;
+  }
+
+  static void coarse_dims(const int n0[3], int l, int n[3]) {
+    for (int a = 0; a < 3; ++a) {
+      n[a] = n0[a];
+      for (int k = 0; k < l; ++k) n[a] = n[a] / 2 + 1;
+    }
+  }
+
+ private:
+  template <typename V>
+  void upload(DevBuf& buf, const std::vector<V>& v) {
+    buf.ensure(v.size() * sizeof(V));
+    HELM_HIP_CHECK(hipMemcpyAsync(buf.p, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice, st_));
+  }
+
+  int nlev_;
+  hipStream_t st_;
+  size_t model_bytes_;
+  int stencil_ = 0;
+  std::vector<std::unique_ptr<LevelSet>> lev_;
+  std::vector<std::unique_ptr<OpTables>> tables_;
+};
+
+// Which partial-sum range a stencil launch with NORM writes.
+inline int stencil_range(const LevelSet& L) { return L.stencil == 0 ? PR_STENCIL : PR_POINT; }
+
+// out = [s_b b -] s_x H x over all segments of level L.
+template <typename TC, typename TX, typename TM, typename TB, typename TO, bool RESID, bool NORM>
+void launch_h(const LevelSet& L, const cx<TX>* x, const double* xs, const cx<TB>* b, const double* bs,
+              cx<TO>* out, double* part, const int* active, hipStream_t st) {
+  if (L.stencil == 1)
+    hipLaunchKernelGGL((k_h27<TC, TX, TM, TB, TO, RESID, NORM>), dim3(L.ntblk), dim3(256), 0, st, L.d(),
+                       L.tmap.as<const int>(), x, xs, b, bs, out, part, active);
+  else
+    hipLaunchKernelGGL((k_h7<TC, TX, TM, TB, TO, RESID, NORM>), dim3(L.nsblk), dim3(256), 0, st, L.d(),
+                       L.smap.as<const int>(), x, xs, b, bs, out, part, active);
 }
 
 }  // namespace helm

@@ -17,15 +17,18 @@
 // different table.  The difference form keeps complex64 rounding relative to
 // the local variation of x instead of to |x| / h^2.
 //
-// Kernel shape: a workgroup owns a TZ x TY tile of the (z, y) plane and marches
-// along x over `xchunk` planes, holding x[i-1], x[i], x[i+1] of its own column
-// in registers; y and z neighbours come from the vector cache (they are the
-// neighbouring lanes' own loads).  z is the lane index, so every load and
-// store is a contiguous 64-lane access; the x-axis coefficients are
-// workgroup-uniform (scalar loads).
+// Launch shape: a workgroup of 256 lanes owns 256 consecutive points of the
+// flattened (y, z) plane (so a ragged nz wastes no lanes) and marches along
+// x over `xchunk` planes.  x[i-1], x[i], x[i+1] of its own column sit in
+// registers and x[i+2] is already in flight while plane i is computed; the
+// y and z neighbours are the neighbouring lanes' own loads and come from the
+// vector cache.  Every access is a contiguous 64-lane run; workgroups are
+// renumbered so that one XCD runs a contiguous range of tiles (shared halos
+// stay in one L2).
 #pragma once
 
 #include "common.h"
+#include "segment.h"
 
 namespace helm {
 
@@ -36,12 +39,30 @@ struct Tab7 {
   const cx<T>* de[3];
 };
 
-// 27-point interior description (compact stencil away from the layer).
-struct Int27 {
-  int lo[3], hi[3];  // rows i with lo <= i <= hi on every axis are interior
-  double lw[4];      // Laplacian weights: centre, face, edge, corner
-  double mw[4];      // mass weights: centre, face, edge, corner
-};
+template <typename TC>
+__device__ __forceinline__ Tab7<TC> seg_tables(const Seg& S);
+template <>
+__device__ __forceinline__ Tab7<float> seg_tables<float>(const Seg& S) {
+  Tab7<float> t;
+  const cx<float>* base = reinterpret_cast<const cx<float>*>(S.tabf) + (int64_t)S.dir * S.tdir;
+  for (int a = 0; a < 3; ++a) {
+    t.al[a] = base + S.tpre[a];
+    t.be[a] = base + S.tpre[a] + S.n[a];
+    t.de[a] = base + S.tpre[a] + 2 * S.n[a];
+  }
+  return t;
+}
+template <>
+__device__ __forceinline__ Tab7<double> seg_tables<double>(const Seg& S) {
+  Tab7<double> t;
+  const cx<double>* base = reinterpret_cast<const cx<double>*>(S.tabd) + (int64_t)S.dir * S.tdir;
+  for (int a = 0; a < 3; ++a) {
+    t.al[a] = base + S.tpre[a];
+    t.be[a] = base + S.tpre[a] + S.n[a];
+    t.de[a] = base + S.tpre[a] + 2 * S.n[a];
+  }
+  return t;
+}
 
 template <typename TX, typename TC>
 __device__ __forceinline__ cx<TC> ld(const cx<TX>* p) {
@@ -50,60 +71,71 @@ __device__ __forceinline__ cx<TC> ld(const cx<TX>* p) {
 
 // out = s_x * H x            (RESID = false)
 // out = s_b * b - s_x * H x  (RESID = true)
-// optional per-workgroup partial sum of |out|^2 (in TC precision -> double)
-// written to part[(r * nblk + blk) * PSTRIDE].
-template <typename TC, typename TX, typename TM, typename TB, typename TO,
-          bool RESID, bool NORM, int TZ, int TY>
-__global__ __launch_bounds__(TZ* TY) void k_h7(
-    const cx<TX>* __restrict__ x, const double* __restrict__ xs,
-    const TM* __restrict__ m, TC w2, Tab7<TC> tab,
-    const cx<TB>* __restrict__ b, const double* __restrict__ bs,
-    cx<TO>* __restrict__ out, double* __restrict__ part,
-    const int* __restrict__ active, int nx, int ny, int nz, int xchunk,
-    int nxc) {
+// s_x, s_b: per-segment scales (null = 1).  With NORM, the workgroup's sum of
+// |out|^2 (FP64) goes to part[wg * PSTRIDE].
+template <typename TC, typename TX, typename TM, typename TB, typename TO, bool RESID, bool NORM>
+__global__ __launch_bounds__(256) void k_h7(const Seg* __restrict__ segs, const int* __restrict__ smap,
+                                            const cx<TX>* __restrict__ x, const double* __restrict__ xs,
+                                            const cx<TB>* __restrict__ b, const double* __restrict__ bs,
+                                            cx<TO>* __restrict__ out, double* __restrict__ part,
+                                            const int* __restrict__ active) {
   __shared__ double red[16];
-  const int k = blockIdx.x * TZ + threadIdx.x;
-  const int j = blockIdx.y * TY + threadIdx.y;
-  const int xc = blockIdx.z % nxc;
-  const int r = blockIdx.z / nxc;
-  const int nblk = gridDim.x * gridDim.y * nxc;
-  const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * xc);
-  if (active && !active[r]) {
-    if (NORM && threadIdx.x == 0 && threadIdx.y == 0) part[((int64_t)r * nblk + blk) * PSTRIDE] = 0.0;
+  const int wg = xcd_logical(blockIdx.x, gridDim.x);
+  const int sid = smap[wg];
+  const Seg& S = segs[sid];
+  if (active && !active[sid]) {
+    if (NORM && threadIdx.x == 0) part[(int64_t)wg * PSTRIDE] = 0.0;
     return;  // uniform across the workgroup
   }
-  const bool in = (k < nz) && (j < ny);
-  const int64_t N = (int64_t)nx * ny * nz;
+  const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
+  const int local = wg - S.sblk0;
+  const int xc = local / S.plane_blocks;
+  const int pb = local - xc * S.plane_blocks;
+  const int idx = pb * 256 + threadIdx.x;
   const int64_t plane = (int64_t)ny * nz;
-  const cx<TX>* xr = x + r * N;
-  const TC sx = xs ? (TC)xs[r] : TC(1);
-  const int i0 = xc * xchunk;
-  const int i1 = min(nx, i0 + xchunk);
+  const bool in = idx < plane;
+  const int j = in ? idx / nz : 0;
+  const int k = in ? idx - j * nz : 0;
+  const Tab7<TC> tab = seg_tables<TC>(S);
+  const TC w2 = (TC)S.w2;
+  const TM* __restrict__ m = reinterpret_cast<const TM*>(S.m);
+  const cx<TX>* __restrict__ xr = x + S.off;
+  const TC sx = xs ? (TC)xs[sid] : TC(1);
+  TC sb = TC(1);
+  if (RESID) sb = bs ? (TC)bs[sid] : TC(1);
+  const int i0 = xc * S.xchunk;
+  const int i1 = min(nx, i0 + S.xchunk);
   cx<TC> az = czero<TC>(), bz = az, dz = az, ay = az, by = az, dy = az;
   if (in) {
     az = tab.al[2][k]; bz = tab.be[2][k]; dz = tab.de[2][k];
     ay = tab.al[1][j]; by = tab.be[1][j]; dy = tab.de[1][j];
   }
-  int64_t p = (int64_t)i0 * plane + (int64_t)j * nz + k;
-  cx<TC> xm = czero<TC>(), xcur = czero<TC>();
+  const bool has_ym = in && j > 0, has_yp = in && j + 1 < ny;
+  const bool has_zm = in && k > 0, has_zp = in && k + 1 < nz;
+  int64_t p = (int64_t)i0 * plane + idx;
+  cx<TC> xm = czero<TC>(), xcur = czero<TC>(), xp = czero<TC>();
   if (in) {
     if (i0 > 0) xm = ld<TX, TC>(xr + p - plane);
     xcur = ld<TX, TC>(xr + p);
+    if (i0 + 1 < nx) xp = ld<TX, TC>(xr + p + plane);
   }
   double nrm = 0.0;
-  TC sb = TC(1);
-  if (RESID) sb = bs ? (TC)bs[r] : TC(1);
   for (int i = i0; i < i1; ++i, p += plane) {
-    cx<TC> xp = czero<TC>();
-    if (in && i + 1 < nx) xp = ld<TX, TC>(xr + p + plane);
+    cx<TC> ym = czero<TC>(), yp = ym, zm = ym, zp = ym;
+    TC mv = TC(0);
     if (in) {
-      const cx<TC> ym = j > 0 ? ld<TX, TC>(xr + p - nz) : czero<TC>();
-      const cx<TC> yp = j + 1 < ny ? ld<TX, TC>(xr + p + nz) : czero<TC>();
-      const cx<TC> zm = k > 0 ? ld<TX, TC>(xr + p - 1) : czero<TC>();
-      const cx<TC> zp = k + 1 < nz ? ld<TX, TC>(xr + p + 1) : czero<TC>();
+      if (has_ym) ym = ld<TX, TC>(xr + p - nz);
+      if (has_yp) yp = ld<TX, TC>(xr + p + nz);
+      if (has_zm) zm = ld<TX, TC>(xr + p - 1);
+      if (has_zp) zp = ld<TX, TC>(xr + p + 1);
+      mv = (TC)m[p];
+    }
+    // plane i+2 goes in flight while plane i is computed
+    cx<TC> xpp = czero<TC>();
+    if (in && i + 2 < nx) xpp = ld<TX, TC>(xr + p + 2 * plane);
+    if (in) {
       const cx<TC> ax = tab.al[0][i], bx = tab.be[0][i], dx = tab.de[0][i];
-      const TC wm = w2 * (TC)m[p];
-      cx<TC> acc = mk<TC>(wm + dx.re + dy.re + dz.re, dx.im + dy.im + dz.im) * xcur;
+      cx<TC> acc = mk<TC>(w2 * mv + dx.re + dy.re + dz.re, dx.im + dy.im + dz.im) * xcur;
       acc = cfma(ax, xp - xcur, acc);
       acc = cfma(bx, xm - xcur, acc);
       acc = cfma(ay, yp - xcur, acc);
@@ -111,16 +143,17 @@ __global__ __launch_bounds__(TZ* TY) void k_h7(
       acc = cfma(az, zp - xcur, acc);
       acc = cfma(bz, zm - xcur, acc);
       acc = sx * acc;
-      if (RESID) acc = sb * ld<TB, TC>(b + r * N + p) - acc;
-      out[r * N + p] = cast<TO>(acc);
+      if (RESID) acc = sb * ld<TB, TC>(b + S.off + p) - acc;
+      out[S.off + p] = cast<TO>(acc);
       if (NORM) nrm += (double)acc.re * (double)acc.re + (double)acc.im * (double)acc.im;
     }
     xm = xcur;
     xcur = xp;
+    xp = xpp;
   }
   if (NORM) {
     const double s = block_sum(nrm, red);
-    if (threadIdx.x == 0 && threadIdx.y == 0) part[((int64_t)r * nblk + blk) * PSTRIDE] = s;
+    if (threadIdx.x == 0) part[(int64_t)wg * PSTRIDE] = s;
   }
 }
 
@@ -130,37 +163,42 @@ __global__ __launch_bounds__(TZ* TY) void k_h7(
 // class weight; layer rows: the 7-point stretched row from the tables.  Mass
 // term on every row: omega^2 sum_d wm(class d) m_{p+d} x_{p+d}.
 // Adjoint: L27 (mask . x) + L7^H ((1 - mask) . x) + omega^2 m_p (A x)_p.
+// Point-wise workgroups (tmap / tblk0).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool interior27(const Int27& in27, int i, int j, int k) {
   return i >= in27.lo[0] && i <= in27.hi[0] && j >= in27.lo[1] && j <= in27.hi[1] &&
          k >= in27.lo[2] && k <= in27.hi[2];
 }
 
-template <typename TC, typename TX, typename TM, typename TB, typename TO,
-          bool ADJ, bool RESID, bool NORM>
-__global__ __launch_bounds__(256) void k_h27(
-    const cx<TX>* __restrict__ x, const double* __restrict__ xs,
-    const TM* __restrict__ m, TC w2, Tab7<TC> tab, Int27 in27,
-    const cx<TB>* __restrict__ b, const double* __restrict__ bs,
-    cx<TO>* __restrict__ out, double* __restrict__ part,
-    const int* __restrict__ active, int nx, int ny, int nz) {
+template <typename TC, typename TX, typename TM, typename TB, typename TO, bool RESID, bool NORM>
+__global__ __launch_bounds__(256) void k_h27(const Seg* __restrict__ segs, const int* __restrict__ tmap,
+                                             const cx<TX>* __restrict__ x, const double* __restrict__ xs,
+                                             const cx<TB>* __restrict__ b, const double* __restrict__ bs,
+                                             cx<TO>* __restrict__ out, double* __restrict__ part,
+                                             const int* __restrict__ active) {
   __shared__ double red[16];
-  const int r = blockIdx.y;
-  const int nblk = gridDim.x;
-  const int64_t N = (int64_t)nx * ny * nz;
-  if (active && !active[r]) {
-    if (NORM && threadIdx.x == 0) part[((int64_t)r * nblk + blockIdx.x) * PSTRIDE] = 0.0;
+  const int wg = xcd_logical(blockIdx.x, gridDim.x);
+  const int sid = tmap[wg];
+  const Seg& S = segs[sid];
+  if (active && !active[sid]) {
+    if (NORM && threadIdx.x == 0) part[(int64_t)wg * PSTRIDE] = 0.0;
     return;
   }
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const bool in = p < N;
+  const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
+  const int64_t N = S.N;
+  const int64_t p = (int64_t)(wg - S.tblk0) * 256 + threadIdx.x;
+  const bool adj = S.dir != 0;
   double nrm = 0.0;
-  if (in) {
+  if (p < N) {
+    const Tab7<TC> tab = seg_tables<TC>(S);
+    const TC w2 = (TC)S.w2;
+    const TM* __restrict__ m = reinterpret_cast<const TM*>(S.m);
     const int k = (int)(p % nz);
     const int j = (int)((p / nz) % ny);
     const int i = (int)(p / ((int64_t)ny * nz));
-    const cx<TX>* xr = x + r * N;
-    const TC sx = xs ? (TC)xs[r] : TC(1);
+    const cx<TX>* xr = x + S.off;
+    const TC sx = xs ? (TC)xs[sid] : TC(1);
+    const Int27& in27 = S.in27;
     const TC lw[4] = {(TC)in27.lw[0], (TC)in27.lw[1], (TC)in27.lw[2], (TC)in27.lw[3]};
     const TC mw[4] = {(TC)in27.mw[0], (TC)in27.mw[1], (TC)in27.mw[2], (TC)in27.mw[3]};
     cx<TC> lap = czero<TC>(), mass = czero<TC>();
@@ -181,7 +219,7 @@ __global__ __launch_bounds__(256) void k_h27(
           const int cls = (di != 0) + (dj != 0) + (dk != 0);
           const int64_t q = p + (int64_t)di * ny * nz + (int64_t)dj * nz + dk;
           const cx<TC> xq = (cls == 0) ? xcur : ld<TX, TC>(xr + q);
-          if (!ADJ) {
+          if (!adj) {
             if (own_int) lap = cfma(mk<TC>(lw[cls], 0), xq, lap);
             mass = cfma(mk<TC>(mw[cls] * (TC)m[q], 0), xq, mass);
           } else {
@@ -196,7 +234,7 @@ __global__ __launch_bounds__(256) void k_h27(
         }
       }
     }
-    if (!ADJ) {
+    if (!adj) {
       if (!own_int) {
         const cx<TC> xmx = i > 0 ? ld<TX, TC>(xr + p - (int64_t)ny * nz) : czero<TC>();
         const cx<TC> xpx = i + 1 < nx ? ld<TX, TC>(xr + p + (int64_t)ny * nz) : czero<TC>();
@@ -204,7 +242,7 @@ __global__ __launch_bounds__(256) void k_h27(
         const cx<TC> xpy = j + 1 < ny ? ld<TX, TC>(xr + p + nz) : czero<TC>();
         const cx<TC> xmz = k > 0 ? ld<TX, TC>(xr + p - 1) : czero<TC>();
         const cx<TC> xpz = k + 1 < nz ? ld<TX, TC>(xr + p + 1) : czero<TC>();
-        cx<TC> d = tab.de[0][i] + tab.de[1][j] + tab.de[2][k];
+        const cx<TC> d = tab.de[0][i] + tab.de[1][j] + tab.de[2][k];
         lap = d * xcur;
         lap = cfma(tab.al[0][i], xpx - xcur, lap);
         lap = cfma(tab.be[0][i], xmx - xcur, lap);
@@ -228,15 +266,15 @@ __global__ __launch_bounds__(256) void k_h27(
     }
     cx<TC> acc = sx * lap;
     if (RESID) {
-      const TC sb = bs ? (TC)bs[r] : TC(1);
-      acc = sb * ld<TB, TC>(b + r * N + p) - acc;
+      const TC sb = bs ? (TC)bs[sid] : TC(1);
+      acc = sb * ld<TB, TC>(b + S.off + p) - acc;
     }
-    out[r * N + p] = cast<TO>(acc);
+    out[S.off + p] = cast<TO>(acc);
     if (NORM) nrm = (double)acc.re * (double)acc.re + (double)acc.im * (double)acc.im;
   }
   if (NORM) {
     const double s = block_sum(nrm, red);
-    if (threadIdx.x == 0) part[((int64_t)r * nblk + blockIdx.x) * PSTRIDE] = s;
+    if (threadIdx.x == 0) part[(int64_t)wg * PSTRIDE] = s;
   }
 }
 

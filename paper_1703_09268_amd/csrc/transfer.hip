@@ -8,28 +8,35 @@
 // product, i.e. full weighting
 //   (R r)_I = (1/8) sum_{d in {-1,0,1}^3} prod_a (1 - |d_a|/2) r_{2I+d}.
 // The coarse model is injected: m_c(I) = m_f(min(2I, n_f - 1)).
+// All kernels are point-wise over the segments of one level (tmap of the
+// level whose points the lanes own); fine and coarse descriptors of a
+// segment share its index.
 #pragma once
 
 #include "common.h"
+#include "segment.h"
 
 namespace helm {
 
-// rc = R (s_r * rf)  with per-rhs scale s_r (may be null)
+// rc = R (s_r * rf); lanes own coarse points
 template <typename T>
-__global__ __launch_bounds__(256) void k_restrict(const cx<T>* __restrict__ rf, const double* __restrict__ rs,
-                                                  int nfx, int nfy, int nfz, cx<T>* __restrict__ rc,
-                                                  int ncx, int ncy, int ncz,
+__global__ __launch_bounds__(256) void k_restrict(const Seg* __restrict__ fsegs, const Seg* __restrict__ csegs,
+                                                  const int* __restrict__ ctmap, const cx<T>* __restrict__ rf,
+                                                  const double* __restrict__ rs, cx<T>* __restrict__ rc,
                                                   const int* __restrict__ active) {
-  const int r = blockIdx.y;
-  if (active && !active[r]) return;
-  const int64_t Nc = (int64_t)ncx * ncy * ncz;
-  const int64_t Nf = (int64_t)nfx * nfy * nfz;
-  const int64_t pc = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (pc >= Nc) return;
+  const int wg = blockIdx.x;
+  const int sid = ctmap[wg];
+  if (active && !active[sid]) return;
+  const Seg& C = csegs[sid];
+  const Seg& F = fsegs[sid];
+  const int64_t pc = (int64_t)(wg - C.tblk0) * 256 + threadIdx.x;
+  if (pc >= C.N) return;
+  const int ncy = C.n[1], ncz = C.n[2];
+  const int nfx = F.n[0], nfy = F.n[1], nfz = F.n[2];
   const int K = (int)(pc % ncz);
   const int J = (int)((pc / ncz) % ncy);
   const int I = (int)(pc / ((int64_t)ncy * ncz));
-  const cx<T>* f = rf + r * Nf;
+  const cx<T>* f = rf + F.off;
   cx<T> acc = czero<T>();
   for (int di = -1; di <= 1; ++di) {
     const int i = 2 * I + di;
@@ -47,34 +54,36 @@ __global__ __launch_bounds__(256) void k_restrict(const cx<T>* __restrict__ rf, 
       }
     }
   }
-  const T s = rs ? (T)rs[r] : T(1);
-  rc[r * Nc + pc] = (s * T(0.125)) * acc;
+  const T s = rs ? (T)rs[sid] : T(1);
+  rc[C.off + pc] = (s * T(0.125)) * acc;
 }
 
-// xf += P xc
+// xf += P xc; lanes own fine points
 template <typename T>
-__global__ __launch_bounds__(256) void k_prolong_add(const cx<T>* __restrict__ xc, int ncx, int ncy,
-                                                     int ncz, cx<T>* __restrict__ xf, int nfx, int nfy,
-                                                     int nfz, const int* __restrict__ active) {
-  const int r = blockIdx.y;
-  if (active && !active[r]) return;
-  const int64_t Nc = (int64_t)ncx * ncy * ncz;
-  const int64_t Nf = (int64_t)nfx * nfy * nfz;
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (p >= Nf) return;
+__global__ __launch_bounds__(256) void k_prolong_add(const Seg* __restrict__ fsegs, const Seg* __restrict__ csegs,
+                                                     const int* __restrict__ ftmap, const cx<T>* __restrict__ xc,
+                                                     cx<T>* __restrict__ xf, const int* __restrict__ active) {
+  const int wg = blockIdx.x;
+  const int sid = ftmap[wg];
+  if (active && !active[sid]) return;
+  const Seg& F = fsegs[sid];
+  const Seg& C = csegs[sid];
+  const int64_t p = (int64_t)(wg - F.tblk0) * 256 + threadIdx.x;
+  if (p >= F.N) return;
+  const int nfy = F.n[1], nfz = F.n[2];
+  const int ncy = C.n[1], ncz = C.n[2];
   const int k = (int)(p % nfz);
   const int j = (int)((p / nfz) % nfy);
   const int i = (int)(p / ((int64_t)nfy * nfz));
-  // 1D stencils: (index, weight) pairs, second entry weight 0 for even nodes
+  // even node: one coarse node (weight 1); odd node: two (weight 1/2 each)
   const int i0 = i >> 1, i1 = (i + 1) >> 1;
   const int j0 = j >> 1, j1 = (j + 1) >> 1;
   const int k0 = k >> 1, k1 = (k + 1) >> 1;
   const T wi = (i & 1) ? T(0.5) : T(1), wj = (j & 1) ? T(0.5) : T(1), wk = (k & 1) ? T(0.5) : T(1);
-  const cx<T>* c = xc + r * Nc;
+  const cx<T>* c = xc + C.off;
   auto at = [&](int a, int b, int d) { return c[((int64_t)a * ncy + b) * ncz + d]; };
-  cx<T> acc = at(i0, j0, k0);
-  if (k & 1) acc = acc + at(i0, j0, k1);
-  cx<T> s2 = acc;
+  cx<T> s2 = at(i0, j0, k0);
+  if (k & 1) s2 = s2 + at(i0, j0, k1);
   if (j & 1) {
     cx<T> t = at(i0, j1, k0);
     if (k & 1) t = t + at(i0, j1, k1);
@@ -91,20 +100,30 @@ __global__ __launch_bounds__(256) void k_prolong_add(const cx<T>* __restrict__ x
     }
     s3 = s3 + t;
   }
-  xf[r * Nf + p] = xf[r * Nf + p] + (wi * wj * wk) * s3;
+  xf[F.off + p] = xf[F.off + p] + (wi * wj * wk) * s3;
 }
 
+// coarse model by injection, one lane per coarse point of the segments that
+// own their model buffer (own[sid] != 0)
 template <typename TM>
-__global__ __launch_bounds__(256) void k_inject_model(const TM* __restrict__ mf, int nfx, int nfy, int nfz,
-                                                      TM* __restrict__ mc, int ncx, int ncy, int ncz) {
-  const int64_t Nc = (int64_t)ncx * ncy * ncz;
-  const int64_t pc = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (pc >= Nc) return;
+__global__ __launch_bounds__(256) void k_inject_model(const Seg* __restrict__ fsegs, const Seg* __restrict__ csegs,
+                                                      const int* __restrict__ ctmap,
+                                                      const int* __restrict__ own) {
+  const int wg = blockIdx.x;
+  const int sid = ctmap[wg];
+  if (!own[sid]) return;
+  const Seg& C = csegs[sid];
+  const Seg& F = fsegs[sid];
+  const int64_t pc = (int64_t)(wg - C.tblk0) * 256 + threadIdx.x;
+  if (pc >= C.N) return;
+  const int ncy = C.n[1], ncz = C.n[2];
   const int K = (int)(pc % ncz);
   const int J = (int)((pc / ncz) % ncy);
   const int I = (int)(pc / ((int64_t)ncy * ncz));
-  const int i = min(2 * I, nfx - 1), j = min(2 * J, nfy - 1), k = min(2 * K, nfz - 1);
-  mc[pc] = mf[((int64_t)i * nfy + j) * nfz + k];
+  const int i = min(2 * I, F.n[0] - 1), j = min(2 * J, F.n[1] - 1), k = min(2 * K, F.n[2] - 1);
+  const TM* mf = reinterpret_cast<const TM*>(F.m);
+  TM* mc = reinterpret_cast<TM*>(const_cast<void*>(C.m));
+  mc[pc] = mf[((int64_t)i * F.n[1] + j) * F.n[2] + k];
 }
 
 }  // namespace helm
