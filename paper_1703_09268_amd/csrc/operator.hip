@@ -167,7 +167,7 @@ inline std::unique_ptr<OpTables> build_tables(const GridSpec& g, double omega, c
 struct LevelSet {
   int stencil = 0;
   std::vector<Seg> host;
-  DevBuf segs, smap, vmap, tmap, own;
+  DevBuf segs, smap, slocal, vmap, tmap, own;
   int nsblk = 0, nvblk = 0, ntblk = 0;
   int64_t total = 0;  // vector length (sum of N)
   std::vector<std::unique_ptr<DevBuf>> models;  // owned coarse models
@@ -300,14 +300,28 @@ class Hierarchy {
       L.nsblk = sb;
       L.nvblk = vb;
       L.ntblk = tb;
-      std::vector<int> smap(std::max(sb, 1)), vmap(std::max(vb, 1)), tmap(std::max(tb, 1));
+      std::vector<int> smap(std::max(sb, 1)), slocal(std::max(sb, 1)), vmap(std::max(vb, 1)),
+          tmap(std::max(tb, 1));
+      // Stencil workgroups: when every segment of the level has the same
+      // geometry and model (the sources of one frequency), the segments of
+      // one tile get consecutive workgroup ids (segment fastest), so they run
+      // together on one XCD and read that tile of the model once into its L2.
+      bool shared = stencil_ == 0 && ns > 1;
+      for (int s = 1; s < ns && shared; ++s)
+        shared = L.host[s].m == L.host[0].m && L.host[s].n[0] == L.host[0].n[0] &&
+                 L.host[s].n[1] == L.host[0].n[1] && L.host[s].n[2] == L.host[0].n[2];
       for (int s = 0; s < ns; ++s) {
         const Seg& S = L.host[s];
-        for (int b = 0; b < S.snblk; ++b) smap[S.sblk0 + b] = s;
+        for (int b = 0; b < S.snblk; ++b) {
+          const int wg = shared ? b * ns + s : S.sblk0 + b;
+          smap[wg] = s;
+          slocal[wg] = b;
+        }
         for (int b = 0; b < S.vnblk; ++b) vmap[S.vblk0 + b] = s;
         for (int b = 0; b < S.tnblk; ++b) tmap[S.tblk0 + b] = s;
       }
       upload(L.smap, smap);
+      upload(L.slocal, slocal);
       upload(L.vmap, vmap);
       upload(L.tmap, tmap);
       upload(L.own, own);
@@ -392,7 +406,7 @@ void launch_h(const LevelSet& L, const cx<TX>* x, const double* xs, const cx<TB>
                        L.tmap.as<const int>(), x, xs, b, bs, out, part, active);
   else
     hipLaunchKernelGGL((k_h7<TC, TX, TM, TB, TO, RESID, NORM>), dim3(L.nsblk), dim3(256), 0, st, L.d(),
-                       L.smap.as<const int>(), x, xs, b, bs, out, part, active);
+                       L.smap.as<const int>(), L.slocal.as<const int>(), x, xs, b, bs, out, part, active);
 }
 
 }  // namespace helm

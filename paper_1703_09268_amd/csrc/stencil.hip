@@ -19,7 +19,8 @@
 //
 // Launch shape: a workgroup of 256 lanes owns 256 consecutive points of the
 // flattened (y, z) plane (so a ragged nz wastes no lanes) and marches along
-// x over `xchunk` planes.  x[i-1], x[i], x[i+1] of its own column sit in
+// x over `xchunk` planes; smap / slocal give its segment and its tile index
+// inside the segment.  x[i-1], x[i], x[i+1] of its own column sit in
 // registers and x[i+2] is already in flight while plane i is computed; the
 // y and z neighbours are the neighbouring lanes' own loads and come from the
 // vector cache.  Every access is a contiguous 64-lane run; workgroups are
@@ -72,9 +73,10 @@ __device__ __forceinline__ cx<TC> ld(const cx<TX>* p) {
 // out = s_x * H x            (RESID = false)
 // out = s_b * b - s_x * H x  (RESID = true)
 // s_x, s_b: per-segment scales (null = 1).  With NORM, the workgroup's sum of
-// |out|^2 (FP64) goes to part[wg * PSTRIDE].
+// |out|^2 (FP64) goes to part[(sblk0 + local) * PSTRIDE].
 template <typename TC, typename TX, typename TM, typename TB, typename TO, bool RESID, bool NORM>
 __global__ __launch_bounds__(256) void k_h7(const Seg* __restrict__ segs, const int* __restrict__ smap,
+                                            const int* __restrict__ slocal,
                                             const cx<TX>* __restrict__ x, const double* __restrict__ xs,
                                             const cx<TB>* __restrict__ b, const double* __restrict__ bs,
                                             cx<TO>* __restrict__ out, double* __restrict__ part,
@@ -82,13 +84,15 @@ __global__ __launch_bounds__(256) void k_h7(const Seg* __restrict__ segs, const 
   __shared__ double red[16];
   const int wg = xcd_logical(blockIdx.x, gridDim.x);
   const int sid = smap[wg];
+  const int local = slocal[wg];
   const Seg& S = segs[sid];
+  // partial sums go to the segment's own range, whatever the launch order
+  double* const pslot = NORM ? part + (int64_t)(S.sblk0 + local) * PSTRIDE : nullptr;
   if (active && !active[sid]) {
-    if (NORM && threadIdx.x == 0) part[(int64_t)wg * PSTRIDE] = 0.0;
+    if (NORM && threadIdx.x == 0) *pslot = 0.0;
     return;  // uniform across the workgroup
   }
   const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
-  const int local = wg - S.sblk0;
   const int xc = local / S.plane_blocks;
   const int pb = local - xc * S.plane_blocks;
   const int idx = pb * 256 + threadIdx.x;
@@ -153,7 +157,7 @@ __global__ __launch_bounds__(256) void k_h7(const Seg* __restrict__ segs, const 
   }
   if (NORM) {
     const double s = block_sum(nrm, red);
-    if (threadIdx.x == 0) part[(int64_t)wg * PSTRIDE] = s;
+    if (threadIdx.x == 0) *pslot = s;
   }
 }
 
