@@ -54,17 +54,48 @@ __device__ __forceinline__ void seg_range(const Seg& S, int which, int& b0, int&
 
 __device__ __forceinline__ double2 d2(double a, double b) { return make_double2(a, b); }
 
-// sum of part[(b0+b)*PSTRIDE + c] over the segment's workgroups (64 lanes)
-__device__ __forceinline__ double seg_sum(const double* part, int b0, int nb, int c) {
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nb; b += 64) s += part[(int64_t)(b0 + b) * PSTRIDE + c];
-  return wave_sum(s);
+// Column sums s[c] = sum_b part[(b0+b)*PSTRIDE + c], c < NC (c < nc unless
+// EXACT), over the segment's workgroups, by one 256-lane workgroup.  Every
+// lane issues the loads of all its rows and columns before adding, so the
+// reduction costs one memory round trip; lanes add their rows in increasing
+// order and the four wave totals are added in a fixed order (deterministic).
+// The result is valid in every lane.  `red` holds 4*NC doubles of LDS.
+template <int NC, bool EXACT>
+__device__ __forceinline__ void seg_sums(const double* __restrict__ part, int b0, int nb, int nc,
+                                         double (&s)[NC], double* red) {
+#pragma unroll
+  for (int c = 0; c < NC; ++c) s[c] = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) {
+    const double* row = part + (int64_t)(b0 + b) * PSTRIDE;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      if (EXACT || c < nc) s[c] += row[c];
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const double v = wave_sum(s[c]);
+    if (lane == 0) red[wid * NC + c] = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < NC; ++c) s[c] = red[c] + red[NC + c] + red[2 * NC + c] + red[3 * NC + c];
+}
+
+// single column 0
+__device__ __forceinline__ double seg_sum0(const double* __restrict__ part, int b0, int nb, double* red) {
+  double s[1];
+  seg_sums<1, true>(part, b0, nb, 1, s, red);
+  return s[0];
 }
 
 // ---------------------------------------------------------------------------
 // partial inner products  s_i = sum_p conj(V_i[p]) w[p],  i < nv
 // ---------------------------------------------------------------------------
-template <typename T, int NVMAX>
+// NV = NVMAX exactly when EXACT (no per-vector guards, so every load of an
+// element is in flight at once); otherwise nv <= NVMAX.  Each lane visits
+// its elements in increasing order two at a time.
+template <typename T, int NVMAX, bool EXACT>
 __global__ __launch_bounds__(256) void k_dots(const Seg* __restrict__ segs, const int* __restrict__ vmap,
                                              VecList<T> V, int nv, const cx<T>* __restrict__ w,
                                              double* __restrict__ part, const int* __restrict__ active) {
@@ -73,8 +104,9 @@ __global__ __launch_bounds__(256) void k_dots(const Seg* __restrict__ segs, cons
   const int sid = vmap[wg];
   const Seg& S = segs[sid];
   double* out = part + (int64_t)wg * PSTRIDE;
+  if (EXACT) nv = NVMAX;
   if (active && !active[sid]) {
-    if (threadIdx.x < 2 * NVMAX) out[threadIdx.x] = 0.0;
+    if (threadIdx.x < 2 * nv) out[threadIdx.x] = 0.0;
     return;
   }
   double ar[NVMAX], ai[NVMAX];
@@ -82,21 +114,43 @@ __global__ __launch_bounds__(256) void k_dots(const Seg* __restrict__ segs, cons
   for (int i = 0; i < NVMAX; ++i) ar[i] = ai[i] = 0.0;
   const int64_t N = S.N, off = S.off;
   const int64_t stride = (int64_t)S.vnblk * 256;
-  for (int64_t p = (int64_t)(wg - S.vblk0) * 256 + threadIdx.x; p < N; p += stride) {
-    const cx<T> wv = w[off + p];
+  auto acc = [&](const cx<T>& wv, const cx<T>* a) {
 #pragma unroll
     for (int i = 0; i < NVMAX; ++i) {
-      if (i < nv) {
-        const cx<T> a = V.v[i][off + p];
-        ar[i] += (double)a.re * (double)wv.re + (double)a.im * (double)wv.im;
-        ai[i] += (double)a.re * (double)wv.im - (double)a.im * (double)wv.re;
+      if (EXACT || i < nv) {
+        ar[i] += (double)a[i].re * (double)wv.re + (double)a[i].im * (double)wv.im;
+        ai[i] += (double)a[i].re * (double)wv.im - (double)a[i].im * (double)wv.re;
       }
     }
+  };
+  int64_t p = (int64_t)(wg - S.vblk0) * 256 + threadIdx.x;
+  if (EXACT) {  // two elements per iteration: twice the loads in flight
+    for (; p + stride < N; p += 2 * stride) {
+      const cx<T> w0 = w[off + p], w1 = w[off + p + stride];
+      cx<T> a0[NVMAX], a1[NVMAX];
+#pragma unroll
+      for (int i = 0; i < NVMAX; ++i) {
+        if (EXACT || i < nv) {
+          a0[i] = V.v[i][off + p];
+          a1[i] = V.v[i][off + p + stride];
+        }
+      }
+      acc(w0, a0);
+      acc(w1, a1);
+    }
+  }
+  for (; p < N; p += stride) {
+    const cx<T> w0 = w[off + p];
+    cx<T> a0[NVMAX];
+#pragma unroll
+    for (int i = 0; i < NVMAX; ++i)
+      if (EXACT || i < nv) a0[i] = V.v[i][off + p];
+    acc(w0, a0);
   }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int i = 0; i < NVMAX; ++i) {
-    if (i < nv) {
+    if (EXACT || i < nv) {
       const double sr = wave_sum(ar[i]);
       const double si = wave_sum(ai[i]);
       if (lane == 0) {
@@ -110,28 +164,34 @@ __global__ __launch_bounds__(256) void k_dots(const Seg* __restrict__ segs, cons
     out[threadIdx.x] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
 }
 
-// One 64-lane workgroup per segment: H[i][j] = scale_i * sum of partials,
+// One workgroup per segment: H[i][j] = scale_i * sum of partials,
 // coef_i = H[i][j] * scale_i.
-__global__ __launch_bounds__(64) void k_reduce_dots(const Seg* __restrict__ segs, KState st, int nv, int j,
-                                                    const int* __restrict__ active) {
+template <int NVMAX, bool EXACT>
+__global__ __launch_bounds__(256) void k_reduce_dots(const Seg* __restrict__ segs, KState st, int nv, int j,
+                                                     const int* __restrict__ active) {
+  __shared__ double red[4 * 2 * NVMAX];
   const int sid = blockIdx.x;
   if (active && !active[sid]) return;
   const Seg& S = segs[sid];
   const int ns = st.nseg;
-  for (int i = 0; i < nv; ++i) {
-    const double sr = seg_sum(st.part, S.vblk0, S.vnblk, 2 * i);
-    const double si = seg_sum(st.part, S.vblk0, S.vnblk, 2 * i + 1);
-    if (threadIdx.x == 0) {
-      const double s = st.scale[i * ns + sid];
-      const double2 h = d2(s * sr, s * si);
-      st.H[(i * KMAX + j) * ns + sid] = h;
-      st.coef[i * ns + sid] = d2(h.x * s, h.y * s);
+  if (EXACT) nv = NVMAX;
+  double s[2 * NVMAX];
+  seg_sums<2 * NVMAX, EXACT>(st.part, S.vblk0, S.vnblk, 2 * nv, s, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NVMAX; ++i) {
+      if (EXACT || i < nv) {
+        const double sc = st.scale[i * ns + sid];
+        const double2 h = d2(sc * s[2 * i], sc * s[2 * i + 1]);
+        st.H[(i * KMAX + j) * ns + sid] = h;
+        st.coef[i * ns + sid] = d2(h.x * sc, h.y * sc);
+      }
     }
   }
 }
 
 // w <- w - sum_i coef_i V_i  (in place), partial ||w||^2 per workgroup.
-template <typename T, int NVMAX>
+template <typename T, int NVMAX, bool EXACT>
 __global__ __launch_bounds__(256) void k_axpy_norm(const Seg* __restrict__ segs, const int* __restrict__ vmap,
                                                   VecList<T> V, int nv, cx<T>* __restrict__ w, KState st,
                                                   const int* __restrict__ active) {
@@ -144,10 +204,11 @@ __global__ __launch_bounds__(256) void k_axpy_norm(const Seg* __restrict__ segs,
     if (threadIdx.x == 0) out[0] = 0.0;
     return;
   }
+  if (EXACT) nv = NVMAX;
   cx<T> c[NVMAX];
 #pragma unroll
   for (int i = 0; i < NVMAX; ++i) {
-    if (i < nv) {
+    if (EXACT || i < nv) {
       const double2 q = st.coef[i * st.nseg + sid];
       c[i] = mk<T>((T)q.x, (T)q.y);
     }
@@ -155,14 +216,40 @@ __global__ __launch_bounds__(256) void k_axpy_norm(const Seg* __restrict__ segs,
   const int64_t N = S.N, off = S.off;
   const int64_t stride = (int64_t)S.vnblk * 256;
   double nrm = 0.0;
-  for (int64_t p = (int64_t)(wg - S.vblk0) * 256 + threadIdx.x; p < N; p += stride) {
-    cx<T> acc = w[off + p];
+  auto upd = [&](cx<T> acc, const cx<T>* a) {
 #pragma unroll
-    for (int i = 0; i < NVMAX; ++i) {
-      if (i < nv) acc = acc - c[i] * V.v[i][off + p];
+    for (int i = 0; i < NVMAX; ++i)
+      if (EXACT || i < nv) acc = acc - c[i] * a[i];
+    return acc;
+  };
+  int64_t p = (int64_t)(wg - S.vblk0) * 256 + threadIdx.x;
+  if (EXACT) {  // two elements per iteration: twice the loads in flight
+    for (; p + stride < N; p += 2 * stride) {
+      const cx<T> w0 = w[off + p], w1 = w[off + p + stride];
+      cx<T> a0[NVMAX], a1[NVMAX];
+#pragma unroll
+      for (int i = 0; i < NVMAX; ++i) {
+        if (EXACT || i < nv) {
+          a0[i] = V.v[i][off + p];
+          a1[i] = V.v[i][off + p + stride];
+        }
+      }
+      const cx<T> r0 = upd(w0, a0), r1 = upd(w1, a1);
+      w[off + p] = r0;
+      w[off + p + stride] = r1;
+      nrm += (double)r0.re * (double)r0.re + (double)r0.im * (double)r0.im;
+      nrm += (double)r1.re * (double)r1.re + (double)r1.im * (double)r1.im;
     }
-    w[off + p] = acc;
-    nrm += (double)acc.re * (double)acc.re + (double)acc.im * (double)acc.im;
+  }
+  for (; p < N; p += stride) {
+    const cx<T> w0 = w[off + p];
+    cx<T> a0[NVMAX];
+#pragma unroll
+    for (int i = 0; i < NVMAX; ++i)
+      if (EXACT || i < nv) a0[i] = V.v[i][off + p];
+    const cx<T> r0 = upd(w0, a0);
+    w[off + p] = r0;
+    nrm += (double)r0.re * (double)r0.re + (double)r0.im * (double)r0.im;
   }
   const double s = block_sum(nrm, red);
   if (threadIdx.x == 0) out[0] = s;
@@ -194,27 +281,29 @@ __global__ __launch_bounds__(256) void k_norm2(const Seg* __restrict__ segs, con
 }
 
 // out[sid] = sqrt(sum of the segment's partial norms) (range `which`)
-__global__ __launch_bounds__(64) void k_seg_norm(const Seg* __restrict__ segs, const double* __restrict__ part,
-                                                 int which, double* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_seg_norm(const Seg* __restrict__ segs, const double* __restrict__ part,
+                                                  int which, double* __restrict__ out) {
+  __shared__ double red[4];
   const int sid = blockIdx.x;
   int b0, nb;
   seg_range(segs[sid], which, b0, nb);
-  const double s = seg_sum(part, b0, nb, 0);
+  const double s = seg_sum0(part, b0, nb, red);
   if (threadIdx.x == 0) out[sid] = sqrt(s);
 }
 
 // Start of a cycle: beta = vscale_in * sqrt(sum of partials of range
 // `which`) (the partials are of the unscaled residual vector), g = (beta, 0,
 // ...), scale_0 = vscale_in / beta (0 when beta == 0), beta_out = beta.
-__global__ __launch_bounds__(64) void k_start_cycle(const Seg* __restrict__ segs, KState st, int which,
-                                                    const double* __restrict__ vscale_in,
-                                                    double* __restrict__ beta_out,
-                                                    const int* __restrict__ active) {
+__global__ __launch_bounds__(256) void k_start_cycle(const Seg* __restrict__ segs, KState st, int which,
+                                                     const double* __restrict__ vscale_in,
+                                                     double* __restrict__ beta_out,
+                                                     const int* __restrict__ active) {
+  __shared__ double red[4];
   const int sid = blockIdx.x;
   if (active && !active[sid]) return;
   int b0, nb;
   seg_range(segs[sid], which, b0, nb);
-  const double s = seg_sum(st.part, b0, nb, 0);
+  const double s = seg_sum0(st.part, b0, nb, red);
   if (threadIdx.x == 0) {
     const int ns = st.nseg;
     const double vin = vscale_in ? vscale_in[sid] : 1.0;
@@ -229,12 +318,13 @@ __global__ __launch_bounds__(64) void k_start_cycle(const Seg* __restrict__ segs
 // Finish Arnoldi column j: h_{j+1,j} = sqrt(sum partials); apply the
 // previous rotations to column j, build rotation j, update g, set
 // scale_{j+1} = 1/h_{j+1,j} (0 on breakdown).
-__global__ __launch_bounds__(64) void k_givens(const Seg* __restrict__ segs, KState st, int j,
-                                               const int* __restrict__ active) {
+__global__ __launch_bounds__(256) void k_givens(const Seg* __restrict__ segs, KState st, int j,
+                                                const int* __restrict__ active) {
+  __shared__ double red[4];
   const int sid = blockIdx.x;
   if (active && !active[sid]) return;
   const Seg& S = segs[sid];
-  const double s = seg_sum(st.part, S.vblk0, S.vnblk, 0);
+  const double s = seg_sum0(st.part, S.vblk0, S.vnblk, red);
   if (threadIdx.x != 0) return;
   const int ns = st.nseg;
   const double hn = sqrt(s);
@@ -299,7 +389,7 @@ __device__ __forceinline__ void solve_upper(const KState& st, int sid, int k, do
 // x += sum_j y_j * s_j * D_j, with D = V (GMRES, s = scale) or Z (FGMRES,
 // s = 1).  y from R y = g solved per workgroup.  x may be of higher
 // precision than D (mixed-precision outer iterate).
-template <typename TX, typename T, int KM>
+template <typename TX, typename T, int KM, bool EXACT>
 __global__ __launch_bounds__(256) void k_update_x(const Seg* __restrict__ segs, const int* __restrict__ vmap,
                                                  VecList<T> D, int k, bool use_scale, KState st,
                                                  cx<TX>* __restrict__ x, const int* __restrict__ active) {
@@ -308,6 +398,7 @@ __global__ __launch_bounds__(256) void k_update_x(const Seg* __restrict__ segs, 
   const int sid = vmap[wg];
   if (active && !active[sid]) return;
   const Seg& S = segs[sid];
+  if (EXACT) k = KM;
   if (threadIdx.x == 0) {
     double2 y[KMAX];
     solve_upper(st, sid, k, y);
@@ -320,15 +411,38 @@ __global__ __launch_bounds__(256) void k_update_x(const Seg* __restrict__ segs, 
   cx<TX> c[KM];
 #pragma unroll
   for (int j = 0; j < KM; ++j)
-    if (j < k) c[j] = mk<TX>((TX)ys[j].x, (TX)ys[j].y);
+    if (EXACT || j < k) c[j] = mk<TX>((TX)ys[j].x, (TX)ys[j].y);
   const int64_t N = S.N, off = S.off;
   const int64_t stride = (int64_t)S.vnblk * 256;
-  for (int64_t p = (int64_t)(wg - S.vblk0) * 256 + threadIdx.x; p < N; p += stride) {
-    cx<TX> acc = x[off + p];
+  auto upd = [&](cx<TX> acc, const cx<T>* d) {
 #pragma unroll
     for (int j = 0; j < KM; ++j)
-      if (j < k) acc = cfma(c[j], cast<TX>(D.v[j][off + p]), acc);
-    x[off + p] = acc;
+      if (EXACT || j < k) acc = cfma(c[j], cast<TX>(d[j]), acc);
+    return acc;
+  };
+  int64_t p = (int64_t)(wg - S.vblk0) * 256 + threadIdx.x;
+  if (EXACT) {  // two elements per iteration: twice the loads in flight
+    for (; p + stride < N; p += 2 * stride) {
+      const cx<TX> x0 = x[off + p], x1 = x[off + p + stride];
+      cx<T> d0[KM], d1[KM];
+#pragma unroll
+      for (int j = 0; j < KM; ++j) {
+        if (EXACT || j < k) {
+          d0[j] = D.v[j][off + p];
+          d1[j] = D.v[j][off + p + stride];
+        }
+      }
+      x[off + p] = upd(x0, d0);
+      x[off + p + stride] = upd(x1, d1);
+    }
+  }
+  for (; p < N; p += stride) {
+    const cx<TX> x0 = x[off + p];
+    cx<T> d0[KM];
+#pragma unroll
+    for (int j = 0; j < KM; ++j)
+      if (EXACT || j < k) d0[j] = D.v[j][off + p];
+    x[off + p] = upd(x0, d0);
   }
 }
 

@@ -459,11 +459,8 @@ size_t helm_workspace_bytes(const helm_grid* g, const helm_solver_opts* o, int n
     check_coarse_sizes(g, so);
     const int nlev = so.method == HELM_FGMRES_ML ? so.levels : 1;
     std::vector<int64_t> Nlev(nlev);
-    for (int l = 0; l < nlev; ++l) {
-      int n[3];
-      helm::Hierarchy::coarse_dims(g->n, l, n);
-      Nlev[l] = (int64_t)n[0] * n[1] * n[2] * nrhs;
-    }
+    const bool pairs = helm::Hierarchy::uses_pairs(g->stencil, g->dtype == HELM_C64 ? 4 : 8);
+    for (int l = 0; l < nlev; ++l) Nlev[l] = helm::Hierarchy::level_points(g->n, l, pairs) * nrhs;
     return g->dtype == HELM_C64 ? helm::Solver<float>::workspace_bytes(Nlev, so)
                                 : helm::Solver<double>::workspace_bytes(Nlev, so);
   } catch (...) {

@@ -17,6 +17,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -110,19 +111,26 @@ inline std::unique_ptr<OpTables> build_tables(const GridSpec& g, double omega, c
       cm[i] = 1.0 / (h * h * s0 * sm);
     }
     for (int i = 0; i < na; ++i) {
-      // forward: alpha = cp, beta = cm, delta = 0
+      // forward: alpha = cp, beta = cm, delta = 0.  The coupling to a node
+      // outside the grid (zero Dirichlet value) is folded into delta and the
+      // coupling itself set to zero, so a kernel may read any finite value
+      // in place of the missing neighbour.
       const size_t f0 = (size_t)T->tpre[a];
-      hd[f0 + i] = mk<double>(cp[i].real(), cp[i].imag());
-      hd[f0 + na + i] = mk<double>(cm[i].real(), cm[i].imag());
-      hd[f0 + 2 * na + i] = mk<double>(0.0, 0.0);
-      // adjoint: conjugates of the transposed couplings
-      const C al = (i + 1 < na) ? std::conj(cm[i + 1]) : C(0, 0);
-      const C be = (i > 0) ? std::conj(cp[i - 1]) : C(0, 0);
-      const C de = -std::conj(cp[i] + cm[i]) + al + be;
+      const C al = (i + 1 < na) ? cp[i] : C(0, 0);
+      const C be = (i > 0) ? cm[i] : C(0, 0);
+      const C de = (i + 1 < na ? C(0, 0) : -cp[i]) + (i > 0 ? C(0, 0) : -cm[i]);
+      hd[f0 + i] = mk<double>(al.real(), al.imag());
+      hd[f0 + na + i] = mk<double>(be.real(), be.imag());
+      hd[f0 + 2 * na + i] = mk<double>(de.real(), de.imag());
+      // adjoint: conjugates of the transposed couplings (already zero
+      // towards nodes outside the grid)
+      const C aal = (i + 1 < na) ? std::conj(cm[i + 1]) : C(0, 0);
+      const C abe = (i > 0) ? std::conj(cp[i - 1]) : C(0, 0);
+      const C ade = -std::conj(cp[i] + cm[i]) + aal + abe;
       const size_t a0 = (size_t)T->tdir + T->tpre[a];
-      hd[a0 + i] = mk<double>(al.real(), al.imag());
-      hd[a0 + na + i] = mk<double>(be.real(), be.imag());
-      hd[a0 + 2 * na + i] = mk<double>(de.real(), de.imag());
+      hd[a0 + i] = mk<double>(aal.real(), aal.imag());
+      hd[a0 + na + i] = mk<double>(abe.real(), abe.imag());
+      hd[a0 + 2 * na + i] = mk<double>(ade.real(), ade.imag());
     }
   }
   std::vector<cx<float>> hf(hd.size());
@@ -169,18 +177,27 @@ struct LevelSet {
   std::vector<Seg> host;
   DevBuf segs, smap, slocal, vmap, tmap, own;
   int nsblk = 0, nvblk = 0, ntblk = 0;
+  bool pair = false;  // every segment uses pair stencil tiles
   int64_t total = 0;  // vector length (sum of N)
   std::vector<std::unique_ptr<DevBuf>> models;  // owned coarse models
   const Seg* d() const { return segs.as<const Seg>(); }
 };
 
-// x-chunk (planes per stencil workgroup) for a level: enough workgroups to
-// fill the chip several times, at least 4 planes per workgroup.  The
-// HELM_XCHUNK environment variable overrides it (tile experiments).
+// x-chunk (planes per stencil workgroup) for a level: about `target`
+// workgroups over the level (a few per wave slot of the chip), at least 4
+// planes per workgroup.  The HELM_XCHUNK / HELM_STENCIL_WG environment
+// variables override the chunk / the target (tile experiments).
 inline int choose_xchunk(const std::vector<Seg>& segs) {
   if (const char* e = std::getenv("HELM_XCHUNK")) {
     const int v = std::atoi(e);
     if (v >= 1) return v;
+  }
+  // measured on 128^3 and 65x65x66 with 16 right-hand sides: pair tiles
+  // prefer longer marches (2048 workgroups), one-point tiles 8192
+  int64_t target = (!segs.empty() && segs[0].pair) ? 2048 : 8192;
+  if (const char* e = std::getenv("HELM_STENCIL_WG")) {
+    const int v = std::atoi(e);
+    if (v >= 1) target = v;
   }
   int64_t plane = 0;
   int nxmax = 1;
@@ -188,7 +205,6 @@ inline int choose_xchunk(const std::vector<Seg>& segs) {
     plane += s.plane_blocks;
     nxmax = std::max(nxmax, s.n[0]);
   }
-  const int64_t target = 8192;
   const int64_t nxc = std::max<int64_t>(1, (target + plane - 1) / std::max<int64_t>(plane, 1));
   int xchunk = (int)((nxmax + nxc - 1) / nxc);
   return std::max(4, std::min(xchunk, nxmax));
@@ -205,6 +221,7 @@ class Hierarchy {
     HELM_REQUIRE(ns >= 1, "no problems");
     stencil_ = probs[0].g.stencil;
     for (const auto& p : probs) HELM_REQUIRE(p.g.stencil == stencil_, "a batch must use one stencil type");
+    pair_path_ = uses_pairs(stencil_, model_bytes_);
     lev_.resize(nlev);
     // segment -> table index per level, deduplicated by (grid, omega)
     std::vector<int> tab_of(ns);
@@ -248,14 +265,17 @@ class Hierarchy {
         tl[t] = tables_.back().get();
       }
       int64_t off = 0;
+      bool pair = pair_path_;
       for (int s = 0; s < ns; ++s) {
         Seg& S = L.host[s];
         std::memset(&S, 0, sizeof(Seg));
         coarse_dims(probs[s].g.n, l, S.n);
         S.dir = probs[s].dir;
-        S.N = (int64_t)S.n[0] * S.n[1] * S.n[2];
+        S.pz = z_pitch(S.n[2], l, pair_path_);
+        S.N = (int64_t)S.n[0] * S.n[1] * S.pz;
         S.off = off;
         off += S.N;
+        pair = pair && (S.pz % 2 == 0);
         S.w2 = probs[s].omega * probs[s].omega;
         const OpTables& T = *tl[tab_of[s]];
         S.tabf = T.tabf.p;
@@ -263,8 +283,13 @@ class Hierarchy {
         for (int a = 0; a < 3; ++a) S.tpre[a] = T.tpre[a];
         S.tdir = T.tdir;
         S.in27 = T.in27;
-        S.plane_blocks = (int)ceil_div((int64_t)S.n[1] * S.n[2], 256);
       }
+      for (int s = 0; s < ns; ++s) {
+        Seg& S = L.host[s];
+        S.pair = pair ? 1 : 0;
+        S.plane_blocks = (int)ceil_div((int64_t)S.n[1] * S.pz, pair ? 512 : 256);
+      }
+      L.pair = pair;
       L.total = off;
       // models: level 0 borrows the caller's; coarse levels own one per distinct model
       std::vector<int> own(ns, 0);
@@ -372,6 +397,18 @@ class Hierarchy {
     return mx;
   }
 
+  // The complex64 7-point path tiles its stencil in z-pairs (16-byte
+  // accesses); its coarse levels get an even z pitch.  The fine level keeps
+  // the caller's layout (pairs there need an even n2).
+  static bool uses_pairs(int stencil, size_t model_bytes) { return stencil == 0 && model_bytes == 4; }
+  static int z_pitch(int nz, int level, bool pairs) { return (pairs && level > 0) ? nz + (nz & 1) : nz; }
+  // vector length of one problem on level l
+  static int64_t level_points(const int n0[3], int l, bool pairs) {
+    int n[3];
+    coarse_dims(n0, l, n);
+    return (int64_t)n[0] * n[1] * z_pitch(n[2], l, pairs);
+  }
+
   static void coarse_dims(const int n0[3], int l, int n[3]) {
     for (int a = 0; a < 3; ++a) {
       n[a] = n0[a];
@@ -390,6 +427,7 @@ class Hierarchy {
   hipStream_t st_;
   size_t model_bytes_;
   int stencil_ = 0;
+  bool pair_path_ = false;
   std::vector<std::unique_ptr<LevelSet>> lev_;
   std::vector<std::unique_ptr<OpTables>> tables_;
 };
@@ -397,16 +435,27 @@ class Hierarchy {
 // Which partial-sum range a stencil launch with NORM writes.
 inline int stencil_range(const LevelSet& L) { return L.stencil == 0 ? PR_STENCIL : PR_POINT; }
 
-// out = [s_b b -] s_x H x over all segments of level L.
+inline bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+// out = [s_b b -] s_x H x over all segments of level L.  The complex64
+// 7-point operator runs pair tiles when the level and the buffers allow it.
 template <typename TC, typename TX, typename TM, typename TB, typename TO, bool RESID, bool NORM>
 void launch_h(const LevelSet& L, const cx<TX>* x, const double* xs, const cx<TB>* b, const double* bs,
               cx<TO>* out, double* part, const int* active, hipStream_t st) {
-  if (L.stencil == 1)
+  constexpr bool all_f32 = std::is_same<TC, float>::value && std::is_same<TX, float>::value &&
+                           std::is_same<TM, float>::value && std::is_same<TB, float>::value &&
+                           std::is_same<TO, float>::value;
+  if (L.stencil == 1) {
     hipLaunchKernelGGL((k_h27<TC, TX, TM, TB, TO, RESID, NORM>), dim3(L.ntblk), dim3(256), 0, st, L.d(),
                        L.tmap.as<const int>(), x, xs, b, bs, out, part, active);
-  else
+  } else if (all_f32 && L.pair && aligned16(x) && aligned16(out) && (!RESID || aligned16(b))) {
+    hipLaunchKernelGGL((k_h7p<RESID, NORM>), dim3(L.nsblk), dim3(256), 0, st, L.d(), L.smap.as<const int>(),
+                       L.slocal.as<const int>(), reinterpret_cast<const c32*>(x), xs,
+                       reinterpret_cast<const c32*>(b), bs, reinterpret_cast<c32*>(out), part, active);
+  } else {
     hipLaunchKernelGGL((k_h7<TC, TX, TM, TB, TO, RESID, NORM>), dim3(L.nsblk), dim3(256), 0, st, L.d(),
                        L.smap.as<const int>(), L.slocal.as<const int>(), x, xs, b, bs, out, part, active);
+  }
 }
 
 }  // namespace helm

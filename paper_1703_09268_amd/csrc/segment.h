@@ -21,10 +21,14 @@ struct Int27 {
 struct Seg {
   int n[3];
   int dir;            // 0: H, 1: H^H
-  int64_t N;          // n0*n1*n2
+  int pz;             // z pitch of the level's vectors: n2, or n2 + 1 to make it even
+                      // (coarse levels of the pair-tiled 7-point path; the pad
+                      // entries of every vector and model are kept at zero)
+  int pair;           // stencil tiles of 256 lanes x 2 consecutive z-points
+  int64_t N;          // n0*n1*pz (vector length including pads)
   int64_t off;        // element offset of this segment in a level vector
   // stencil launch: flattened (y,z) plane tiles of 256 lanes, x chunks
-  int plane_blocks;   // ceil(n1*n2 / 256)
+  int plane_blocks;   // ceil(n1*n2 / 256), or ceil(n1*pz / 512) with pair tiles
   int xchunk, nxc;    // x planes per workgroup, number of x chunks
   int sblk0, snblk;   // stencil workgroups [sblk0, sblk0 + snblk)
   int vblk0, vnblk;   // vector-kernel workgroups (grid-stride over N)

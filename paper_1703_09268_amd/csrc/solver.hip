@@ -101,7 +101,7 @@ class Solver {
     // ||q||
     hipLaunchKernelGGL((k_norm2<T>), dim3(L.nvblk), dim3(256), 0, st_, L.d(), L.vmap.as<const int>(), q, part_,
                        (const int*)nullptr);
-    hipLaunchKernelGGL(k_seg_norm, dim3(nseg_), dim3(64), 0, st_, L.d(), (const double*)part_, (int)PR_VECTOR,
+    hipLaunchKernelGGL(k_seg_norm, dim3(nseg_), dim3(256), 0, st_, L.d(), (const double*)part_, (int)PR_VECTOR,
                        beta_dev_);
     HELM_HIP_CHECK(hipMemcpyAsync(qn.data(), beta_dev_, nseg_ * sizeof(double), hipMemcpyDeviceToHost, st_));
     HELM_HIP_CHECK(hipStreamSynchronize(st_));
@@ -134,7 +134,7 @@ class Solver {
       // true residual in FP64, stored (rounded) as the first basis vector
       launch_h<double, double, T, T, T, true, true>(L, X_, nullptr, q, nullptr, outer_.V[0], part_, active_, st_);
       fine_mv_++;
-      hipLaunchKernelGGL(k_start_cycle, dim3(nseg_), dim3(64), 0, st_, L.d(), outer_.ks, stencil_range(L),
+      hipLaunchKernelGGL(k_start_cycle, dim3(nseg_), dim3(256), 0, st_, L.d(), outer_.ks, stencil_range(L),
                          (const double*)nullptr, beta_dev_, (const int*)active_);
       HELM_HIP_CHECK(hipMemcpyAsync(beta.data(), beta_dev_, nseg_ * sizeof(double), hipMemcpyDeviceToHost, st_));
       HELM_HIP_CHECK(hipStreamSynchronize(st_));
@@ -179,12 +179,17 @@ class Solver {
     size_t total = 0;
     const int nlev = (int)Nlev.size();
     for (int l = 0; l < nlev; ++l) {
-      total += (size_t)slots_at(o, l, nlev) * Nlev[l] * sizeof(cx<T>);
+      total += (size_t)slots_at(o, l, nlev) * vec_bytes(Nlev[l]);
       if (l > 0) total += (size_t)Nlev[l] * sizeof(T);
     }
-    total += (size_t)Nlev[0] * sizeof(cx<double>);  // FP64 outer iterate
+    total += round256((size_t)Nlev[0] * sizeof(cx<double>));  // FP64 outer iterate
     return total;
   }
+
+  // every workspace vector starts on a 256-byte boundary (16-byte pair
+  // accesses need at least 16)
+  static size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+  static size_t vec_bytes(int64_t len) { return round256((size_t)len * sizeof(cx<T>)); }
 
  private:
   static unsigned flat_blocks(int64_t n) { return std::min<unsigned>(65536, ceil_div(n, 256)); }
@@ -214,12 +219,12 @@ class Solver {
     const int64_t len = H_->level(lvl).total;
     for (int i = 0; i <= k; ++i) {
       S.V[i] = reinterpret_cast<cx<T>*>(cur);
-      cur += (size_t)len * sizeof(cx<T>);
+      cur += vec_bytes(len);
     }
     if (flex)
       for (int i = 0; i < k; ++i) {
         S.Z[i] = reinterpret_cast<cx<T>*>(cur);
-        cur += (size_t)len * sizeof(cx<T>);
+        cur += vec_bytes(len);
       }
   }
 
@@ -247,8 +252,8 @@ class Solver {
                  "inner Krylov dimensions must be in 1..32");
     size_t vbytes = 0;
     for (int l = 0; l < nlev_; ++l)
-      vbytes += (size_t)slots_at(o_, l, nlev_) * H_->level(l).total * sizeof(cx<T>);
-    const size_t xbytes = (size_t)H_->level(0).total * sizeof(cx<double>);
+      vbytes += (size_t)slots_at(o_, l, nlev_) * vec_bytes(H_->level(l).total);
+    const size_t xbytes = round256((size_t)H_->level(0).total * sizeof(cx<double>));
     vec_.ensure(vbytes + xbytes + 256);
     part_buf_.ensure(H_->max_partials() * PSTRIDE * sizeof(double));
     part_ = part_buf_.as<double>();
@@ -276,15 +281,15 @@ class Solver {
         make_space(coarse_[l], l, o_.kc_i, !coarsest, cur);
         make_state(coarse_[l].ks, sc);
         B_[l] = reinterpret_cast<cx<T>*>(cur);
-        cur += (size_t)len * sizeof(cx<T>);
+        cur += vec_bytes(len);
         Xc_[l] = reinterpret_cast<cx<T>*>(cur);
-        cur += (size_t)len * sizeof(cx<T>);
+        cur += vec_bytes(len);
       }
       if (!coarsest) {
         make_space(smooth_[l], l, o_.ks_i, false, cur);
         make_state(smooth_[l].ks, sc);
         R_[l] = reinterpret_cast<cx<T>*>(cur);
-        cur += (size_t)len * sizeof(cx<T>);
+        cur += vec_bytes(len);
       }
     }
     active_ = reinterpret_cast<int*>(sc);
@@ -333,18 +338,20 @@ class Solver {
     update_x<double>(outer_, X_);
   }
 
-  template <int NV>
+  // NV: exact vector count when EXACT, else an upper bound of nv
+  template <int NV, bool EXACT>
   void dots_axpy(Space& S, int nv, int j, cx<T>* w) {
     const LevelSet& L = H_->level(S.lvl);
     VecList<T> vl;
     vl.v[0] = S.v0;
     for (int i = 1; i < nv; ++i) vl.v[i] = S.V[i];
-    hipLaunchKernelGGL((k_dots<T, NV>), dim3(L.nvblk), dim3(256), 0, st_, L.d(), L.vmap.as<const int>(), vl, nv,
-                       (const cx<T>*)w, part_, (const int*)active_);
-    hipLaunchKernelGGL(k_reduce_dots, dim3(nseg_), dim3(64), 0, st_, L.d(), S.ks, nv, j, (const int*)active_);
-    hipLaunchKernelGGL((k_axpy_norm<T, NV>), dim3(L.nvblk), dim3(256), 0, st_, L.d(), L.vmap.as<const int>(), vl,
-                       nv, w, S.ks, (const int*)active_);
-    hipLaunchKernelGGL(k_givens, dim3(nseg_), dim3(64), 0, st_, L.d(), S.ks, j, (const int*)active_);
+    hipLaunchKernelGGL((k_dots<T, NV, EXACT>), dim3(L.nvblk), dim3(256), 0, st_, L.d(), L.vmap.as<const int>(), vl,
+                       nv, (const cx<T>*)w, part_, (const int*)active_);
+    hipLaunchKernelGGL((k_reduce_dots<NV, EXACT>), dim3(nseg_), dim3(256), 0, st_, L.d(), S.ks, nv, j,
+                       (const int*)active_);
+    hipLaunchKernelGGL((k_axpy_norm<T, NV, EXACT>), dim3(L.nvblk), dim3(256), 0, st_, L.d(),
+                       L.vmap.as<const int>(), vl, nv, w, S.ks, (const int*)active_);
+    hipLaunchKernelGGL(k_givens, dim3(nseg_), dim3(256), 0, st_, L.d(), S.ks, j, (const int*)active_);
   }
 
   // Arnoldi column j of space S from basis vector vj (with scale).
@@ -362,10 +369,18 @@ class Solver {
     }
     if (S.lvl == 0) fine_mv_++;
     const int nv = j + 1;
-    if (nv <= 6) dots_axpy<6>(S, nv, j, w);
-    else if (nv <= 11) dots_axpy<11>(S, nv, j, w);
-    else if (nv <= 21) dots_axpy<21>(S, nv, j, w);
-    else dots_axpy<33>(S, nv, j, w);
+    switch (nv) {
+      case 1: dots_axpy<1, true>(S, nv, j, w); break;
+      case 2: dots_axpy<2, true>(S, nv, j, w); break;
+      case 3: dots_axpy<3, true>(S, nv, j, w); break;
+      case 4: dots_axpy<4, true>(S, nv, j, w); break;
+      case 5: dots_axpy<5, true>(S, nv, j, w); break;
+      case 6: dots_axpy<6, true>(S, nv, j, w); break;
+      default:
+        if (nv <= 11) dots_axpy<11, false>(S, nv, j, w);
+        else if (nv <= 21) dots_axpy<21, false>(S, nv, j, w);
+        else dots_axpy<33, false>(S, nv, j, w);
+    }
   }
 
   template <typename TX>
@@ -375,18 +390,22 @@ class Solver {
     for (int j = 0; j < S.k; ++j) D.v[j] = S.flex ? S.Z[j] : (j == 0 ? S.v0 : S.V[j]);
     const dim3 grid(L.nvblk);
     const int* vm = L.vmap.as<const int>();
-    if (S.k <= 5)
-      hipLaunchKernelGGL((k_update_x<TX, T, 5>), grid, dim3(256), 0, st_, L.d(), vm, D, S.k, !S.flex, S.ks, x,
-                         (const int*)active_);
-    else if (S.k <= 10)
-      hipLaunchKernelGGL((k_update_x<TX, T, 10>), grid, dim3(256), 0, st_, L.d(), vm, D, S.k, !S.flex, S.ks, x,
-                         (const int*)active_);
-    else if (S.k <= 20)
-      hipLaunchKernelGGL((k_update_x<TX, T, 20>), grid, dim3(256), 0, st_, L.d(), vm, D, S.k, !S.flex, S.ks, x,
-                         (const int*)active_);
-    else
-      hipLaunchKernelGGL((k_update_x<TX, T, 32>), grid, dim3(256), 0, st_, L.d(), vm, D, S.k, !S.flex, S.ks, x,
-                         (const int*)active_);
+    const int* act = active_;
+    const bool sc = !S.flex;
+#define HELM_UPD(KM, EX) \
+  hipLaunchKernelGGL((k_update_x<TX, T, KM, EX>), grid, dim3(256), 0, st_, L.d(), vm, D, S.k, sc, S.ks, x, act)
+    switch (S.k) {
+      case 1: HELM_UPD(1, true); break;
+      case 2: HELM_UPD(2, true); break;
+      case 3: HELM_UPD(3, true); break;
+      case 4: HELM_UPD(4, true); break;
+      case 5: HELM_UPD(5, true); break;
+      default:
+        if (S.k <= 10) HELM_UPD(10, false);
+        else if (S.k <= 20) HELM_UPD(20, false);
+        else HELM_UPD(32, false);
+    }
+#undef HELM_UPD
   }
 
   // `cycles` restart cycles of the space's (F)GMRES on level S.lvl for
@@ -401,13 +420,13 @@ class Solver {
         S.v0 = b.p;
         hipLaunchKernelGGL((k_norm2<T>), dim3(L.nvblk), dim3(256), 0, st_, L.d(), vm, b.p, part_,
                            (const int*)active_);
-        hipLaunchKernelGGL(k_start_cycle, dim3(nseg_), dim3(64), 0, st_, L.d(), S.ks, (int)PR_VECTOR, b.s,
+        hipLaunchKernelGGL(k_start_cycle, dim3(nseg_), dim3(256), 0, st_, L.d(), S.ks, (int)PR_VECTOR, b.s,
                            (double*)nullptr, (const int*)active_);
       } else {
         S.v0 = S.V[0];
         launch_h<T, T, T, T, T, true, true>(L, x, nullptr, b.p, b.s, S.V[0], part_, active_, st_);
         if (S.lvl == 0) fine_mv_++;
-        hipLaunchKernelGGL(k_start_cycle, dim3(nseg_), dim3(64), 0, st_, L.d(), S.ks, stencil_range(L),
+        hipLaunchKernelGGL(k_start_cycle, dim3(nseg_), dim3(256), 0, st_, L.d(), S.ks, stencil_range(L),
                            (const double*)nullptr, (double*)nullptr, (const int*)active_);
       }
       for (int j = 0; j < S.k; ++j) {

@@ -70,10 +70,34 @@ __device__ __forceinline__ cx<TC> ld(const cx<TX>* p) {
   return cast<TC>(*p);
 }
 
+// Workgroup-uniform table entry through the scalar cache (constant address
+// space: the tables are read-only while any kernel runs).  Keeps these reads
+// off the vector memory counter, so they never wait for the field loads in
+// flight.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+__device__ __forceinline__ cx<T> uload(const cx<T>* p, int i) {
+  typedef const __attribute__((address_space(4))) cx<T> ccx;
+  return ((ccx*)p)[i];
+}
+// global address space pointers (a plain pointer read from a segment
+// descriptor would otherwise be accessed with flat instructions, which wait
+// for every vector and scalar access in flight)
+#define HELM_GLOBAL __attribute__((address_space(1)))
+#else
+template <typename T>
+__device__ __forceinline__ cx<T> uload(const cx<T>* p, int i) {
+  return p[i];
+}
+#define HELM_GLOBAL
+#endif
+
 // out = s_x * H x            (RESID = false)
 // out = s_b * b - s_x * H x  (RESID = true)
 // s_x, s_b: per-segment scales (null = 1).  With NORM, the workgroup's sum of
 // |out|^2 (FP64) goes to part[(sblk0 + local) * PSTRIDE].
+// Any precision; one point per lane (a pair tile is walked as two halves).
+// Pad entries (k >= n2 on a padded level) are written as zero.
 template <typename TC, typename TX, typename TM, typename TB, typename TO, bool RESID, bool NORM>
 __global__ __launch_bounds__(256) void k_h7(const Seg* __restrict__ segs, const int* __restrict__ smap,
                                             const int* __restrict__ slocal,
@@ -92,14 +116,10 @@ __global__ __launch_bounds__(256) void k_h7(const Seg* __restrict__ segs, const 
     if (NORM && threadIdx.x == 0) *pslot = 0.0;
     return;  // uniform across the workgroup
   }
-  const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
+  const int nx = S.n[0], ny = S.n[1], nz = S.n[2], pz = S.pz;
   const int xc = local / S.plane_blocks;
   const int pb = local - xc * S.plane_blocks;
-  const int idx = pb * 256 + threadIdx.x;
-  const int64_t plane = (int64_t)ny * nz;
-  const bool in = idx < plane;
-  const int j = in ? idx / nz : 0;
-  const int k = in ? idx - j * nz : 0;
+  const int64_t plane = (int64_t)ny * pz;
   const Tab7<TC> tab = seg_tables<TC>(S);
   const TC w2 = (TC)S.w2;
   const TM* __restrict__ m = reinterpret_cast<const TM*>(S.m);
@@ -109,51 +129,190 @@ __global__ __launch_bounds__(256) void k_h7(const Seg* __restrict__ segs, const 
   if (RESID) sb = bs ? (TC)bs[sid] : TC(1);
   const int i0 = xc * S.xchunk;
   const int i1 = min(nx, i0 + S.xchunk);
-  cx<TC> az = czero<TC>(), bz = az, dz = az, ay = az, by = az, dy = az;
-  if (in) {
-    az = tab.al[2][k]; bz = tab.be[2][k]; dz = tab.de[2][k];
-    ay = tab.al[1][j]; by = tab.be[1][j]; dy = tab.de[1][j];
-  }
-  const bool has_ym = in && j > 0, has_yp = in && j + 1 < ny;
-  const bool has_zm = in && k > 0, has_zp = in && k + 1 < nz;
-  int64_t p = (int64_t)i0 * plane + idx;
-  cx<TC> xm = czero<TC>(), xcur = czero<TC>(), xp = czero<TC>();
-  if (in) {
-    if (i0 > 0) xm = ld<TX, TC>(xr + p - plane);
-    xcur = ld<TX, TC>(xr + p);
-    if (i0 + 1 < nx) xp = ld<TX, TC>(xr + p + plane);
-  }
   double nrm = 0.0;
-  for (int i = i0; i < i1; ++i, p += plane) {
-    cx<TC> ym = czero<TC>(), yp = ym, zm = ym, zp = ym;
-    TC mv = TC(0);
-    if (in) {
-      if (has_ym) ym = ld<TX, TC>(xr + p - nz);
-      if (has_yp) yp = ld<TX, TC>(xr + p + nz);
-      if (has_zm) zm = ld<TX, TC>(xr + p - 1);
-      if (has_zp) zp = ld<TX, TC>(xr + p + 1);
-      mv = (TC)m[p];
+  const int halves = S.pair ? 2 : 1;
+  for (int half = 0; half < halves; ++half) {
+    const int idx = (pb * halves + half) * 256 + threadIdx.x;
+    const bool in = idx < plane;
+    const int j = in ? idx / pz : 0;
+    const int k = in ? idx - j * pz : 0;
+    const bool real = in && k < nz;
+    cx<TC> az = czero<TC>(), bz = az, dz = az, ay = az, by = az, dy = az;
+    if (real) {
+      az = tab.al[2][k]; bz = tab.be[2][k]; dz = tab.de[2][k];
+      ay = tab.al[1][j]; by = tab.be[1][j]; dy = tab.de[1][j];
     }
-    // plane i+2 goes in flight while plane i is computed
-    cx<TC> xpp = czero<TC>();
-    if (in && i + 2 < nx) xpp = ld<TX, TC>(xr + p + 2 * plane);
-    if (in) {
-      const cx<TC> ax = tab.al[0][i], bx = tab.be[0][i], dx = tab.de[0][i];
-      cx<TC> acc = mk<TC>(w2 * mv + dx.re + dy.re + dz.re, dx.im + dy.im + dz.im) * xcur;
-      acc = cfma(ax, xp - xcur, acc);
-      acc = cfma(bx, xm - xcur, acc);
-      acc = cfma(ay, yp - xcur, acc);
-      acc = cfma(by, ym - xcur, acc);
-      acc = cfma(az, zp - xcur, acc);
-      acc = cfma(bz, zm - xcur, acc);
-      acc = sx * acc;
-      if (RESID) acc = sb * ld<TB, TC>(b + S.off + p) - acc;
-      out[S.off + p] = cast<TO>(acc);
-      if (NORM) nrm += (double)acc.re * (double)acc.re + (double)acc.im * (double)acc.im;
+    const bool has_ym = real && j > 0, has_yp = real && j + 1 < ny;
+    const bool has_zm = real && k > 0, has_zp = real && k + 1 < nz;
+    int64_t p = (int64_t)i0 * plane + idx;
+    cx<TC> xm = czero<TC>(), xcur = czero<TC>(), xp = czero<TC>();
+    if (real) {
+      if (i0 > 0) xm = ld<TX, TC>(xr + p - plane);
+      xcur = ld<TX, TC>(xr + p);
+      if (i0 + 1 < nx) xp = ld<TX, TC>(xr + p + plane);
     }
-    xm = xcur;
-    xcur = xp;
-    xp = xpp;
+    for (int i = i0; i < i1; ++i, p += plane) {
+      cx<TC> ym = czero<TC>(), yp = ym, zm = ym, zp = ym;
+      TC mv = TC(0);
+      if (real) {
+        if (has_ym) ym = ld<TX, TC>(xr + p - pz);
+        if (has_yp) yp = ld<TX, TC>(xr + p + pz);
+        if (has_zm) zm = ld<TX, TC>(xr + p - 1);
+        if (has_zp) zp = ld<TX, TC>(xr + p + 1);
+        mv = (TC)m[p];
+      }
+      // plane i+2 goes in flight while plane i is computed
+      cx<TC> xpp = czero<TC>();
+      if (real && i + 2 < nx) xpp = ld<TX, TC>(xr + p + 2 * plane);
+      if (in) {
+        cx<TC> acc = czero<TC>();
+        if (real) {
+          const cx<TC> ax = uload(tab.al[0], i), bx = uload(tab.be[0], i), dx = uload(tab.de[0], i);
+          acc = mk<TC>(w2 * mv + dx.re + dy.re + dz.re, dx.im + dy.im + dz.im) * xcur;
+          acc = cfma(ax, xp - xcur, acc);
+          acc = cfma(bx, xm - xcur, acc);
+          acc = cfma(ay, yp - xcur, acc);
+          acc = cfma(by, ym - xcur, acc);
+          acc = cfma(az, zp - xcur, acc);
+          acc = cfma(bz, zm - xcur, acc);
+          acc = sx * acc;
+          if (RESID) acc = sb * ld<TB, TC>(b + S.off + p) - acc;
+        }
+        out[S.off + p] = cast<TO>(acc);
+        if (NORM) nrm += (double)acc.re * (double)acc.re + (double)acc.im * (double)acc.im;
+      }
+      xm = xcur;
+      xcur = xp;
+      xp = xpp;
+    }
+  }
+  if (NORM) {
+    const double s = block_sum(nrm, red);
+    if (threadIdx.x == 0) *pslot = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// complex64 7-point operator with pair tiles: a lane owns two consecutive
+// z-points (e0, e0 + 1) of the flattened (y, z) plane, e0 even, and moves
+// them with 16-byte accesses; a workgroup covers 512 points of the plane and
+// marches along x.  Per plane and pair: one 16-byte load of x (plane i+2, the
+// three before it are in registers), two 16-byte loads of the y neighbour
+// pairs, two 8-byte loads of the outer z neighbours (the inner ones are the
+// pair itself), one 8-byte model load and one 16-byte store.
+// Requirements (checked by the launcher): every segment of the level has an
+// even z pitch and an even element offset, and x, b, out are 16-byte aligned.
+// Couplings to nodes outside the grid are zero in the tables (folded into
+// delta), so clamped neighbour addresses need no masks.  Out-of-plane lanes
+// compute the plane's last pair again (same inputs, same instructions) and
+// store the identical values, which keeps the loop body branch-free.  The
+// output must not alias x or b.
+// ---------------------------------------------------------------------------
+struct alignas(16) c32x2 {
+  float a, b, c, d;  // (re, im) of element 0, then of element 1
+};
+
+template <bool RESID, bool NORM>
+__global__ __launch_bounds__(256) void k_h7p(const Seg* __restrict__ segs, const int* __restrict__ smap,
+                                             const int* __restrict__ slocal, const c32* __restrict__ x,
+                                             const double* __restrict__ xs, const c32* __restrict__ b,
+                                             const double* __restrict__ bs, c32* __restrict__ out,
+                                             double* __restrict__ part, const int* __restrict__ active) {
+  __shared__ double red[16];
+  const int wg = xcd_logical(blockIdx.x, gridDim.x);
+  const int sid = smap[wg];
+  const int local = slocal[wg];
+  const Seg& S = segs[sid];
+  double* const pslot = NORM ? part + (int64_t)(S.sblk0 + local) * PSTRIDE : nullptr;
+  if (active && !active[sid]) {
+    if (NORM && threadIdx.x == 0) *pslot = 0.0;
+    return;
+  }
+  const int nx = S.n[0], nz = S.n[2], pz = S.pz;
+  const int plane = S.n[1] * pz;  // even
+  const int npair = plane >> 1;
+  const int xc = local / S.plane_blocks;
+  const int pb = local - xc * S.plane_blocks;
+  const int q0 = pb * 256 + threadIdx.x;
+  const bool in = q0 < npair;
+  const int e0 = 2 * (in ? q0 : npair - 1);
+  const int j = e0 / pz, k0 = e0 - j * pz;  // k0 even, k0 + 1 < pz
+  const bool pad1 = k0 + 1 >= nz;           // element 1 is a pitch pad
+  const Tab7<float> tab = seg_tables<float>(S);
+  const c32 ay = tab.al[1][j], by = tab.be[1][j], dy = tab.de[1][j];
+  const c32 az0 = tab.al[2][k0], bz0 = tab.be[2][k0];
+  const c32 d0 = dy + tab.de[2][k0];
+  c32 az1 = czero<float>(), bz1 = czero<float>(), d1 = dy;
+  if (!pad1) {
+    az1 = tab.al[2][k0 + 1];
+    bz1 = tab.be[2][k0 + 1];
+    d1 = dy + tab.de[2][k0 + 1];
+  }
+  // neighbour element offsets inside the plane, clamped where the coupling is zero
+  const int oym = e0 >= pz ? e0 - pz : e0;
+  const int oyp = e0 + pz < plane ? e0 + pz : e0;
+  const int ozm = e0 > 0 ? e0 - 1 : e0;
+  const int ozp = e0 + 2 < plane ? e0 + 2 : e0 + 1;
+  const float w2 = (float)S.w2;
+  const HELM_GLOBAL float2* __restrict__ mp =
+      (const HELM_GLOBAL float2*)(reinterpret_cast<const float*>(S.m) + e0);  // e0 even: 8-byte aligned
+  const c32* __restrict__ xr = x + S.off;
+  const float sx = xs ? (float)xs[sid] : 1.0f;
+  float sb = 1.0f;
+  if (RESID) sb = bs ? (float)bs[sid] : 1.0f;
+  auto L2 = [&](int ip, int e) { return *reinterpret_cast<const c32x2*>(xr + (int64_t)ip * plane + e); };
+  const int i0 = xc * S.xchunk;
+  const int i1 = min(nx, i0 + S.xchunk);
+  double nrm = 0.0;
+  const double wn = in ? 1.0 : 0.0;  // norm weight (duplicates count zero)
+  // One plane: qm, qc, qp hold x planes i-1, i, i+1; qn receives plane i+2.
+  auto step = [&](int i, const c32x2& qm, const c32x2& qc, const c32x2& qp, c32x2& qn) {
+    const int64_t pl = (int64_t)i * plane;
+    // this plane's loads first, then the prefetch of plane i+2 (vector
+    // loads complete in order, so waiting for these leaves it in flight)
+    const c32x2 ym = L2(i, oym), yp = L2(i, oyp);
+    const c32 zm = xr[pl + ozm], zp = xr[pl + ozp];
+    const float2 mv = mp[pl >> 1];  // plane is even
+    qn = L2(min(i + 2, nx - 1), e0);
+    const c32 ax = uload(tab.al[0], i), bx = uload(tab.be[0], i), dx = uload(tab.de[0], i);
+    const c32 x0 = mk(qc.a, qc.b), x1 = mk(qc.c, qc.d);
+    c32 a0 = mk(w2 * mv.x + dx.re + d0.re, dx.im + d0.im) * x0;
+    a0 = cfma(ax, mk(qp.a, qp.b) - x0, a0);
+    a0 = cfma(bx, mk(qm.a, qm.b) - x0, a0);
+    a0 = cfma(ay, mk(yp.a, yp.b) - x0, a0);
+    a0 = cfma(by, mk(ym.a, ym.b) - x0, a0);
+    a0 = cfma(az0, x1 - x0, a0);
+    a0 = cfma(bz0, zm - x0, a0);
+    c32 a1 = mk(w2 * mv.y + dx.re + d1.re, dx.im + d1.im) * x1;
+    a1 = cfma(ax, mk(qp.c, qp.d) - x1, a1);
+    a1 = cfma(bx, mk(qm.c, qm.d) - x1, a1);
+    a1 = cfma(ay, mk(yp.c, yp.d) - x1, a1);
+    a1 = cfma(by, mk(ym.c, ym.d) - x1, a1);
+    a1 = cfma(az1, zp - x1, a1);
+    a1 = cfma(bz1, x0 - x1, a1);
+    a0 = sx * a0;
+    a1 = sx * a1;
+    if (RESID) {
+      const c32x2 bv = *reinterpret_cast<const c32x2*>(b + S.off + pl + e0);
+      a0 = sb * mk(bv.a, bv.b) - a0;
+      a1 = sb * mk(bv.c, bv.d) - a1;
+    }
+    if (pad1) a1 = czero<float>();
+    // out-of-plane lanes hold the last pair of the plane and store the same
+    // values as its owner (no branch around the loop body)
+    c32x2 o;
+    o.a = a0.re; o.b = a0.im; o.c = a1.re; o.d = a1.im;
+    *reinterpret_cast<c32x2*>(out + S.off + pl + e0) = o;
+    if (NORM)
+      nrm += wn * ((double)a0.re * (double)a0.re + (double)a0.im * (double)a0.im +
+                   ((double)a1.re * (double)a1.re + (double)a1.im * (double)a1.im));
+  };
+  c32x2 qm = L2(max(i0 - 1, 0), e0), qc = L2(i0, e0), qp = L2(min(i0 + 1, nx - 1), e0), qn;
+  for (int i = i0; i < i1; ++i) {
+    step(i, qm, qc, qp, qn);
+    qm = qc;
+    qc = qp;
+    qp = qn;
   }
   if (NORM) {
     const double s = block_sum(nrm, red);

@@ -10,7 +10,8 @@
 // The coarse model is injected: m_c(I) = m_f(min(2I, n_f - 1)).
 // All kernels are point-wise over the segments of one level (tmap of the
 // level whose points the lanes own); fine and coarse descriptors of a
-// segment share its index.
+// segment share its index.  Vectors use each level's z pitch; pad entries of
+// the coarse outputs are written as zero, fine pads are left untouched.
 #pragma once
 
 #include "common.h"
@@ -31,11 +32,15 @@ __global__ __launch_bounds__(256) void k_restrict(const Seg* __restrict__ fsegs,
   const Seg& F = fsegs[sid];
   const int64_t pc = (int64_t)(wg - C.tblk0) * 256 + threadIdx.x;
   if (pc >= C.N) return;
-  const int ncy = C.n[1], ncz = C.n[2];
-  const int nfx = F.n[0], nfy = F.n[1], nfz = F.n[2];
-  const int K = (int)(pc % ncz);
-  const int J = (int)((pc / ncz) % ncy);
-  const int I = (int)(pc / ((int64_t)ncy * ncz));
+  const int ncy = C.n[1], ncz = C.n[2], cpz = C.pz;
+  const int nfx = F.n[0], nfy = F.n[1], nfz = F.n[2], fpz = F.pz;
+  const int K = (int)(pc % cpz);
+  const int J = (int)((pc / cpz) % ncy);
+  const int I = (int)(pc / ((int64_t)ncy * cpz));
+  if (K >= ncz) {
+    rc[C.off + pc] = czero<T>();
+    return;
+  }
   const cx<T>* f = rf + F.off;
   cx<T> acc = czero<T>();
   for (int di = -1; di <= 1; ++di) {
@@ -50,7 +55,7 @@ __global__ __launch_bounds__(256) void k_restrict(const Seg* __restrict__ fsegs,
         const int k = 2 * K + dk;
         if (k < 0 || k >= nfz) continue;
         const T wk = dk ? T(0.5) : T(1);
-        acc = acc + (wi * wj * wk) * f[((int64_t)i * nfy + j) * nfz + k];
+        acc = acc + (wi * wj * wk) * f[((int64_t)i * nfy + j) * fpz + k];
       }
     }
   }
@@ -70,18 +75,19 @@ __global__ __launch_bounds__(256) void k_prolong_add(const Seg* __restrict__ fse
   const Seg& C = csegs[sid];
   const int64_t p = (int64_t)(wg - F.tblk0) * 256 + threadIdx.x;
   if (p >= F.N) return;
-  const int nfy = F.n[1], nfz = F.n[2];
-  const int ncy = C.n[1], ncz = C.n[2];
-  const int k = (int)(p % nfz);
-  const int j = (int)((p / nfz) % nfy);
-  const int i = (int)(p / ((int64_t)nfy * nfz));
+  const int nfy = F.n[1], nfz = F.n[2], fpz = F.pz;
+  const int ncy = C.n[1], cpz = C.pz;
+  const int k = (int)(p % fpz);
+  const int j = (int)((p / fpz) % nfy);
+  const int i = (int)(p / ((int64_t)nfy * fpz));
+  if (k >= nfz) return;
   // even node: one coarse node (weight 1); odd node: two (weight 1/2 each)
   const int i0 = i >> 1, i1 = (i + 1) >> 1;
   const int j0 = j >> 1, j1 = (j + 1) >> 1;
   const int k0 = k >> 1, k1 = (k + 1) >> 1;
   const T wi = (i & 1) ? T(0.5) : T(1), wj = (j & 1) ? T(0.5) : T(1), wk = (k & 1) ? T(0.5) : T(1);
   const cx<T>* c = xc + C.off;
-  auto at = [&](int a, int b, int d) { return c[((int64_t)a * ncy + b) * ncz + d]; };
+  auto at = [&](int a, int b, int d) { return c[((int64_t)a * ncy + b) * cpz + d]; };
   cx<T> s2 = at(i0, j0, k0);
   if (k & 1) s2 = s2 + at(i0, j0, k1);
   if (j & 1) {
@@ -116,14 +122,18 @@ __global__ __launch_bounds__(256) void k_inject_model(const Seg* __restrict__ fs
   const Seg& F = fsegs[sid];
   const int64_t pc = (int64_t)(wg - C.tblk0) * 256 + threadIdx.x;
   if (pc >= C.N) return;
-  const int ncy = C.n[1], ncz = C.n[2];
-  const int K = (int)(pc % ncz);
-  const int J = (int)((pc / ncz) % ncy);
-  const int I = (int)(pc / ((int64_t)ncy * ncz));
+  const int ncy = C.n[1], ncz = C.n[2], cpz = C.pz;
+  const int K = (int)(pc % cpz);
+  const int J = (int)((pc / cpz) % ncy);
+  const int I = (int)(pc / ((int64_t)ncy * cpz));
+  TM* mc = reinterpret_cast<TM*>(const_cast<void*>(C.m));
+  if (K >= ncz) {
+    mc[pc] = TM(0);
+    return;
+  }
   const int i = min(2 * I, F.n[0] - 1), j = min(2 * J, F.n[1] - 1), k = min(2 * K, F.n[2] - 1);
   const TM* mf = reinterpret_cast<const TM*>(F.m);
-  TM* mc = reinterpret_cast<TM*>(const_cast<void*>(C.m));
-  mc[pc] = mf[((int64_t)i * F.n[1] + j) * F.n[2] + k];
+  mc[pc] = mf[((int64_t)i * F.n[1] + j) * F.pz + k];
 }
 
 }  // namespace helm
