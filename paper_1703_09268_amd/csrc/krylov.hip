@@ -22,7 +22,8 @@
 
 namespace helm {
 
-constexpr int DOT_BLOCKS = 240;  // largest number of vector workgroups per segment
+constexpr int DOT_BLOCKS = 240;        // default cap of vector workgroups per segment
+constexpr int DOT_BLOCKS_MAX = 4096;   // hard cap (reducers loop over any count)
 
 // Up to KMAX+1 vector pointers (element Seg::off + p of each).
 template <typename T>
@@ -164,19 +165,22 @@ __global__ __launch_bounds__(256) void k_dots(const Seg* __restrict__ segs, cons
     out[threadIdx.x] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
 }
 
-// One workgroup per segment: H[i][j] = scale_i * sum of partials,
+// One workgroup per segment: H[i][j] = scale_i * sum of partials (of the
+// workgroup range `which`: the vector pass or the fused stencil pass),
 // coef_i = H[i][j] * scale_i.
 template <int NVMAX, bool EXACT>
 __global__ __launch_bounds__(256) void k_reduce_dots(const Seg* __restrict__ segs, KState st, int nv, int j,
-                                                     const int* __restrict__ active) {
+                                                     int which, const int* __restrict__ active) {
   __shared__ double red[4 * 2 * NVMAX];
   const int sid = blockIdx.x;
   if (active && !active[sid]) return;
   const Seg& S = segs[sid];
   const int ns = st.nseg;
   if (EXACT) nv = NVMAX;
+  int b0, nb;
+  seg_range(S, which, b0, nb);
   double s[2 * NVMAX];
-  seg_sums<2 * NVMAX, EXACT>(st.part, S.vblk0, S.vnblk, 2 * nv, s, red);
+  seg_sums<2 * NVMAX, EXACT>(st.part, b0, nb, 2 * nv, s, red);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int i = 0; i < NVMAX; ++i) {

@@ -210,6 +210,16 @@ inline int choose_xchunk(const std::vector<Seg>& segs) {
   return std::max(4, std::min(xchunk, nxmax));
 }
 
+// Largest number of vector-kernel workgroups per segment (grid-stride over
+// the segment).  HELM_VEC_WG overrides it (tile experiments).
+inline int vector_blocks_cap() {
+  if (const char* e = std::getenv("HELM_VEC_WG")) {
+    const int v = std::atoi(e);
+    if (v >= 1 && v <= DOT_BLOCKS_MAX) return v;
+  }
+  return DOT_BLOCKS;
+}
+
 // The operator hierarchy of a list of problems: tables, segments, maps,
 // coarse models.
 class Hierarchy {
@@ -307,6 +317,7 @@ class Hierarchy {
       }
       // workgroup ranges
       const int xchunk = choose_xchunk(L.host);
+      const int vcap = vector_blocks_cap();
       int sb = 0, vb = 0, tb = 0;
       for (int s = 0; s < ns; ++s) {
         Seg& S = L.host[s];
@@ -316,7 +327,7 @@ class Hierarchy {
         S.snblk = stencil_ == 0 ? S.plane_blocks * S.nxc : 0;
         sb += S.snblk;
         S.vblk0 = vb;
-        S.vnblk = (int)std::min<int64_t>(DOT_BLOCKS, ceil_div(S.N, 256));
+        S.vnblk = (int)std::min<int64_t>(vcap, ceil_div(S.N, 256));
         vb += S.vnblk;
         S.tblk0 = tb;
         S.tnblk = (int)ceil_div(S.N, 256);
@@ -449,13 +460,54 @@ void launch_h(const LevelSet& L, const cx<TX>* x, const double* xs, const cx<TB>
     hipLaunchKernelGGL((k_h27<TC, TX, TM, TB, TO, RESID, NORM>), dim3(L.ntblk), dim3(256), 0, st, L.d(),
                        L.tmap.as<const int>(), x, xs, b, bs, out, part, active);
   } else if (all_f32 && L.pair && aligned16(x) && aligned16(out) && (!RESID || aligned16(b))) {
-    hipLaunchKernelGGL((k_h7p<RESID, NORM>), dim3(L.nsblk), dim3(256), 0, st, L.d(), L.smap.as<const int>(),
-                       L.slocal.as<const int>(), reinterpret_cast<const c32*>(x), xs,
-                       reinterpret_cast<const c32*>(b), bs, reinterpret_cast<c32*>(out), part, active);
+    hipLaunchKernelGGL((k_h7p<RESID, NORM, 0, false>), dim3(L.nsblk), dim3(256), 0, st, L.d(),
+                       L.smap.as<const int>(), L.slocal.as<const int>(), reinterpret_cast<const c32*>(x), xs,
+                       reinterpret_cast<const c32*>(b), bs, reinterpret_cast<c32*>(out), part, active,
+                       VecPtrs{});
   } else {
     hipLaunchKernelGGL((k_h7<TC, TX, TM, TB, TO, RESID, NORM>), dim3(L.nsblk), dim3(256), 0, st, L.d(),
                        L.smap.as<const int>(), L.slocal.as<const int>(), x, xs, b, bs, out, part, active);
   }
+}
+
+// out = s_x H x together with the partial inner products of out with
+// D[0..nmem) and, when self, with x itself (last); complex64 pair tiles only.
+// Returns false (nothing launched) when the level or the buffers do not allow
+// the fused pass; the caller then runs the separate inner-product kernel.
+template <int NMEM, bool SELF>
+void launch_h_dots_n(const LevelSet& L, const c32* x, const double* xs, c32* out, const VecPtrs& D,
+                     double* part, const int* active, hipStream_t st) {
+  hipLaunchKernelGGL((k_h7p<false, false, NMEM, SELF>), dim3(L.nsblk), dim3(256), 0, st, L.d(),
+                     L.smap.as<const int>(), L.slocal.as<const int>(), x, xs, (const c32*)nullptr,
+                     (const double*)nullptr, out, part, active, D);
+}
+
+inline bool launch_h_dots(const LevelSet& L, const c32* x, const double* xs, c32* out, const c32* const* D,
+                          int nmem, bool self, double* part, const int* active, hipStream_t st) {
+  if (L.stencil != 0 || !L.pair || !aligned16(x) || !aligned16(out)) return false;
+  if (nmem < 0 || nmem > 5 || nmem + (self ? 1 : 0) < 1) return false;
+  VecPtrs v{};
+  for (int t = 0; t < nmem; ++t) {
+    if (!aligned16(D[t])) return false;
+    v.v[t] = D[t];
+  }
+#define HELM_HD(NM)                                                                                   \
+  case NM:                                                                                           \
+    if (self) launch_h_dots_n<NM, true>(L, x, xs, out, v, part, active, st);                        \
+    else launch_h_dots_n<NM, false>(L, x, xs, out, v, part, active, st);                            \
+    return true;
+  switch (nmem) {
+    HELM_HD(1)
+    HELM_HD(2)
+    HELM_HD(3)
+    HELM_HD(4)
+    HELM_HD(5)
+    case 0:
+      launch_h_dots_n<0, true>(L, x, xs, out, v, part, active, st);
+      return true;
+  }
+#undef HELM_HD
+  return false;
 }
 
 }  // namespace helm

@@ -52,6 +52,14 @@ struct VRef {
   const double* s;  // per-segment scale (null = 1)
 };
 
+// The complex64 7-point Arnoldi steps form their inner products inside the
+// stencil pass; HELM_FUSED_DOTS=0 runs the separate pass instead (A/B
+// measurements).
+inline bool fused_dots_enabled() {
+  const char* e = std::getenv("HELM_FUSED_DOTS");
+  return !(e && e[0] == '0');
+}
+
 inline bool graphs_enabled() {
   const char* e = std::getenv("HELM_GRAPH");
   return !(e && e[0] == '0');
@@ -338,48 +346,69 @@ class Solver {
     update_x<double>(outer_, X_);
   }
 
-  // NV: exact vector count when EXACT, else an upper bound of nv
+  // Inner products of column j (unless the stencil pass formed them:
+  // fused), then w -= sum coef_i V_i with ||w||^2, and the Givens step.
+  // NV: exact vector count when EXACT, else an upper bound of nv.
   template <int NV, bool EXACT>
-  void dots_axpy(Space& S, int nv, int j, cx<T>* w) {
+  void dots_axpy(Space& S, int nv, int j, cx<T>* w, bool fused) {
     const LevelSet& L = H_->level(S.lvl);
     VecList<T> vl;
     vl.v[0] = S.v0;
     for (int i = 1; i < nv; ++i) vl.v[i] = S.V[i];
-    hipLaunchKernelGGL((k_dots<T, NV, EXACT>), dim3(L.nvblk), dim3(256), 0, st_, L.d(), L.vmap.as<const int>(), vl,
-                       nv, (const cx<T>*)w, part_, (const int*)active_);
+    if (!fused)
+      hipLaunchKernelGGL((k_dots<T, NV, EXACT>), dim3(L.nvblk), dim3(256), 0, st_, L.d(), L.vmap.as<const int>(),
+                         vl, nv, (const cx<T>*)w, part_, (const int*)active_);
     hipLaunchKernelGGL((k_reduce_dots<NV, EXACT>), dim3(nseg_), dim3(256), 0, st_, L.d(), S.ks, nv, j,
-                       (const int*)active_);
+                       fused ? (int)PR_STENCIL : (int)PR_VECTOR, (const int*)active_);
     hipLaunchKernelGGL((k_axpy_norm<T, NV, EXACT>), dim3(L.nvblk), dim3(256), 0, st_, L.d(),
                        L.vmap.as<const int>(), vl, nv, w, S.ks, (const int*)active_);
     hipLaunchKernelGGL(k_givens, dim3(nseg_), dim3(256), 0, st_, L.d(), S.ks, j, (const int*)active_);
   }
 
+  // w = s_x H x with, where the level allows it, the inner products of w
+  // with the basis V_0..V_j in the same pass (x itself is V_j for GMRES).
+  bool apply_arnoldi(Space& S, int j, const cx<T>* x, const double* xs, cx<T>* w) {
+    const LevelSet& L = H_->level(S.lvl);
+    bool fused = false;
+    if (std::is_same<T, float>::value && fused_dots_) {
+      const c32* D[6];
+      const bool self = !S.flex;  // GMRES: x is the basis vector V_j
+      const int nmem = self ? j : j + 1;
+      if (nmem <= 5) {
+        for (int i = 0; i < nmem; ++i) D[i] = reinterpret_cast<const c32*>(i == 0 ? S.v0 : S.V[i]);
+        fused = launch_h_dots(L, reinterpret_cast<const c32*>(x), xs, reinterpret_cast<c32*>(w), D, nmem, self,
+                              part_, active_, st_);
+      }
+    }
+    if (!fused)
+      launch_h<T, T, T, T, T, false, false>(L, x, xs, (const cx<T>*)nullptr, nullptr, w, nullptr, active_, st_);
+    return fused;
+  }
+
   // Arnoldi column j of space S from basis vector vj (with scale).
   void arnoldi_step(Space& S, int j, VRef<T> vj, bool precond) {
-    const LevelSet& L = H_->level(S.lvl);
     cx<T>* w = S.V[j + 1];
+    bool fused;
     if (S.flex) {
       HELM_REQUIRE(precond, "flexible space without preconditioner");
       vcycle(S.lvl, vj, S.Z[j]);
-      launch_h<T, T, T, T, T, false, false>(L, S.Z[j], nullptr, (const cx<T>*)nullptr, nullptr, w, nullptr,
-                                            active_, st_);
+      fused = apply_arnoldi(S, j, S.Z[j], nullptr, w);
     } else {
-      launch_h<T, T, T, T, T, false, false>(L, vj.p, vj.s, (const cx<T>*)nullptr, nullptr, w, nullptr, active_,
-                                            st_);
+      fused = apply_arnoldi(S, j, vj.p, vj.s, w);
     }
     if (S.lvl == 0) fine_mv_++;
     const int nv = j + 1;
     switch (nv) {
-      case 1: dots_axpy<1, true>(S, nv, j, w); break;
-      case 2: dots_axpy<2, true>(S, nv, j, w); break;
-      case 3: dots_axpy<3, true>(S, nv, j, w); break;
-      case 4: dots_axpy<4, true>(S, nv, j, w); break;
-      case 5: dots_axpy<5, true>(S, nv, j, w); break;
-      case 6: dots_axpy<6, true>(S, nv, j, w); break;
+      case 1: dots_axpy<1, true>(S, nv, j, w, fused); break;
+      case 2: dots_axpy<2, true>(S, nv, j, w, fused); break;
+      case 3: dots_axpy<3, true>(S, nv, j, w, fused); break;
+      case 4: dots_axpy<4, true>(S, nv, j, w, fused); break;
+      case 5: dots_axpy<5, true>(S, nv, j, w, fused); break;
+      case 6: dots_axpy<6, true>(S, nv, j, w, fused); break;
       default:
-        if (nv <= 11) dots_axpy<11, false>(S, nv, j, w);
-        else if (nv <= 21) dots_axpy<21, false>(S, nv, j, w);
-        else dots_axpy<33, false>(S, nv, j, w);
+        if (nv <= 11) dots_axpy<11, false>(S, nv, j, w, fused);
+        else if (nv <= 21) dots_axpy<21, false>(S, nv, j, w, fused);
+        else dots_axpy<33, false>(S, nv, j, w, fused);
     }
   }
 
@@ -468,6 +497,7 @@ class Solver {
   std::vector<Space> smooth_, coarse_;
   std::vector<cx<T>*> R_, B_, Xc_;
   int64_t fine_mv_ = 0, body_mv_ = 0;
+  bool fused_dots_ = fused_dots_enabled();
   hipGraph_t graph_ = nullptr;
   hipGraphExec_t exec_ = nullptr;
 };

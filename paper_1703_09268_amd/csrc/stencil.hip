@@ -212,20 +212,36 @@ struct alignas(16) c32x2 {
   float a, b, c, d;  // (re, im) of element 0, then of element 1
 };
 
-template <bool RESID, bool NORM>
+// level vectors an Arnoldi stencil pass takes inner products with
+struct VecPtrs {
+  const c32* v[6];
+};
+
+//
+// Arnoldi variant (NMEM + SELF > 0, plain H x only): the same pass also forms
+// the workgroup's partial inner products s_t = sum conj(D_t) out over its
+// points, for D_t = Vd.v[t] (t < NMEM, read from memory) and, with SELF, the
+// stored input x itself as the last one; they go to
+// part[(sblk0 + local) * PSTRIDE + 2t (+1)] (re, im).  This replaces a
+// separate pass that would read the output back.
+template <bool RESID, bool NORM, int NMEM, bool SELF>
 __global__ __launch_bounds__(256) void k_h7p(const Seg* __restrict__ segs, const int* __restrict__ smap,
                                              const int* __restrict__ slocal, const c32* __restrict__ x,
                                              const double* __restrict__ xs, const c32* __restrict__ b,
                                              const double* __restrict__ bs, c32* __restrict__ out,
-                                             double* __restrict__ part, const int* __restrict__ active) {
-  __shared__ double red[16];
+                                             double* __restrict__ part, const int* __restrict__ active,
+                                             VecPtrs Vd) {
+  constexpr int ND = NMEM + (SELF ? 1 : 0);
+  static_assert(!(ND > 0 && (RESID || NORM)), "inner products only with the plain operator");
+  __shared__ double red[ND > 0 ? 4 * 2 * ND : 16];
   const int wg = xcd_logical(blockIdx.x, gridDim.x);
   const int sid = smap[wg];
   const int local = slocal[wg];
   const Seg& S = segs[sid];
-  double* const pslot = NORM ? part + (int64_t)(S.sblk0 + local) * PSTRIDE : nullptr;
+  double* const pslot = (NORM || ND > 0) ? part + (int64_t)(S.sblk0 + local) * PSTRIDE : nullptr;
   if (active && !active[sid]) {
     if (NORM && threadIdx.x == 0) *pslot = 0.0;
+    if (ND > 0 && threadIdx.x < 2 * ND) pslot[threadIdx.x] = 0.0;
     return;
   }
   const int nx = S.n[0], nz = S.n[2], pz = S.pz;
@@ -265,11 +281,18 @@ __global__ __launch_bounds__(256) void k_h7p(const Seg* __restrict__ segs, const
   const int i1 = min(nx, i0 + S.xchunk);
   double nrm = 0.0;
   const double wn = in ? 1.0 : 0.0;  // norm weight (duplicates count zero)
+  double dr[ND > 0 ? ND : 1], di[ND > 0 ? ND : 1];
+#pragma unroll
+  for (int t = 0; t < ND; ++t) dr[t] = di[t] = 0.0;
+  const float wf = in ? 1.0f : 0.0f;
   // One plane: qm, qc, qp hold x planes i-1, i, i+1; qn receives plane i+2.
   auto step = [&](int i, const c32x2& qm, const c32x2& qc, const c32x2& qp, c32x2& qn) {
     const int64_t pl = (int64_t)i * plane;
     // this plane's loads first, then the prefetch of plane i+2 (vector
     // loads complete in order, so waiting for these leaves it in flight)
+    c32x2 dv[NMEM > 0 ? NMEM : 1];
+#pragma unroll
+    for (int t = 0; t < NMEM; ++t) dv[t] = *reinterpret_cast<const c32x2*>(Vd.v[t] + S.off + pl + e0);
     const c32x2 ym = L2(i, oym), yp = L2(i, oyp);
     const c32 zm = xr[pl + ozm], zp = xr[pl + ozp];
     const float2 mv = mp[pl >> 1];  // plane is even
@@ -306,6 +329,15 @@ __global__ __launch_bounds__(256) void k_h7p(const Seg* __restrict__ segs, const
     if (NORM)
       nrm += wn * ((double)a0.re * (double)a0.re + (double)a0.im * (double)a0.im +
                    ((double)a1.re * (double)a1.re + (double)a1.im * (double)a1.im));
+    if (ND > 0) {
+      const c32 u0 = wf * a0, u1 = wf * a1;  // duplicates count zero
+#pragma unroll
+      for (int t = 0; t < ND; ++t) {
+        const c32x2 v = (SELF && t == ND - 1) ? qc : dv[t < NMEM ? t : 0];
+        dr[t] += (double)v.a * u0.re + (double)v.b * u0.im + ((double)v.c * u1.re + (double)v.d * u1.im);
+        di[t] += (double)v.a * u0.im - (double)v.b * u0.re + ((double)v.c * u1.im - (double)v.d * u1.re);
+      }
+    }
   };
   c32x2 qm = L2(max(i0 - 1, 0), e0), qc = L2(i0, e0), qp = L2(min(i0 + 1, nx - 1), e0), qn;
   for (int i = i0; i < i1; ++i) {
@@ -317,6 +349,22 @@ __global__ __launch_bounds__(256) void k_h7p(const Seg* __restrict__ segs, const
   if (NORM) {
     const double s = block_sum(nrm, red);
     if (threadIdx.x == 0) *pslot = s;
+  }
+  if (ND > 0) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int t = 0; t < ND; ++t) {
+      const double sr = wave_sum(dr[t]);
+      const double si = wave_sum(di[t]);
+      if (lane == 0) {
+        red[wid * 2 * ND + 2 * t] = sr;
+        red[wid * 2 * ND + 2 * t + 1] = si;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * ND)
+      pslot[threadIdx.x] = red[threadIdx.x] + red[2 * ND + threadIdx.x] + red[4 * ND + threadIdx.x] +
+                           red[6 * ND + threadIdx.x];
   }
 }
 
