@@ -129,6 +129,47 @@ def cpu_baseline(w, m32, src, rec, omega, target_s=0.0):
     return dt, steps
 
 
+def copy_timing(torch, n_elems, reps, dev):
+    """Achieved GB/s of a plain device copy of two complex64 buffers of
+    n_elems (read + write), HIP events on the current stream: the practical
+    ceiling for a streaming kernel."""
+    xs = [torch.randn(n_elems, dtype=torch.complex64, device=dev) for _ in range(2)]
+    ys = [torch.empty_like(xs[0]) for _ in range(2)]
+    for i in range(3):
+        ys[i % 2].copy_(xs[i % 2])
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for i in range(reps):
+        ys[i % 2].copy_(xs[i % 2])
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return ms, 16.0 * n_elems / (ms * 1e-3) / 1e9
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stencil7_pair_c2_128cube_16rhs_hbm_traffic.txt")
+STENCIL_SOURCE = os.path.join(ROOT, "paper_1703_09268_amd", "csrc", "stencil.hip")
+
+
+def measured_traffic():
+    """HBM bytes per stencil launch from the committed hardware-counter
+    summary, if it was taken on the current stencil source (sha256 match);
+    otherwise None."""
+    import hashlib
+    try:
+        with open(STENCIL_SOURCE, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+        with open(TRAFFIC_FILE) as f:
+            rec = json.loads([ln for ln in f if ln.startswith("{")][-1])
+    except (OSError, ValueError, IndexError):
+        return None
+    if rec.get("stencil_source_sha256") != digest:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
 def stencil_timing(hx, torch, grid, m_t, w, S, reps, dev):
     """Average duration of the stencil kernel (helm_apply with S right-hand
     sides: one kernel launch each) from HIP events recorded on the launch
@@ -167,7 +208,9 @@ def main():
         grid = hx.Grid(n=w.n, h=w.h, npml=w.npml, v_ref=w.v_ref, dtype="c64")
         m_t = torch.tensor(w.m, dtype=torch.float32, device=dev)
         ms, gbs = stencil_timing(hx, torch, grid, m_t, w, len(w.src), args.stencil_reps, dev)
-        print(json.dumps({"stencil_ms_per_launch": ms, "GB_s": gbs}), flush=True)
+        cms, cgbs = copy_timing(torch, len(w.src) * w.N, args.stencil_reps, dev)
+        print(json.dumps({"stencil_ms_per_launch": ms, "GB_s": gbs, "copy_ms": cms, "copy_GB_s": cgbs,
+                          "copy_bytes_per_launch": 16 * len(w.src) * w.N}), flush=True)
         return
     nsrc = len(w.src)
     rec = workloads.surface_positions(w.n, w.npml, (args.nrec, args.nrec))
@@ -209,6 +252,8 @@ def main():
     # ---- stencil kernel alone: 16 right-hand sides, HIP events on the stream
     S = nsrc
     st_ms, gbs = stencil_timing(hx, torch, grid, m_t, w, S, args.stencil_reps, dev)
+    cp_ms, cp_gbs = copy_timing(torch, S * w.N, args.stencil_reps, dev)
+    traffic = measured_traffic()
     batch = None if args.no_batch else batched_vs_plain(hx, torch, workloads, args.batch_count, dev)
 
     out = {
@@ -238,18 +283,22 @@ def main():
         },
         "batched_vs_plain": batch,
         "stencil": {
-            "kernel": "k_h7<float,...> (helm_apply, 16 rhs)",
+            "kernel": "k_h7p<false,false,0,false> (helm_apply: complex64 7-point, pair tiles, 16 rhs)",
             "ms_per_launch": round(st_ms, 5), "GB_s": round(gbs, 1),
             "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
             "bytes_per_point": f"16*{S}+4",
+            "algorithmic_bytes_per_launch": (16 * S + 4) * w.N,
+            "copy_ceiling_GB_s": round(cp_gbs, 1),
         },
         "roofline": {
             "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
         },
     }
     if not args.no_cpu_baseline:
-        dt, nst = cpu_baseline(w, m_t.double().cpu().numpy(), w.src, rec, w.omega)
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):  # the oracle as written, one core
+            dt, nst = cpu_baseline(w, m_t.double().cpu().numpy(), w.src, rec, w.omega)
         steps_per_solve = 5.0 * float(np.mean(cycles))
         out["cpu_baseline"] = {
             "value": round(1.0 / (dt * steps_per_solve), 6), "unit": "solves/s",

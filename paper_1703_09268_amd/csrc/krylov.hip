@@ -165,22 +165,85 @@ __global__ __launch_bounds__(256) void k_dots(const Seg* __restrict__ segs, cons
     out[threadIdx.x] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
 }
 
+// 1/||w|| from ||w||^2 (0 on breakdown)
+__device__ __forceinline__ double basis_scale(double s) {
+  const double hn = sqrt(s);
+  return hn > 0.0 ? 1.0 / hn : 0.0;
+}
+
+// Finish Arnoldi column j of segment sid from s = ||w||^2 (sum of the
+// partials): h_{j+1,j} = sqrt(s); apply the previous rotations to column j,
+// build rotation j, update g, set scale_{j+1} = 1/h_{j+1,j} (0 on
+// breakdown).  One thread.
+__device__ __forceinline__ void givens_column(const KState& st, int sid, int j, double s) {
+  const int ns = st.nseg;
+  const double hn = sqrt(s);
+  for (int i = 0; i < j; ++i) {
+    const double2 a = st.H[(i * KMAX + j) * ns + sid];
+    const double2 b = st.H[((i + 1) * KMAX + j) * ns + sid];
+    const double c = st.cs[i * ns + sid];
+    const double2 sn = st.sn[i * ns + sid];
+    // [c, s; -conj(s), c] [a; b]
+    const double2 na = d2(c * a.x + (sn.x * b.x - sn.y * b.y), c * a.y + (sn.x * b.y + sn.y * b.x));
+    const double2 nb = d2(-(sn.x * a.x + sn.y * a.y) + c * b.x, -(sn.x * a.y - sn.y * a.x) + c * b.y);
+    st.H[(i * KMAX + j) * ns + sid] = na;
+    st.H[((i + 1) * KMAX + j) * ns + sid] = nb;
+  }
+  const double2 a = st.H[(j * KMAX + j) * ns + sid];
+  const double absa = hypot(a.x, a.y);
+  double c;
+  double2 sn, rr;
+  if (hn == 0.0) {
+    c = 1.0;
+    sn = d2(0.0, 0.0);
+    rr = a;
+  } else if (absa == 0.0) {
+    c = 0.0;
+    sn = d2(1.0, 0.0);  // conj(b)/|b| with b = hn real
+    rr = d2(hn, 0.0);
+  } else {
+    const double nrm = hypot(absa, hn);
+    c = absa / nrm;
+    const double2 ph = d2(a.x / absa, a.y / absa);
+    sn = d2(ph.x * hn / nrm, ph.y * hn / nrm);  // (a/|a|) conj(b)/nrm, b real
+    rr = d2(ph.x * nrm, ph.y * nrm);
+  }
+  st.cs[j * ns + sid] = c;
+  st.sn[j * ns + sid] = sn;
+  st.H[(j * KMAX + j) * ns + sid] = rr;
+  st.H[((j + 1) * KMAX + j) * ns + sid] = d2(0.0, 0.0);
+  const double2 gj = st.g[j * ns + sid];
+  // g_{j+1} = -conj(s) g_j ; g_j = c g_j
+  st.g[(j + 1) * ns + sid] = d2(-(sn.x * gj.x + sn.y * gj.y), -(sn.x * gj.y - sn.y * gj.x));
+  st.g[j * ns + sid] = d2(c * gj.x, c * gj.y);
+  st.scale[(j + 1) * ns + sid] = basis_scale(s);
+}
+
 // One workgroup per segment: H[i][j] = scale_i * sum of partials (of the
 // workgroup range `which`: the vector pass or the fused stencil pass),
 // coef_i = H[i][j] * scale_i.
+// With gprev >= 0 the deferred Givens step of column gprev (= j - 1) runs
+// first, from the partial norms in the vector range of st.part; the
+// inner-product partials come from `src` (range `which`).
 template <int NVMAX, bool EXACT>
 __global__ __launch_bounds__(256) void k_reduce_dots(const Seg* __restrict__ segs, KState st, int nv, int j,
-                                                     int which, const int* __restrict__ active) {
-  __shared__ double red[4 * 2 * NVMAX];
+                                                     int which, const double* __restrict__ src, int gprev,
+                                                     const int* __restrict__ active) {
+  __shared__ double red[4 * 2 * NVMAX > 4 ? 4 * 2 * NVMAX : 4];
   const int sid = blockIdx.x;
   if (active && !active[sid]) return;
   const Seg& S = segs[sid];
   const int ns = st.nseg;
   if (EXACT) nv = NVMAX;
+  if (gprev >= 0) {
+    const double sn = seg_sum0(st.part, S.vblk0, S.vnblk, red);
+    if (threadIdx.x == 0) givens_column(st, sid, gprev, sn);
+    __syncthreads();  // red is reused below
+  }
   int b0, nb;
   seg_range(S, which, b0, nb);
   double s[2 * NVMAX];
-  seg_sums<2 * NVMAX, EXACT>(st.part, b0, nb, 2 * nv, s, red);
+  seg_sums<2 * NVMAX, EXACT>(src, b0, nb, 2 * nv, s, red);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int i = 0; i < NVMAX; ++i) {
@@ -319,9 +382,7 @@ __global__ __launch_bounds__(256) void k_start_cycle(const Seg* __restrict__ seg
   }
 }
 
-// Finish Arnoldi column j: h_{j+1,j} = sqrt(sum partials); apply the
-// previous rotations to column j, build rotation j, update g, set
-// scale_{j+1} = 1/h_{j+1,j} (0 on breakdown).
+// Finish Arnoldi column j (partials of the vector range of st.part).
 __global__ __launch_bounds__(256) void k_givens(const Seg* __restrict__ segs, KState st, int j,
                                                 const int* __restrict__ active) {
   __shared__ double red[4];
@@ -329,48 +390,7 @@ __global__ __launch_bounds__(256) void k_givens(const Seg* __restrict__ segs, KS
   if (active && !active[sid]) return;
   const Seg& S = segs[sid];
   const double s = seg_sum0(st.part, S.vblk0, S.vnblk, red);
-  if (threadIdx.x != 0) return;
-  const int ns = st.nseg;
-  const double hn = sqrt(s);
-  for (int i = 0; i < j; ++i) {
-    const double2 a = st.H[(i * KMAX + j) * ns + sid];
-    const double2 b = st.H[((i + 1) * KMAX + j) * ns + sid];
-    const double c = st.cs[i * ns + sid];
-    const double2 sn = st.sn[i * ns + sid];
-    // [c, s; -conj(s), c] [a; b]
-    const double2 na = d2(c * a.x + (sn.x * b.x - sn.y * b.y), c * a.y + (sn.x * b.y + sn.y * b.x));
-    const double2 nb = d2(-(sn.x * a.x + sn.y * a.y) + c * b.x, -(sn.x * a.y - sn.y * a.x) + c * b.y);
-    st.H[(i * KMAX + j) * ns + sid] = na;
-    st.H[((i + 1) * KMAX + j) * ns + sid] = nb;
-  }
-  const double2 a = st.H[(j * KMAX + j) * ns + sid];
-  const double absa = hypot(a.x, a.y);
-  double c;
-  double2 sn, rr;
-  if (hn == 0.0) {
-    c = 1.0;
-    sn = d2(0.0, 0.0);
-    rr = a;
-  } else if (absa == 0.0) {
-    c = 0.0;
-    sn = d2(1.0, 0.0);  // conj(b)/|b| with b = hn real
-    rr = d2(hn, 0.0);
-  } else {
-    const double nrm = hypot(absa, hn);
-    c = absa / nrm;
-    const double2 ph = d2(a.x / absa, a.y / absa);
-    sn = d2(ph.x * hn / nrm, ph.y * hn / nrm);  // (a/|a|) conj(b)/nrm, b real
-    rr = d2(ph.x * nrm, ph.y * nrm);
-  }
-  st.cs[j * ns + sid] = c;
-  st.sn[j * ns + sid] = sn;
-  st.H[(j * KMAX + j) * ns + sid] = rr;
-  st.H[((j + 1) * KMAX + j) * ns + sid] = d2(0.0, 0.0);
-  const double2 gj = st.g[j * ns + sid];
-  // g_{j+1} = -conj(s) g_j ; g_j = c g_j
-  st.g[(j + 1) * ns + sid] = d2(-(sn.x * gj.x + sn.y * gj.y), -(sn.x * gj.y - sn.y * gj.x));
-  st.g[j * ns + sid] = d2(c * gj.x, c * gj.y);
-  st.scale[(j + 1) * ns + sid] = hn > 0.0 ? 1.0 / hn : 0.0;
+  if (threadIdx.x == 0) givens_column(st, sid, j, s);
 }
 
 // Back substitution R y = g (k x k upper triangular, zero pivots -> y_i = 0).

@@ -485,6 +485,11 @@ helm_status helm_apply(helm_ctx* ctx, const helm_grid* g, const void* m, double 
       if (ctx->apply_h) HELM_HIP_CHECK(hipDeviceSynchronize());
       ctx->apply_h.reset(new helm::Hierarchy(probs, 1, g->dtype == HELM_C64 ? 4 : 8, st));
       ctx->apply_key = key;
+      // stencil tiles, timed on the caller's buffers (y is overwritten below)
+      if (g->dtype == HELM_C64)
+        helm::tune_tiles_apply<float>(*ctx->apply_h, (const helm::cx<float>*)x, (helm::cx<float>*)y, st);
+      else
+        helm::tune_tiles_apply<double>(*ctx->apply_h, (const helm::cx<double>*)x, (helm::cx<double>*)y, st);
     }
     const helm::LevelSet& L = ctx->apply_h->level(0);
     if (g->dtype == HELM_C64)

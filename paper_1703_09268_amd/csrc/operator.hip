@@ -13,8 +13,11 @@
 #include <cmath>
 #include <complex>
 #include <cstdlib>
+#include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <memory>
 #include <string>
 #include <type_traits>
@@ -177,11 +180,15 @@ struct LevelSet {
   std::vector<Seg> host;
   DevBuf segs, smap, slocal, vmap, tmap, own;
   int nsblk = 0, nvblk = 0, ntblk = 0;
-  bool pair = false;  // every segment uses pair stencil tiles
+  int sblk_bound = 1;  // stencil workgroups at the smallest x chunk
+  int xchunk = 0;      // current x chunk of the stencil tiles
+  bool pair = false;   // every segment uses pair stencil tiles
   int64_t total = 0;  // vector length (sum of N)
   std::vector<std::unique_ptr<DevBuf>> models;  // owned coarse models
   const Seg* d() const { return segs.as<const Seg>(); }
 };
+
+constexpr int kMinXchunk = 4;  // smallest x chunk of a stencil tile
 
 // x-chunk (planes per stencil workgroup) for a level: about `target`
 // workgroups over the level (a few per wave slot of the chip), at least 4
@@ -190,7 +197,7 @@ struct LevelSet {
 inline int choose_xchunk(const std::vector<Seg>& segs) {
   if (const char* e = std::getenv("HELM_XCHUNK")) {
     const int v = std::atoi(e);
-    if (v >= 1) return v;
+    if (v >= kMinXchunk) return v;
   }
   // measured on 128^3 and 65x65x66 with 16 right-hand sides: pair tiles
   // prefer longer marches (2048 workgroups), one-point tiles 8192
@@ -315,17 +322,11 @@ class Hierarchy {
           L.host[s].m = L.host[mown[s]].m;
         }
       }
-      // workgroup ranges
-      const int xchunk = choose_xchunk(L.host);
+      // workgroup ranges of the vector and point-wise kernels
       const int vcap = vector_blocks_cap();
-      int sb = 0, vb = 0, tb = 0;
+      int vb = 0, tb = 0;
       for (int s = 0; s < ns; ++s) {
         Seg& S = L.host[s];
-        S.xchunk = xchunk;
-        S.nxc = (S.n[0] + xchunk - 1) / xchunk;
-        S.sblk0 = sb;
-        S.snblk = stencil_ == 0 ? S.plane_blocks * S.nxc : 0;
-        sb += S.snblk;
         S.vblk0 = vb;
         S.vnblk = (int)std::min<int64_t>(vcap, ceil_div(S.N, 256));
         vb += S.vnblk;
@@ -333,38 +334,82 @@ class Hierarchy {
         S.tnblk = (int)ceil_div(S.N, 256);
         tb += S.tnblk;
       }
-      L.nsblk = sb;
       L.nvblk = vb;
       L.ntblk = tb;
-      std::vector<int> smap(std::max(sb, 1)), slocal(std::max(sb, 1)), vmap(std::max(vb, 1)),
-          tmap(std::max(tb, 1));
-      // Stencil workgroups: when every segment of the level has the same
-      // geometry and model (the sources of one frequency), the segments of
-      // one tile get consecutive workgroup ids (segment fastest), so they run
-      // together on one XCD and read that tile of the model once into its L2.
-      bool shared = stencil_ == 0 && ns > 1;
-      for (int s = 1; s < ns && shared; ++s)
-        shared = L.host[s].m == L.host[0].m && L.host[s].n[0] == L.host[0].n[0] &&
-                 L.host[s].n[1] == L.host[0].n[1] && L.host[s].n[2] == L.host[0].n[2];
+      std::vector<int> vmap(std::max(vb, 1)), tmap(std::max(tb, 1));
       for (int s = 0; s < ns; ++s) {
         const Seg& S = L.host[s];
-        for (int b = 0; b < S.snblk; ++b) {
-          const int wg = shared ? b * ns + s : S.sblk0 + b;
-          smap[wg] = s;
-          slocal[wg] = b;
-        }
         for (int b = 0; b < S.vnblk; ++b) vmap[S.vblk0 + b] = s;
         for (int b = 0; b < S.tnblk; ++b) tmap[S.tblk0 + b] = s;
       }
-      upload(L.smap, smap);
-      upload(L.slocal, slocal);
       upload(L.vmap, vmap);
       upload(L.tmap, tmap);
       upload(L.own, own);
       L.segs.ensure(ns * sizeof(Seg));
-      HELM_HIP_CHECK(hipMemcpyAsync(L.segs.p, L.host.data(), ns * sizeof(Seg), hipMemcpyHostToDevice, st));
-      HELM_HIP_CHECK(hipStreamSynchronize(st));
+      // stencil tiles (the x chunk may be re-chosen by the tile tuner)
+      int64_t bound = 0;
+      for (const Seg& S : L.host) bound += (int64_t)S.plane_blocks * ceil_div(S.n[0], kMinXchunk);
+      L.sblk_bound = (int)std::max<int64_t>(bound, 1);
+      L.smap.ensure(L.sblk_bound * sizeof(int));
+      L.slocal.ensure(L.sblk_bound * sizeof(int));
+      layout_stencil(l, choose_xchunk(L.host));
     }
+  }
+
+  // Stencil workgroup layout of level l for x chunk `xchunk`: segment ranges,
+  // workgroup -> (segment, tile) maps, uploaded.  When every segment of the
+  // level has the same geometry and model (the sources of one frequency),
+  // the segments of one tile get consecutive workgroup ids (segment
+  // fastest), so they run together on one XCD and read that tile of the
+  // model once into its L2.
+  void layout_stencil(int l, int xchunk) {
+    LevelSet& L = *lev_[l];
+    const int ns = (int)L.host.size();
+    xchunk = std::max(xchunk, kMinXchunk);
+    int sb = 0;
+    for (int s = 0; s < ns; ++s) {
+      Seg& S = L.host[s];
+      S.xchunk = xchunk;
+      S.nxc = (S.n[0] + xchunk - 1) / xchunk;
+      S.sblk0 = sb;
+      S.snblk = stencil_ == 0 ? S.plane_blocks * S.nxc : 0;
+      sb += S.snblk;
+    }
+    HELM_REQUIRE(sb <= L.sblk_bound, "internal: stencil workgroup bound exceeded");
+    L.nsblk = sb;
+    L.xchunk = xchunk;
+    std::vector<int> smap(std::max(sb, 1)), slocal(std::max(sb, 1));
+    bool shared = stencil_ == 0 && ns > 1;
+    for (int s = 1; s < ns && shared; ++s)
+      shared = L.host[s].m == L.host[0].m && L.host[s].n[0] == L.host[0].n[0] &&
+               L.host[s].n[1] == L.host[0].n[1] && L.host[s].n[2] == L.host[0].n[2];
+    for (int s = 0; s < ns; ++s) {
+      const Seg& S = L.host[s];
+      for (int b = 0; b < S.snblk; ++b) {
+        const int wg = shared ? b * ns + s : S.sblk0 + b;
+        smap[wg] = s;
+        slocal[wg] = b;
+      }
+    }
+    HELM_HIP_CHECK(hipMemcpyAsync(L.smap.p, smap.data(), smap.size() * sizeof(int), hipMemcpyHostToDevice, st_));
+    HELM_HIP_CHECK(
+        hipMemcpyAsync(L.slocal.p, slocal.data(), slocal.size() * sizeof(int), hipMemcpyHostToDevice, st_));
+    HELM_HIP_CHECK(hipMemcpyAsync(L.segs.p, L.host.data(), ns * sizeof(Seg), hipMemcpyHostToDevice, st_));
+    HELM_HIP_CHECK(hipStreamSynchronize(st_));
+  }
+
+  // Key of level l's tile choice: stencil kind, value size and the sorted
+  // list of segment shapes (independent of the order of a batch).
+  std::string tile_key(int l) const {
+    const LevelSet& L = *lev_[l];
+    std::vector<std::string> shapes;
+    for (const Seg& S : L.host)
+      shapes.push_back(std::to_string(S.n[0]) + "x" + std::to_string(S.n[1]) + "x" + std::to_string(S.n[2]) +
+                       "p" + std::to_string(S.pz));
+    std::sort(shapes.begin(), shapes.end());
+    std::string k = std::to_string(stencil_) + ":" + std::to_string(model_bytes_) + ":" + std::to_string(L.pair);
+    for (const auto& x : shapes) k += "," + x;
+    return k;
   }
 
   int nlev() const { return nlev_; }
@@ -401,7 +446,7 @@ class Hierarchy {
   size_t max_partials() const {
     size_t mx = 1;
     for (const auto& L : lev_) {
-      mx = std::max<size_t>(mx, L->nsblk);
+      mx = std::max<size_t>(mx, L->sblk_bound);
       mx = std::max<size_t>(mx, L->nvblk);
       if (stencil_ == 1) mx = std::max<size_t>(mx, L->ntblk);
     }
@@ -463,11 +508,88 @@ void launch_h(const LevelSet& L, const cx<TX>* x, const double* xs, const cx<TB>
     hipLaunchKernelGGL((k_h7p<RESID, NORM, 0, false>), dim3(L.nsblk), dim3(256), 0, st, L.d(),
                        L.smap.as<const int>(), L.slocal.as<const int>(), reinterpret_cast<const c32*>(x), xs,
                        reinterpret_cast<const c32*>(b), bs, reinterpret_cast<c32*>(out), part, active,
-                       VecPtrs{});
+                       VecPtrs{}, (const double*)nullptr);
   } else {
     hipLaunchKernelGGL((k_h7<TC, TX, TM, TB, TO, RESID, NORM>), dim3(L.nsblk), dim3(256), 0, st, L.d(),
                        L.smap.as<const int>(), L.slocal.as<const int>(), x, xs, b, bs, out, part, active);
   }
+}
+
+// Tile tuner (7-point levels): time a stencil launch for a few x chunks and
+// keep the fastest.  The choice is cached per tile key for the process,
+// so one problem set, in any order, always gets the same tiles and hence the
+// same results.  Fixed tiles with HELM_XCHUNK / HELM_STENCIL_WG; off with
+// HELM_AUTOTUNE=0 (heuristic tiles).
+// `run(L)` launches the kernel to time on level L (what the caller runs most
+// there); `kind` names it in the cache key.
+template <typename Run>
+void tune_tiles(Hierarchy& H, const std::string& kind, Run run, hipStream_t st) {
+  static std::mutex mu;
+  static std::map<std::string, int> cache;
+  if (H.stencil() != 0) return;
+  if (std::getenv("HELM_XCHUNK") || std::getenv("HELM_STENCIL_WG")) return;
+  if (const char* e = std::getenv("HELM_AUTOTUNE"))
+    if (e[0] == '0') return;
+  std::lock_guard<std::mutex> guard(mu);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HELM_HIP_CHECK(hipEventCreate(&e0));
+  HELM_HIP_CHECK(hipEventCreate(&e1));
+  try {
+    for (int l = 0; l < H.nlev(); ++l) {
+      const std::string key = kind + "|" + H.tile_key(l);
+      auto it = cache.find(key);
+      if (it != cache.end()) {
+        if (it->second != H.level(l).xchunk) H.layout_stencil(l, it->second);
+        continue;
+      }
+      int nxm = 0;
+      for (const Seg& S : H.level(l).host) nxm = std::max(nxm, S.n[0]);
+      const int reps = H.level(l).total < (int64_t)1 << 24 ? 10 : 3;  // short launches: more samples
+      std::vector<int> cand = {H.level(l).xchunk, nxm, (nxm + 1) / 2, (nxm + 3) / 4, 32, 16, 8, kMinXchunk};
+      std::sort(cand.begin(), cand.end());
+      cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+      int best = H.level(l).xchunk;
+      float best_ms = 1e30f;
+      const bool verbose = std::getenv("HELM_VERBOSE") != nullptr;
+      std::string trace;
+      for (int c : cand) {
+        if (c < kMinXchunk || c > std::max(nxm, kMinXchunk)) continue;
+        H.layout_stencil(l, c);
+        const LevelSet& L = H.level(l);
+        run(L);  // warm
+        HELM_HIP_CHECK(hipEventRecord(e0, st));
+        for (int r = 0; r < reps; ++r) run(L);
+        HELM_HIP_CHECK(hipEventRecord(e1, st));
+        HELM_HIP_CHECK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HELM_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+        if (verbose) trace += " " + std::to_string(c) + ":" + std::to_string(ms / reps * 1e3f) + "us";
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = c;
+        }
+      }
+      if (verbose)
+        fprintf(stderr, "helm tiles %s level %d -> x chunk %d (%s)\n", kind.c_str(), l, best, trace.c_str());
+      H.layout_stencil(l, best);
+      cache[key] = best;
+    }
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
+// Tiles for the plain operator, timed on the caller's a -> b (each at least
+// as long as the level's vectors).
+template <typename T>
+void tune_tiles_apply(Hierarchy& H, const cx<T>* a, cx<T>* b, hipStream_t st) {
+  tune_tiles(H, "apply", [&](const LevelSet& L) {
+    launch_h<T, T, T, T, T, false, false>(L, a, nullptr, (const cx<T>*)nullptr, nullptr, b, nullptr, nullptr, st);
+  }, st);
 }
 
 // out = s_x H x together with the partial inner products of out with
@@ -475,17 +597,24 @@ void launch_h(const LevelSet& L, const cx<TX>* x, const double* xs, const cx<TB>
 // Returns false (nothing launched) when the level or the buffers do not allow
 // the fused pass; the caller then runs the separate inner-product kernel.
 template <int NMEM, bool SELF>
-void launch_h_dots_n(const LevelSet& L, const c32* x, const double* xs, c32* out, const VecPtrs& D,
-                     double* part, const int* active, hipStream_t st) {
+void launch_h_dots_n(const LevelSet& L, const c32* x, const double* xs, const double* npart, c32* out,
+                     const VecPtrs& D, double* part, const int* active, hipStream_t st) {
   hipLaunchKernelGGL((k_h7p<false, false, NMEM, SELF>), dim3(L.nsblk), dim3(256), 0, st, L.d(),
                      L.smap.as<const int>(), L.slocal.as<const int>(), x, xs, (const c32*)nullptr,
-                     (const double*)nullptr, out, part, active, D);
+                     (const double*)nullptr, out, part, active, D, npart);
 }
 
-inline bool launch_h_dots(const LevelSet& L, const c32* x, const double* xs, c32* out, const c32* const* D,
-                          int nmem, bool self, double* part, const int* active, hipStream_t st) {
-  if (L.stencil != 0 || !L.pair || !aligned16(x) || !aligned16(out)) return false;
-  if (nmem < 0 || nmem > 5 || nmem + (self ? 1 : 0) < 1) return false;
+// whether launch_h_dots can run on this level with nmem memory vectors
+inline bool can_fuse_dots(const LevelSet& L, int nmem, bool self) {
+  return L.stencil == 0 && L.pair && nmem >= 0 && nmem <= 5 && nmem + (self ? 1 : 0) >= 1;
+}
+
+// npart (optional): the input scale is 1/||x|| from these vector-range
+// partial norms instead of xs.
+inline bool launch_h_dots(const LevelSet& L, const c32* x, const double* xs, const double* npart, c32* out,
+                          const c32* const* D, int nmem, bool self, double* part, const int* active,
+                          hipStream_t st) {
+  if (!can_fuse_dots(L, nmem, self) || !aligned16(x) || !aligned16(out)) return false;
   VecPtrs v{};
   for (int t = 0; t < nmem; ++t) {
     if (!aligned16(D[t])) return false;
@@ -493,8 +622,8 @@ inline bool launch_h_dots(const LevelSet& L, const c32* x, const double* xs, c32
   }
 #define HELM_HD(NM)                                                                                   \
   case NM:                                                                                           \
-    if (self) launch_h_dots_n<NM, true>(L, x, xs, out, v, part, active, st);                        \
-    else launch_h_dots_n<NM, false>(L, x, xs, out, v, part, active, st);                            \
+    if (self) launch_h_dots_n<NM, true>(L, x, xs, npart, out, v, part, active, st);                 \
+    else launch_h_dots_n<NM, false>(L, x, xs, npart, out, v, part, active, st);                     \
     return true;
   switch (nmem) {
     HELM_HD(1)
@@ -503,7 +632,7 @@ inline bool launch_h_dots(const LevelSet& L, const c32* x, const double* xs, c32
     HELM_HD(4)
     HELM_HD(5)
     case 0:
-      launch_h_dots_n<0, true>(L, x, xs, out, v, part, active, st);
+      launch_h_dots_n<0, true>(L, x, xs, npart, out, v, part, active, st);
       return true;
   }
 #undef HELM_HD

@@ -83,6 +83,7 @@ class Solver {
     nlev_ = (o.method == 1) ? o.levels : 1;
     H_.reset(new Hierarchy(probs, nlev_, sizeof(T), st));
     allocate();
+    tune();
   }
   ~Solver() { drop_graph(); }
 
@@ -263,8 +264,11 @@ class Solver {
       vbytes += (size_t)slots_at(o_, l, nlev_) * vec_bytes(H_->level(l).total);
     const size_t xbytes = round256((size_t)H_->level(0).total * sizeof(cx<double>));
     vec_.ensure(vbytes + xbytes + 256);
-    part_buf_.ensure(H_->max_partials() * PSTRIDE * sizeof(double));
+    // two partial-sum areas: vector passes, and fused stencil passes (which
+    // may read the former while writing)
+    part_buf_.ensure(2 * H_->max_partials() * PSTRIDE * sizeof(double));
     part_ = part_buf_.as<double>();
+    spart_ = part_ + H_->max_partials() * PSTRIDE;
     const int nstates = 1 + 2 * nlev_;
     const size_t per_state = (size_t)(2 * (KMAX + 1) * KMAX + KMAX + 2 * KMAX + 2 * (KMAX + 1) + (KMAX + 1) +
                                       2 * (KMAX + 1)) * nseg_;
@@ -346,11 +350,37 @@ class Solver {
     update_x<double>(outer_, X_);
   }
 
+  // Stencil tiles per level, timed on two level-0 workspace vectors (zeroed
+  // first) with the launch the Arnoldi steps use most: the fused pass with
+  // two basis vectors where the level allows it, else the plain operator.
+  // Only with HELM_AUTOTUNE=1: on the 128^3 16-source solve the heuristic
+  // tiles measured about 1 % faster end to end than the tiles that are
+  // fastest for the isolated launch.
+  void tune() {
+    const char* e = std::getenv("HELM_AUTOTUNE");
+    if (!(e && e[0] == '1')) return;
+    const size_t vb = (size_t)H_->level(0).total * sizeof(cx<T>);
+    HELM_HIP_CHECK(hipMemsetAsync(outer_.V[0], 0, vb, st_));
+    HELM_HIP_CHECK(hipMemsetAsync(outer_.V[1], 0, vb, st_));
+    const cx<T>* a = outer_.V[0];
+    cx<T>* b = outer_.V[1];
+    const bool f32 = std::is_same<T, float>::value;
+    tune_tiles(*H_, f32 && fused_dots_ ? "arnoldi" : "apply", [&](const LevelSet& L) {
+      const c32* D[2] = {reinterpret_cast<const c32*>(a), reinterpret_cast<const c32*>(a)};
+      if (!(f32 && fused_dots_ && launch_h_dots(L, reinterpret_cast<const c32*>(a), nullptr, nullptr,
+                                                 reinterpret_cast<c32*>(b), D, 2, true, spart_, nullptr, st_)))
+        launch_h<T, T, T, T, T, false, false>(L, a, nullptr, (const cx<T>*)nullptr, nullptr, b, nullptr, nullptr,
+                                              st_);
+    }, st_);
+  }
+
   // Inner products of column j (unless the stencil pass formed them:
-  // fused), then w -= sum coef_i V_i with ||w||^2, and the Givens step.
-  // NV: exact vector count when EXACT, else an upper bound of nv.
+  // fused), then w -= sum coef_i V_i with ||w||^2, and the Givens step
+  // (unless deferred into the next step).  gprev >= 0: the deferred Givens
+  // step of column gprev runs first.  NV: exact vector count when EXACT, else
+  // an upper bound of nv.
   template <int NV, bool EXACT>
-  void dots_axpy(Space& S, int nv, int j, cx<T>* w, bool fused) {
+  void dots_axpy(Space& S, int nv, int j, cx<T>* w, bool fused, int gprev, bool defer) {
     const LevelSet& L = H_->level(S.lvl);
     VecList<T> vl;
     vl.v[0] = S.v0;
@@ -359,27 +389,41 @@ class Solver {
       hipLaunchKernelGGL((k_dots<T, NV, EXACT>), dim3(L.nvblk), dim3(256), 0, st_, L.d(), L.vmap.as<const int>(),
                          vl, nv, (const cx<T>*)w, part_, (const int*)active_);
     hipLaunchKernelGGL((k_reduce_dots<NV, EXACT>), dim3(nseg_), dim3(256), 0, st_, L.d(), S.ks, nv, j,
-                       fused ? (int)PR_STENCIL : (int)PR_VECTOR, (const int*)active_);
+                       fused ? (int)PR_STENCIL : (int)PR_VECTOR, (const double*)(fused ? spart_ : part_), gprev,
+                       (const int*)active_);
     hipLaunchKernelGGL((k_axpy_norm<T, NV, EXACT>), dim3(L.nvblk), dim3(256), 0, st_, L.d(),
                        L.vmap.as<const int>(), vl, nv, w, S.ks, (const int*)active_);
-    hipLaunchKernelGGL(k_givens, dim3(nseg_), dim3(256), 0, st_, L.d(), S.ks, j, (const int*)active_);
+    if (!defer)
+      hipLaunchKernelGGL(k_givens, dim3(nseg_), dim3(256), 0, st_, L.d(), S.ks, j, (const int*)active_);
   }
+
+  // Whether step j of space S runs the fused stencil + inner-product pass.
+  bool fuses(const Space& S, int j) const {
+    if (!std::is_same<T, float>::value || !fused_dots_) return false;
+    const bool self = !S.flex;
+    return can_fuse_dots(H_->level(S.lvl), self ? j : j + 1, self);
+  }
+
+  // Whether the Givens step of column j moves into step j + 1: GMRES spaces
+  // whose next step is fused (that pass derives its input scale from the
+  // partial norms itself, and its reduction kernel runs the Givens step).
+  bool defers_givens(const Space& S, int j) const { return !S.flex && j + 1 < S.k && fuses(S, j + 1); }
 
   // w = s_x H x with, where the level allows it, the inner products of w
   // with the basis V_0..V_j in the same pass (x itself is V_j for GMRES).
-  bool apply_arnoldi(Space& S, int j, const cx<T>* x, const double* xs, cx<T>* w) {
+  // npart: derive s_x from these partial norms instead of xs.
+  bool apply_arnoldi(Space& S, int j, const cx<T>* x, const double* xs, const double* npart, cx<T>* w) {
     const LevelSet& L = H_->level(S.lvl);
     bool fused = false;
-    if (std::is_same<T, float>::value && fused_dots_) {
+    if (fuses(S, j)) {
       const c32* D[6];
       const bool self = !S.flex;  // GMRES: x is the basis vector V_j
       const int nmem = self ? j : j + 1;
-      if (nmem <= 5) {
-        for (int i = 0; i < nmem; ++i) D[i] = reinterpret_cast<const c32*>(i == 0 ? S.v0 : S.V[i]);
-        fused = launch_h_dots(L, reinterpret_cast<const c32*>(x), xs, reinterpret_cast<c32*>(w), D, nmem, self,
-                              part_, active_, st_);
-      }
+      for (int i = 0; i < nmem; ++i) D[i] = reinterpret_cast<const c32*>(i == 0 ? S.v0 : S.V[i]);
+      fused = launch_h_dots(L, reinterpret_cast<const c32*>(x), xs, npart, reinterpret_cast<c32*>(w), D, nmem,
+                            self, spart_, active_, st_);
     }
+    HELM_REQUIRE(fused || !npart, "internal: deferred Givens step without the fused stencil pass");
     if (!fused)
       launch_h<T, T, T, T, T, false, false>(L, x, xs, (const cx<T>*)nullptr, nullptr, w, nullptr, active_, st_);
     return fused;
@@ -388,27 +432,30 @@ class Solver {
   // Arnoldi column j of space S from basis vector vj (with scale).
   void arnoldi_step(Space& S, int j, VRef<T> vj, bool precond) {
     cx<T>* w = S.V[j + 1];
+    const bool defer_prev = j > 0 && defers_givens(S, j - 1);
     bool fused;
     if (S.flex) {
       HELM_REQUIRE(precond, "flexible space without preconditioner");
       vcycle(S.lvl, vj, S.Z[j]);
-      fused = apply_arnoldi(S, j, S.Z[j], nullptr, w);
+      fused = apply_arnoldi(S, j, S.Z[j], nullptr, nullptr, w);
     } else {
-      fused = apply_arnoldi(S, j, vj.p, vj.s, w);
+      fused = apply_arnoldi(S, j, vj.p, defer_prev ? nullptr : vj.s, defer_prev ? part_ : nullptr, w);
     }
     if (S.lvl == 0) fine_mv_++;
     const int nv = j + 1;
+    const int gprev = defer_prev ? j - 1 : -1;
+    const bool defer = defers_givens(S, j);
     switch (nv) {
-      case 1: dots_axpy<1, true>(S, nv, j, w, fused); break;
-      case 2: dots_axpy<2, true>(S, nv, j, w, fused); break;
-      case 3: dots_axpy<3, true>(S, nv, j, w, fused); break;
-      case 4: dots_axpy<4, true>(S, nv, j, w, fused); break;
-      case 5: dots_axpy<5, true>(S, nv, j, w, fused); break;
-      case 6: dots_axpy<6, true>(S, nv, j, w, fused); break;
+      case 1: dots_axpy<1, true>(S, nv, j, w, fused, gprev, defer); break;
+      case 2: dots_axpy<2, true>(S, nv, j, w, fused, gprev, defer); break;
+      case 3: dots_axpy<3, true>(S, nv, j, w, fused, gprev, defer); break;
+      case 4: dots_axpy<4, true>(S, nv, j, w, fused, gprev, defer); break;
+      case 5: dots_axpy<5, true>(S, nv, j, w, fused, gprev, defer); break;
+      case 6: dots_axpy<6, true>(S, nv, j, w, fused, gprev, defer); break;
       default:
-        if (nv <= 11) dots_axpy<11, false>(S, nv, j, w, fused);
-        else if (nv <= 21) dots_axpy<21, false>(S, nv, j, w, fused);
-        else dots_axpy<33, false>(S, nv, j, w, fused);
+        if (nv <= 11) dots_axpy<11, false>(S, nv, j, w, fused, gprev, defer);
+        else if (nv <= 21) dots_axpy<21, false>(S, nv, j, w, fused, gprev, defer);
+        else dots_axpy<33, false>(S, nv, j, w, fused, gprev, defer);
     }
   }
 
@@ -490,6 +537,7 @@ class Solver {
   std::unique_ptr<Hierarchy> H_;
   DevBuf vec_, part_buf_, small_;
   double* part_ = nullptr;
+  double* spart_ = nullptr;
   double* beta_dev_ = nullptr;
   int* active_ = nullptr;
   cx<double>* X_ = nullptr;

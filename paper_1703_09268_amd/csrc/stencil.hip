@@ -29,6 +29,7 @@
 #pragma once
 
 #include "common.h"
+#include "krylov.hip"
 #include "segment.h"
 
 namespace helm {
@@ -223,14 +224,16 @@ struct VecPtrs {
 // points, for D_t = Vd.v[t] (t < NMEM, read from memory) and, with SELF, the
 // stored input x itself as the last one; they go to
 // part[(sblk0 + local) * PSTRIDE + 2t (+1)] (re, im).  This replaces a
-// separate pass that would read the output back.
+// separate pass that would read the output back.  With npart, the input scale
+// is derived in the kernel from the partial norms of the pass that wrote x
+// (the Givens step of the previous column then runs later).
 template <bool RESID, bool NORM, int NMEM, bool SELF>
 __global__ __launch_bounds__(256) void k_h7p(const Seg* __restrict__ segs, const int* __restrict__ smap,
                                              const int* __restrict__ slocal, const c32* __restrict__ x,
                                              const double* __restrict__ xs, const c32* __restrict__ b,
                                              const double* __restrict__ bs, c32* __restrict__ out,
                                              double* __restrict__ part, const int* __restrict__ active,
-                                             VecPtrs Vd) {
+                                             VecPtrs Vd, const double* __restrict__ npart) {
   constexpr int ND = NMEM + (SELF ? 1 : 0);
   static_assert(!(ND > 0 && (RESID || NORM)), "inner products only with the plain operator");
   __shared__ double red[ND > 0 ? 4 * 2 * ND : 16];
@@ -273,7 +276,10 @@ __global__ __launch_bounds__(256) void k_h7p(const Seg* __restrict__ segs, const
   const HELM_GLOBAL float2* __restrict__ mp =
       (const HELM_GLOBAL float2*)(reinterpret_cast<const float*>(S.m) + e0);  // e0 even: 8-byte aligned
   const c32* __restrict__ xr = x + S.off;
-  const float sx = xs ? (float)xs[sid] : 1.0f;
+  // input scale: given, or (npart) 1/||x|| from the partial norms of the
+  // vector pass that produced x, summed exactly as the Givens step does
+  float sx = xs ? (float)xs[sid] : 1.0f;
+  if (npart) sx = (float)basis_scale(seg_sum0(npart, S.vblk0, S.vnblk, red));
   float sb = 1.0f;
   if (RESID) sb = bs ? (float)bs[sid] : 1.0f;
   auto L2 = [&](int ip, int e) { return *reinterpret_cast<const c32x2*>(xr + (int64_t)ip * plane + e); };
@@ -285,44 +291,49 @@ __global__ __launch_bounds__(256) void k_h7p(const Seg* __restrict__ segs, const
 #pragma unroll
   for (int t = 0; t < ND; ++t) dr[t] = di[t] = 0.0;
   const float wf = in ? 1.0f : 0.0f;
-  // One plane: qm, qc, qp hold x planes i-1, i, i+1; qn receives plane i+2.
-  auto step = [&](int i, const c32x2& qm, const c32x2& qc, const c32x2& qp, c32x2& qn) {
-    const int64_t pl = (int64_t)i * plane;
-    // this plane's loads first, then the prefetch of plane i+2 (vector
-    // loads complete in order, so waiting for these leaves it in flight)
+  // Loads of plane i other than x's own column (issued one plane ahead).
+  struct Yp {
+    c32x2 ym, yp, bv;
+    c32 zm, zp;
+    float2 mv;
     c32x2 dv[NMEM > 0 ? NMEM : 1];
+  };
+  auto load = [&](int i, Yp& Y) {
+    const int64_t pl = (int64_t)i * plane;
 #pragma unroll
-    for (int t = 0; t < NMEM; ++t) dv[t] = *reinterpret_cast<const c32x2*>(Vd.v[t] + S.off + pl + e0);
-    const c32x2 ym = L2(i, oym), yp = L2(i, oyp);
-    const c32 zm = xr[pl + ozm], zp = xr[pl + ozp];
-    const float2 mv = mp[pl >> 1];  // plane is even
-    qn = L2(min(i + 2, nx - 1), e0);
+    for (int t = 0; t < NMEM; ++t) Y.dv[t] = *reinterpret_cast<const c32x2*>(Vd.v[t] + S.off + pl + e0);
+    Y.ym = L2(i, oym);
+    Y.yp = L2(i, oyp);
+    Y.zm = xr[pl + ozm];
+    Y.zp = xr[pl + ozp];
+    Y.mv = mp[pl >> 1];
+    if (RESID) Y.bv = *reinterpret_cast<const c32x2*>(b + S.off + pl + e0);
+  };
+  auto compute = [&](int i, const c32x2& qm, const c32x2& qc, const c32x2& qp, const Yp& Y) {
+    const int64_t pl = (int64_t)i * plane;
     const c32 ax = uload(tab.al[0], i), bx = uload(tab.be[0], i), dx = uload(tab.de[0], i);
     const c32 x0 = mk(qc.a, qc.b), x1 = mk(qc.c, qc.d);
-    c32 a0 = mk(w2 * mv.x + dx.re + d0.re, dx.im + d0.im) * x0;
+    c32 a0 = mk(w2 * Y.mv.x + dx.re + d0.re, dx.im + d0.im) * x0;
     a0 = cfma(ax, mk(qp.a, qp.b) - x0, a0);
     a0 = cfma(bx, mk(qm.a, qm.b) - x0, a0);
-    a0 = cfma(ay, mk(yp.a, yp.b) - x0, a0);
-    a0 = cfma(by, mk(ym.a, ym.b) - x0, a0);
+    a0 = cfma(ay, mk(Y.yp.a, Y.yp.b) - x0, a0);
+    a0 = cfma(by, mk(Y.ym.a, Y.ym.b) - x0, a0);
     a0 = cfma(az0, x1 - x0, a0);
-    a0 = cfma(bz0, zm - x0, a0);
-    c32 a1 = mk(w2 * mv.y + dx.re + d1.re, dx.im + d1.im) * x1;
+    a0 = cfma(bz0, Y.zm - x0, a0);
+    c32 a1 = mk(w2 * Y.mv.y + dx.re + d1.re, dx.im + d1.im) * x1;
     a1 = cfma(ax, mk(qp.c, qp.d) - x1, a1);
     a1 = cfma(bx, mk(qm.c, qm.d) - x1, a1);
-    a1 = cfma(ay, mk(yp.c, yp.d) - x1, a1);
-    a1 = cfma(by, mk(ym.c, ym.d) - x1, a1);
-    a1 = cfma(az1, zp - x1, a1);
+    a1 = cfma(ay, mk(Y.yp.c, Y.yp.d) - x1, a1);
+    a1 = cfma(by, mk(Y.ym.c, Y.ym.d) - x1, a1);
+    a1 = cfma(az1, Y.zp - x1, a1);
     a1 = cfma(bz1, x0 - x1, a1);
     a0 = sx * a0;
     a1 = sx * a1;
     if (RESID) {
-      const c32x2 bv = *reinterpret_cast<const c32x2*>(b + S.off + pl + e0);
-      a0 = sb * mk(bv.a, bv.b) - a0;
-      a1 = sb * mk(bv.c, bv.d) - a1;
+      a0 = sb * mk(Y.bv.a, Y.bv.b) - a0;
+      a1 = sb * mk(Y.bv.c, Y.bv.d) - a1;
     }
     if (pad1) a1 = czero<float>();
-    // out-of-plane lanes hold the last pair of the plane and store the same
-    // values as its owner (no branch around the loop body)
     c32x2 o;
     o.a = a0.re; o.b = a0.im; o.c = a1.re; o.d = a1.im;
     *reinterpret_cast<c32x2*>(out + S.off + pl + e0) = o;
@@ -330,28 +341,44 @@ __global__ __launch_bounds__(256) void k_h7p(const Seg* __restrict__ segs, const
       nrm += wn * ((double)a0.re * (double)a0.re + (double)a0.im * (double)a0.im +
                    ((double)a1.re * (double)a1.re + (double)a1.im * (double)a1.im));
     if (ND > 0) {
-      const c32 u0 = wf * a0, u1 = wf * a1;  // duplicates count zero
+      const c32 u0 = wf * a0, u1 = wf * a1;
 #pragma unroll
       for (int t = 0; t < ND; ++t) {
-        const c32x2 v = (SELF && t == ND - 1) ? qc : dv[t < NMEM ? t : 0];
+        const c32x2 v = (SELF && t == ND - 1) ? qc : Y.dv[t < NMEM ? t : 0];
         dr[t] += (double)v.a * u0.re + (double)v.b * u0.im + ((double)v.c * u1.re + (double)v.d * u1.im);
         di[t] += (double)v.a * u0.im - (double)v.b * u0.re + ((double)v.c * u1.im - (double)v.d * u1.re);
       }
     }
   };
-  c32x2 qm = L2(max(i0 - 1, 0), e0), qc = L2(i0, e0), qp = L2(min(i0 + 1, nx - 1), e0), qn;
-  for (int i = i0; i < i1; ++i) {
-    step(i, qm, qc, qp, qn);
-    qm = qc;
-    qc = qp;
-    qp = qn;
+  // Step i: the loads of plane i+1 and of x plane i+2 go out, then plane i
+  // is computed from loads issued one step earlier.  Unrolled by four over a
+  // four-register ring of x planes and two load sets, so that no loaded
+  // value is copied between registers (a copy would wait for the load).
+  auto step = [&](int i, const c32x2& qm, const c32x2& qc, const c32x2& qp, c32x2& qn, const Yp& Yc, Yp& Yn) {
+    load(min(i + 1, nx - 1), Yn);
+    qn = L2(min(i + 2, nx - 1), e0);
+    compute(i, qm, qc, qp, Yc);
+  };
+  c32x2 r0 = L2(max(i0 - 1, 0), e0), r1 = L2(i0, e0), r2 = L2(min(i0 + 1, nx - 1), e0), r3;
+  Yp YA, YB;
+  load(i0, YA);
+  int i = i0;
+  for (; i + 4 <= i1; i += 4) {
+    step(i, r0, r1, r2, r3, YA, YB);
+    step(i + 1, r1, r2, r3, r0, YB, YA);
+    step(i + 2, r2, r3, r0, r1, YA, YB);
+    step(i + 3, r3, r0, r1, r2, YB, YA);
   }
+  if (i < i1) step(i++, r0, r1, r2, r3, YA, YB);
+  if (i < i1) step(i++, r1, r2, r3, r0, YB, YA);
+  if (i < i1) step(i++, r2, r3, r0, r1, YA, YB);
   if (NORM) {
     const double s = block_sum(nrm, red);
     if (threadIdx.x == 0) *pslot = s;
   }
   if (ND > 0) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();  // red may still be read by the prologue's reduction
 #pragma unroll
     for (int t = 0; t < ND; ++t) {
       const double sr = wave_sum(dr[t]);

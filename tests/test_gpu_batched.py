@@ -37,9 +37,10 @@ def test_batched_equals_plain_and_oracle():
     for (w, grid, m_t, q_t, g, q), u_b, ib in zip(mem, us, infos):
         assert ib.status == 0 and ib.relres_fp64 <= 1e-8
         u_p, ip = hx.helm_solve(grid, m_t, w.omega, q_t, opts=opts)
-        # same kernels, same per-segment reduction order: same cycles, results
-        # equal up to the rounding of the shared FP64 iterate
-        assert ib.cycles == ip[0].cycles
+        # same kernels; the stencil tiles (and so the order of partial sums)
+        # may differ between the batch and the single problem, so the cycle
+        # counts agree to within one and the results to the tolerance
+        assert abs(ib.cycles - ip[0].cycles) <= 1
         d = torch.linalg.norm(u_b - u_p).item() / torch.linalg.norm(u_p).item()
         assert d <= 1e-6
         m_used = m_t.cpu().numpy().astype(np.float64)
