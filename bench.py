@@ -150,17 +150,25 @@ def copy_timing(torch, n_elems, reps, dev):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stencil7_pair_c2_128cube_16rhs_hbm_traffic.txt")
-STENCIL_SOURCE = os.path.join(ROOT, "paper_1703_09268_amd", "csrc", "stencil.hip")
+# the kernel (stencil.hip) and its launch / tile choice (operator.hip)
+STENCIL_SOURCES = [os.path.join(ROOT, "paper_1703_09268_amd", "csrc", f) for f in ("stencil.hip", "operator.hip")]
+
+
+def stencil_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for path in STENCIL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic():
     """HBM bytes per stencil launch from the committed hardware-counter
-    summary, if it was taken on the current stencil source (sha256 match);
+    summary, if it was taken on the current stencil sources (sha256 match);
     otherwise None."""
-    import hashlib
     try:
-        with open(STENCIL_SOURCE, "rb") as f:
-            digest = hashlib.sha256(f.read()).hexdigest()
+        digest = stencil_source_digest()
         with open(TRAFFIC_FILE) as f:
             rec = json.loads([ln for ln in f if ln.startswith("{")][-1])
     except (OSError, ValueError, IndexError):
