@@ -1,0 +1,95 @@
+"""GPU parity at the full sizes of the workloads, in the launch
+configurations bench.py times.  Where the oracle cannot solve at that size,
+it checks what holds at any size: the FP64 residual of the returned fields,
+recomputed on the CPU with the oracle's operator.  The operator itself is
+compared array-wide at the largest (27-point) size."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1703_09268_amd as hx
+import workloads
+from oracle import operators as ops
+from oracle import fwi
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def _relres(g, m, u, q, stencil="7pt", w27=None, adjoint=False):
+    r = q - ops.apply(g, m, u, adjoint=adjoint, stencil=stencil, w27=w27)
+    return np.linalg.norm(r) / np.linalg.norm(q)
+
+
+def test_c2_full_multisource_solve_is_certified():
+    """128^3 layered model, all 16 sources in one multi-right-hand-side
+    forward solve (as in the bench step): the FP64 fields returned satisfy
+    ||q - H u|| / ||q|| <= 1e-6 with the residual recomputed by the oracle,
+    and the GPU's own FP64 certificate agrees with the oracle's value."""
+    print("case full c2 128^3 x 16 sources", flush=True)
+    w = workloads.c2_layered()
+    grid = hx.Grid(n=w.n, h=w.h, npml=w.npml, v_ref=w.v_ref, dtype="c64")
+    m_t = torch.tensor(w.m, dtype=torch.float32, device=DEV)
+    rec = workloads.surface_positions(w.n, w.npml, (4, 4))
+    nsrc = len(w.src)
+    d = torch.zeros((nsrc, len(rec)), dtype=torch.complex64, device=DEV)
+    u = torch.empty((nsrc,) + w.n, dtype=torch.complex128, device=DEV)
+    _, _, infos = hx.misfit_gradient(grid, m_t, w.omega, w.src, rec, d, u_store=u, forward_only=True,
+                                     u_fp64=True, opts=hx.SolverOpts(tol=1e-6, max_cycles=30))
+    assert all(i.status == 0 and i.relres_fp64 <= 1e-6 for i in infos[:nsrc])
+    g = ops.make_grid(w.n, w.h, w.npml, w.omega, w.v_ref)
+    m_used = m_t.cpu().numpy().astype(np.float64)
+    for s in (0, 7, 15):
+        q = fwi.point_source(g, tuple(w.src[s]))
+        rel = _relres(g, m_used, u[s].cpu().numpy(), q)
+        assert rel <= 1e-6
+        assert abs(rel - infos[s].relres_fp64) <= 1e-3 * rel
+
+
+def test_c5_full_size_27pt_operator():
+    """320x320x160 salt model, 27-point operator, 8 right-hand sides in one
+    launch: forward (right-hand side 0) and adjoint (right-hand side 5) equal
+    the oracle's FP64 evaluation over the whole array."""
+    print("case full c5 320x320x160 27pt x 8", flush=True)
+    w = workloads.c5_salt()
+    grid = hx.Grid(n=w.n, h=w.h, npml=w.npml, v_ref=w.v_ref, stencil="27pt", dtype="c64", w27=w.w27)
+    m_t = torch.tensor(w.m, dtype=torch.float32, device=DEV)
+    gen = torch.Generator(device="cpu").manual_seed(5)
+    x_t = torch.randn((8,) + w.n, dtype=torch.complex64, generator=gen).to(DEV)
+    g = ops.make_grid(w.n, w.h, w.npml, w.omega, w.v_ref)
+    m_used = m_t.cpu().numpy().astype(np.float64)
+    for adjoint, r in ((False, 0), (True, 5)):
+        y_t = hx.helm_apply(grid, m_t, w.omega, x_t, adjoint=adjoint)
+        torch.cuda.synchronize()
+        y = y_t[r].cpu().numpy().astype(np.complex128)
+        del y_t
+        ref = ops.apply(g, m_used, x_t[r].cpu().numpy().astype(np.complex128), adjoint=adjoint,
+                        stencil="27pt", w27=w.w27)
+        assert np.linalg.norm(y - ref) <= 1e-5 * np.linalg.norm(ref)
+        assert np.abs(y - ref).max() <= 4e-5 * np.abs(ref).max()
+
+
+def test_c4_full_size_members_batched_and_plain():
+    """The first six problems of the seeded 256-problem uneven draw (dims
+    48-160) solved together and one at a time: every FP64 certificate <= 1e-6,
+    and the returned complex64 fields solve the oracle's system (the residual
+    recomputed in FP64 includes the rounding of the fields to complex64)."""
+    print("case full c4 first 6 members", flush=True)
+    params = workloads.c4_problem_params(count=256)[:6]
+    probs, meta = [], []
+    for p in params:
+        w = workloads.c4_problem(p)
+        grid = hx.Grid(n=w.n, h=w.h, npml=w.npml, v_ref=w.v_ref, dtype="c64")
+        m_t = torch.tensor(w.m, dtype=torch.float32, device=DEV)
+        g = ops.make_grid(w.n, w.h, w.npml, w.omega, w.v_ref)
+        q = fwi.point_source(g, tuple(w.src[0]))
+        probs.append((grid, m_t, w.omega, torch.tensor(q, dtype=torch.complex64, device=DEV)))
+        meta.append((g, q, m_t.cpu().numpy().astype(np.float64)))
+    opts = hx.SolverOpts(tol=1e-6, max_cycles=40)
+    ub, ib = hx.helm_solve_batched(probs, opts=opts)
+    for k, (pr, (g, q, m_used)) in enumerate(zip(probs, meta)):
+        up, ip = hx.helm_solve(*pr, opts=opts)
+        assert ib[k].status == 0 and ib[k].relres_fp64 <= 1e-6
+        assert ip[0].status == 0 and ip[0].relres_fp64 <= 1e-6
+        for u in (ub[k], up):
+            assert _relres(g, m_used, u.cpu().numpy().astype(np.complex128), q) <= 1e-4
