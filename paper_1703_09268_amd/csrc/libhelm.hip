@@ -185,21 +185,41 @@ std::unique_ptr<helm::Solver<double>>& slot_of<double>(CachedSolver& c) { return
 // per call.
 template <typename T>
 helm::Solver<T>& solver_for(helm_ctx* ctx, const std::vector<helm::ProblemSpec>& probs, const helm::SolveOpts& o,
-                            hipStream_t st) {
+                            hipStream_t st, bool pad_fine = false) {
   helm::SolveOpts ko = o;
   ko.warm_start = 0;
   ko.max_cycles = 0;
   ko.tol = 0.0;
-  const std::string key = key_of(probs, ko, sizeof(T) == 4 ? HELM_C64 : HELM_C128);
+  const std::string key = key_of(probs, ko, sizeof(T) == 4 ? HELM_C64 : HELM_C128) + (pad_fine ? "P" : "U");
   auto& slot = slot_of<T>(ctx->solver);
   if (!slot || ctx->solver.key != key) {
     ctx->solver.s32.reset();  // free the old workspace before allocating
     ctx->solver.s64.reset();
-    slot.reset(new helm::Solver<T>(probs, o, st));
+    slot.reset(new helm::Solver<T>(probs, o, st, pad_fine));
     ctx->solver.key = key;
   }
   slot->set_call_opts(o);
   return *slot;
+}
+
+// A solve of complex64 7-point problems with an odd nz runs its fine level in
+// the even-pitch layout of the pair-tiled kernels (right-hand sides and
+// fields are copied in and out); everything else uses the caller's layout.
+bool wants_pad(const std::vector<helm::ProblemSpec>& ps, bool f32) {
+  if (!f32) return false;
+  bool odd = false;
+  for (const auto& p : ps) {
+    if (p.g.stencil != 0) return false;
+    odd = odd || (p.g.n[2] & 1);
+  }
+  return odd;
+}
+
+// dst (pitch dpz elements per z row) <- src (pitch spz), `rows` rows of nz
+template <typename T>
+void copy_rows(void* dst, int dpz, const void* src, int spz, int nz, size_t rows, hipStream_t st) {
+  HELM_HIP_CHECK(hipMemcpy2DAsync(dst, (size_t)dpz * sizeof(helm::cx<T>), src, (size_t)spz * sizeof(helm::cx<T>),
+                                  (size_t)nz * sizeof(helm::cx<T>), rows, hipMemcpyDeviceToDevice, st));
 }
 
 std::vector<helm::ProblemSpec> shared_problems(const helm_grid* g, const void* m, double omega, int dir, int n) {
@@ -216,9 +236,28 @@ template <typename T>
 helm_status solve_t(helm_ctx* ctx, const helm_grid* g, const void* m, double omega, int adjoint, int nrhs,
                     const void* q, void* u, const helm::SolveOpts& o, helm_solve_info* info, void* caller) {
   hipStream_t st = solve_stream(ctx, caller);
-  helm::Solver<T>& S = solver_for<T>(ctx, shared_problems(g, m, omega, 0, nrhs), o, st);
+  const auto ps = shared_problems(g, m, omega, 0, nrhs);
+  const bool pad = wants_pad(ps, sizeof(T) == 4);
+  helm::Solver<T>& S = solver_for<T>(ctx, ps, o, st, pad);
   std::vector<helm::SolveInfo> inf(nrhs);
-  const int worst = S.solve(adjoint, (const helm::cx<T>*)q, (helm::cx<T>*)u, inf.data());
+  int worst;
+  if (!pad) {
+    worst = S.solve(adjoint, (const helm::cx<T>*)q, (helm::cx<T>*)u, inf.data());
+  } else {
+    const helm::LevelSet& L0 = S.hierarchy().level(0);
+    const int nz = g->n[2], pz = L0.host[0].pz;
+    const size_t rows = (size_t)nrhs * g->n[0] * g->n[1];
+    const size_t vb = (size_t)L0.total * sizeof(helm::cx<T>);
+    ctx->batch_buf.ensure(2 * vb);
+    helm::cx<T>* Q = ctx->batch_buf.as<helm::cx<T>>();
+    helm::cx<T>* U = Q + L0.total;
+    HELM_HIP_CHECK(hipMemsetAsync(Q, 0, 2 * vb, st));  // pads stay zero
+    copy_rows<T>(Q, pz, q, nz, nz, rows, st);
+    if (o.warm_start) copy_rows<T>(U, pz, u, nz, nz, rows, st);
+    worst = S.solve(adjoint, Q, U, inf.data());
+    copy_rows<T>(u, nz, U, pz, nz, rows, st);
+    HELM_HIP_CHECK(hipStreamSynchronize(st));
+  }
   if (info)
     for (int r = 0; r < nrhs; ++r) to_info(inf[r], info + r);
   return (helm_status)worst;
@@ -239,23 +278,27 @@ helm_status solve_batched_t(helm_ctx* ctx, int nprob, const helm_problem* probs,
     ps[i].m = probs[i].m;
     total += (int64_t)probs[i].grid.n[0] * probs[i].grid.n[1] * probs[i].grid.n[2];
   }
-  Solver<T>& S = solver_for<T>(ctx, ps, o, st);
+  const bool pad = wants_pad(ps, sizeof(T) == 4);
+  Solver<T>& S = solver_for<T>(ctx, ps, o, st, pad);
   // gather the right-hand sides (and initial guesses) into the segment layout
-  ctx->batch_buf.ensure(2 * (size_t)total * sizeof(cx<T>));
-  cx<T>* Q = ctx->batch_buf.as<cx<T>>();
-  cx<T>* U = Q + total;
   const auto& L0 = S.hierarchy().level(0);
+  (void)total;
+  ctx->batch_buf.ensure(2 * (size_t)L0.total * sizeof(cx<T>));
+  cx<T>* Q = ctx->batch_buf.as<cx<T>>();
+  cx<T>* U = Q + L0.total;
+  if (pad) HELM_HIP_CHECK(hipMemsetAsync(Q, 0, 2 * (size_t)L0.total * sizeof(cx<T>), st));  // pads stay zero
   for (int i = 0; i < nprob; ++i) {
-    const size_t bytes = (size_t)L0.host[i].N * sizeof(cx<T>);
-    HELM_HIP_CHECK(hipMemcpyAsync(Q + L0.host[i].off, probs[i].q, bytes, hipMemcpyDeviceToDevice, st));
-    if (o.warm_start)
-      HELM_HIP_CHECK(hipMemcpyAsync(U + L0.host[i].off, probs[i].u, bytes, hipMemcpyDeviceToDevice, st));
+    const Seg& G = L0.host[i];
+    const size_t rows = (size_t)G.n[0] * G.n[1];
+    copy_rows<T>(Q + G.off, G.pz, probs[i].q, G.n[2], G.n[2], rows, st);
+    if (o.warm_start) copy_rows<T>(U + G.off, G.pz, probs[i].u, G.n[2], G.n[2], rows, st);
   }
   std::vector<SolveInfo> inf(nprob);
   const int worst = S.solve(adjoint, Q, U, inf.data());
-  for (int i = 0; i < nprob; ++i)
-    HELM_HIP_CHECK(hipMemcpyAsync(probs[i].u, U + L0.host[i].off, (size_t)L0.host[i].N * sizeof(cx<T>),
-                                  hipMemcpyDeviceToDevice, st));
+  for (int i = 0; i < nprob; ++i) {
+    const Seg& G = L0.host[i];
+    copy_rows<T>(probs[i].u, G.n[2], U + G.off, G.pz, G.n[2], (size_t)G.n[0] * G.n[1], st);
+  }
   HELM_HIP_CHECK(hipStreamSynchronize(st));
   if (info)
     for (int i = 0; i < nprob; ++i) to_info(inf[i], info + i);
@@ -460,7 +503,8 @@ size_t helm_workspace_bytes(const helm_grid* g, const helm_solver_opts* o, int n
     const int nlev = so.method == HELM_FGMRES_ML ? so.levels : 1;
     std::vector<int64_t> Nlev(nlev);
     const bool pairs = helm::Hierarchy::uses_pairs(g->stencil, g->dtype == HELM_C64 ? 4 : 8);
-    for (int l = 0; l < nlev; ++l) Nlev[l] = helm::Hierarchy::level_points(g->n, l, pairs) * nrhs;
+    const bool pad = pairs && (g->n[2] & 1);  // as in a solve (wants_pad)
+    for (int l = 0; l < nlev; ++l) Nlev[l] = helm::Hierarchy::level_points(g->n, l, pairs, pad) * nrhs;
     return g->dtype == HELM_C64 ? helm::Solver<float>::workspace_bytes(Nlev, so)
                                 : helm::Solver<double>::workspace_bytes(Nlev, so);
   } catch (...) {

@@ -232,13 +232,18 @@ inline int vector_blocks_cap() {
 class Hierarchy {
  public:
   // model_bytes: size of one model value (4 for the complex64 path, 8 for complex128)
-  Hierarchy(const std::vector<ProblemSpec>& probs, int nlev, size_t model_bytes, hipStream_t st)
+  // pad_fine: the fine level uses the even z pitch too (the caller then
+  // passes right-hand sides and fields in that layout, and the fine models
+  // are copied into it by refresh_fine_models).
+  Hierarchy(const std::vector<ProblemSpec>& probs, int nlev, size_t model_bytes, hipStream_t st,
+            bool pad_fine = false)
       : nlev_(nlev), st_(st), model_bytes_(model_bytes) {
     const int ns = (int)probs.size();
     HELM_REQUIRE(ns >= 1, "no problems");
     stencil_ = probs[0].g.stencil;
     for (const auto& p : probs) HELM_REQUIRE(p.g.stencil == stencil_, "a batch must use one stencil type");
     pair_path_ = uses_pairs(stencil_, model_bytes_);
+    pad_fine_ = pad_fine && pair_path_;
     lev_.resize(nlev);
     // segment -> table index per level, deduplicated by (grid, omega)
     std::vector<int> tab_of(ns);
@@ -288,7 +293,7 @@ class Hierarchy {
         std::memset(&S, 0, sizeof(Seg));
         coarse_dims(probs[s].g.n, l, S.n);
         S.dir = probs[s].dir;
-        S.pz = z_pitch(S.n[2], l, pair_path_);
+        S.pz = z_pitch(S.n[2], l, pair_path_, pad_fine_);
         S.N = (int64_t)S.n[0] * S.n[1] * S.pz;
         S.off = off;
         off += S.N;
@@ -311,8 +316,19 @@ class Hierarchy {
       // models: level 0 borrows the caller's; coarse levels own one per distinct model
       std::vector<int> own(ns, 0);
       for (int s = 0; s < ns; ++s) {
-        if (l == 0) {
+        if (l == 0 && L.host[s].pz == L.host[s].n[2]) {
           L.host[s].m = probs[s].m;
+        } else if (l == 0) {
+          // fine model in the padded layout, copied from the caller's
+          if (mown[s] == s) {
+            L.models.emplace_back(new DevBuf());
+            L.models.back()->ensure((size_t)L.host[s].N * model_bytes_);
+            HELM_HIP_CHECK(hipMemsetAsync(L.models.back()->p, 0, (size_t)L.host[s].N * model_bytes_, st));
+            L.host[s].m = L.models.back()->p;
+            fine_copies_.push_back({s, probs[s].m});
+          } else {
+            L.host[s].m = L.host[mown[s]].m;
+          }
         } else if (mown[s] == s) {
           L.models.emplace_back(new DevBuf());
           L.models.back()->ensure((size_t)L.host[s].N * model_bytes_);
@@ -457,12 +473,27 @@ class Hierarchy {
   // accesses); its coarse levels get an even z pitch.  The fine level keeps
   // the caller's layout (pairs there need an even n2).
   static bool uses_pairs(int stencil, size_t model_bytes) { return stencil == 0 && model_bytes == 4; }
-  static int z_pitch(int nz, int level, bool pairs) { return (pairs && level > 0) ? nz + (nz & 1) : nz; }
+  static int z_pitch(int nz, int level, bool pairs, bool pad_fine) {
+    return (pairs && (level > 0 || pad_fine)) ? nz + (nz & 1) : nz;
+  }
   // vector length of one problem on level l
-  static int64_t level_points(const int n0[3], int l, bool pairs) {
+  static int64_t level_points(const int n0[3], int l, bool pairs, bool pad_fine) {
     int n[3];
     coarse_dims(n0, l, n);
-    return (int64_t)n[0] * n[1] * z_pitch(n[2], l, pairs);
+    return (int64_t)n[0] * n[1] * z_pitch(n[2], l, pairs, pad_fine);
+  }
+  bool pad_fine() const { return pad_fine_; }
+
+  // Copy the callers' fine models into the padded fine layout (before every
+  // solve: the caller may have changed them in place).
+  void refresh_fine_models() {
+    const LevelSet& L = *lev_[0];
+    for (const auto& fc : fine_copies_) {
+      const Seg& S = L.host[fc.first];
+      HELM_HIP_CHECK(hipMemcpy2DAsync(const_cast<void*>(S.m), (size_t)S.pz * model_bytes_, fc.second,
+                                      (size_t)S.n[2] * model_bytes_, (size_t)S.n[2] * model_bytes_,
+                                      (size_t)S.n[0] * S.n[1], hipMemcpyDeviceToDevice, st_));
+    }
   }
 
   static void coarse_dims(const int n0[3], int l, int n[3]) {
@@ -484,6 +515,8 @@ class Hierarchy {
   size_t model_bytes_;
   int stencil_ = 0;
   bool pair_path_ = false;
+  bool pad_fine_ = false;
+  std::vector<std::pair<int, const void*>> fine_copies_;  // (segment, caller's model)
   std::vector<std::unique_ptr<LevelSet>> lev_;
   std::vector<std::unique_ptr<OpTables>> tables_;
 };

@@ -78,10 +78,12 @@ class Solver {
     KState ks{};
   };
 
-  Solver(const std::vector<ProblemSpec>& probs, const SolveOpts& o, hipStream_t st)
+  // pad_fine: fine-level vectors (q, u of solve) use the even z pitch of the
+  // pair-tiled path (see Hierarchy).
+  Solver(const std::vector<ProblemSpec>& probs, const SolveOpts& o, hipStream_t st, bool pad_fine = false)
       : o_(o), st_(st), nseg_((int)probs.size()) {
     nlev_ = (o.method == 1) ? o.levels : 1;
-    H_.reset(new Hierarchy(probs, nlev_, sizeof(T), st));
+    H_.reset(new Hierarchy(probs, nlev_, sizeof(T), st, pad_fine));
     allocate();
     tune();
   }
@@ -102,6 +104,7 @@ class Solver {
   // level-0 vectors (segment s at offset Seg::off).  Returns the worst status.
   int solve(int dir, const cx<T>* q, cx<T>* u, SolveInfo* info) {
     H_->set_dir(dir);
+    H_->refresh_fine_models();
     H_->template inject_models<T>();
     const LevelSet& L = H_->level(0);
     std::vector<int> act(nseg_, 1);

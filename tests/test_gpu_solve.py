@@ -142,8 +142,9 @@ def test_failure_paths_not_converged_nan_zero():
         hx.helm_solve(grid, m_t, w.omega, q_t)
 
 
-def test_warm_start_from_solution_stops_immediately():
-    w = workloads.layered_random_workload((24, 26, 28), 20.0, 4, 6.0, nsrc_xy=(1, 1), seed=14)
+@pytest.mark.parametrize("n", [(24, 26, 28), (23, 26, 27)])  # even nz; odd nz (padded fine layout)
+def test_warm_start_from_solution_stops_immediately(n):
+    w = workloads.layered_random_workload(n, 20.0, 4, 6.0, nsrc_xy=(1, 1), seed=14)
     grid, g, m_t, m_used, cdt = _setup(w, "c64")
     q, q_t = _sources(g, w.src, cdt)
     u_t, info = hx.helm_solve(grid, m_t, w.omega, q_t, opts=hx.SolverOpts(tol=1e-7))
