@@ -202,16 +202,13 @@ helm::Solver<T>& solver_for(helm_ctx* ctx, const std::vector<helm::ProblemSpec>&
   return *slot;
 }
 
-// A solve of complex64 7-point problems with an odd nz runs its fine level in
+// A complex64 solve of problems with an odd nz runs its fine level in
 // the even-pitch layout of the pair-tiled kernels (right-hand sides and
 // fields are copied in and out); everything else uses the caller's layout.
 bool wants_pad(const std::vector<helm::ProblemSpec>& ps, bool f32) {
   if (!f32) return false;
   bool odd = false;
-  for (const auto& p : ps) {
-    if (p.g.stencil != 0) return false;
-    odd = odd || (p.g.n[2] & 1);
-  }
+  for (const auto& p : ps) odd = odd || (p.g.n[2] & 1);
   return odd;
 }
 

@@ -388,14 +388,14 @@ class Hierarchy {
       S.xchunk = xchunk;
       S.nxc = (S.n[0] + xchunk - 1) / xchunk;
       S.sblk0 = sb;
-      S.snblk = stencil_ == 0 ? S.plane_blocks * S.nxc : 0;
+      S.snblk = (stencil_ == 0 || L.pair) ? S.plane_blocks * S.nxc : 0;
       sb += S.snblk;
     }
     HELM_REQUIRE(sb <= L.sblk_bound, "internal: stencil workgroup bound exceeded");
     L.nsblk = sb;
     L.xchunk = xchunk;
     std::vector<int> smap(std::max(sb, 1)), slocal(std::max(sb, 1));
-    bool shared = stencil_ == 0 && ns > 1;
+    bool shared = (stencil_ == 0 || L.pair) && ns > 1;
     for (int s = 1; s < ns && shared; ++s)
       shared = L.host[s].m == L.host[0].m && L.host[s].n[0] == L.host[0].n[0] &&
                L.host[s].n[1] == L.host[0].n[1] && L.host[s].n[2] == L.host[0].n[2];
@@ -472,7 +472,7 @@ class Hierarchy {
   // The complex64 7-point path tiles its stencil in z-pairs (16-byte
   // accesses); its coarse levels get an even z pitch.  The fine level keeps
   // the caller's layout (pairs there need an even n2).
-  static bool uses_pairs(int stencil, size_t model_bytes) { return stencil == 0 && model_bytes == 4; }
+  static bool uses_pairs(int stencil, size_t model_bytes) { (void)stencil; return model_bytes == 4; }
   static int z_pitch(int nz, int level, bool pairs, bool pad_fine) {
     return (pairs && (level > 0 || pad_fine)) ? nz + (nz & 1) : nz;
   }
@@ -521,31 +521,45 @@ class Hierarchy {
   std::vector<std::unique_ptr<OpTables>> tables_;
 };
 
-// Which partial-sum range a stencil launch with NORM writes.
-inline int stencil_range(const LevelSet& L) { return L.stencil == 0 ? PR_STENCIL : PR_POINT; }
-
 inline bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 // out = [s_b b -] s_x H x over all segments of level L.  The complex64
 // 7-point operator runs pair tiles when the level and the buffers allow it.
+// Returns the partial-sum range a NORM launch wrote (PR_STENCIL: stencil
+// tiles; PR_POINT: point-wise workgroups).
 template <typename TC, typename TX, typename TM, typename TB, typename TO, bool RESID, bool NORM>
-void launch_h(const LevelSet& L, const cx<TX>* x, const double* xs, const cx<TB>* b, const double* bs,
-              cx<TO>* out, double* part, const int* active, hipStream_t st) {
+int launch_h(const LevelSet& L, const cx<TX>* x, const double* xs, const cx<TB>* b, const double* bs,
+             cx<TO>* out, double* part, const int* active, hipStream_t st) {
   constexpr bool all_f32 = std::is_same<TC, float>::value && std::is_same<TX, float>::value &&
                            std::is_same<TM, float>::value && std::is_same<TB, float>::value &&
                            std::is_same<TO, float>::value;
-  if (L.stencil == 1) {
+  const bool pair_ok = all_f32 && L.pair && aligned16(x) && aligned16(out) && (!RESID || aligned16(b));
+  if (L.stencil == 1 && pair_ok) {
+    const int adj = L.host[0].dir;  // one direction per level
+    if (adj)
+      hipLaunchKernelGGL((k_h27p<true, RESID, NORM>), dim3(L.nsblk), dim3(256), 0, st, L.d(), L.smap.as<const int>(),
+                         L.slocal.as<const int>(), reinterpret_cast<const c32*>(x), xs,
+                         reinterpret_cast<const c32*>(b), bs, reinterpret_cast<c32*>(out), part, active);
+    else
+      hipLaunchKernelGGL((k_h27p<false, RESID, NORM>), dim3(L.nsblk), dim3(256), 0, st, L.d(),
+                         L.smap.as<const int>(), L.slocal.as<const int>(), reinterpret_cast<const c32*>(x), xs,
+                         reinterpret_cast<const c32*>(b), bs, reinterpret_cast<c32*>(out), part, active);
+    return PR_STENCIL;
+  } else if (L.stencil == 1) {
     hipLaunchKernelGGL((k_h27<TC, TX, TM, TB, TO, RESID, NORM>), dim3(L.ntblk), dim3(256), 0, st, L.d(),
                        L.tmap.as<const int>(), x, xs, b, bs, out, part, active);
-  } else if (all_f32 && L.pair && aligned16(x) && aligned16(out) && (!RESID || aligned16(b))) {
+    return PR_POINT;
+  } else if (pair_ok) {
     hipLaunchKernelGGL((k_h7p<RESID, NORM, 0, false>), dim3(L.nsblk), dim3(256), 0, st, L.d(),
                        L.smap.as<const int>(), L.slocal.as<const int>(), reinterpret_cast<const c32*>(x), xs,
                        reinterpret_cast<const c32*>(b), bs, reinterpret_cast<c32*>(out), part, active,
                        VecPtrs{}, (const double*)nullptr);
+    return PR_STENCIL;
   } else {
     hipLaunchKernelGGL((k_h7<TC, TX, TM, TB, TO, RESID, NORM>), dim3(L.nsblk), dim3(256), 0, st, L.d(),
                        L.smap.as<const int>(), L.slocal.as<const int>(), x, xs, b, bs, out, part, active);
   }
+  return PR_STENCIL;
 }
 
 // Tile tuner (7-point levels): time a stencil launch for a few x chunks and
@@ -559,7 +573,6 @@ template <typename Run>
 void tune_tiles(Hierarchy& H, const std::string& kind, Run run, hipStream_t st) {
   static std::mutex mu;
   static std::map<std::string, int> cache;
-  if (H.stencil() != 0) return;
   if (std::getenv("HELM_XCHUNK") || std::getenv("HELM_STENCIL_WG")) return;
   if (const char* e = std::getenv("HELM_AUTOTUNE"))
     if (e[0] == '0') return;
@@ -569,6 +582,7 @@ void tune_tiles(Hierarchy& H, const std::string& kind, Run run, hipStream_t st) 
   HELM_HIP_CHECK(hipEventCreate(&e1));
   try {
     for (int l = 0; l < H.nlev(); ++l) {
+      if (H.stencil() != 0 && !H.level(l).pair) continue;  // point-wise 27-point kernel: no tiles
       const std::string key = kind + "|" + H.tile_key(l);
       auto it = cache.find(key);
       if (it != cache.end()) {

@@ -144,9 +144,10 @@ class Solver {
     fine_mv_ = 0;
     for (int cyc = 0;; ++cyc) {
       // true residual in FP64, stored (rounded) as the first basis vector
-      launch_h<double, double, T, T, T, true, true>(L, X_, nullptr, q, nullptr, outer_.V[0], part_, active_, st_);
+      const int rng = launch_h<double, double, T, T, T, true, true>(L, X_, nullptr, q, nullptr, outer_.V[0],
+                                                                    part_, active_, st_);
       fine_mv_++;
-      hipLaunchKernelGGL(k_start_cycle, dim3(nseg_), dim3(256), 0, st_, L.d(), outer_.ks, stencil_range(L),
+      hipLaunchKernelGGL(k_start_cycle, dim3(nseg_), dim3(256), 0, st_, L.d(), outer_.ks, rng,
                          (const double*)nullptr, beta_dev_, (const int*)active_);
       HELM_HIP_CHECK(hipMemcpyAsync(beta.data(), beta_dev_, nseg_ * sizeof(double), hipMemcpyDeviceToHost, st_));
       HELM_HIP_CHECK(hipStreamSynchronize(st_));
@@ -503,9 +504,9 @@ class Solver {
                            (double*)nullptr, (const int*)active_);
       } else {
         S.v0 = S.V[0];
-        launch_h<T, T, T, T, T, true, true>(L, x, nullptr, b.p, b.s, S.V[0], part_, active_, st_);
+        const int rng = launch_h<T, T, T, T, T, true, true>(L, x, nullptr, b.p, b.s, S.V[0], part_, active_, st_);
         if (S.lvl == 0) fine_mv_++;
-        hipLaunchKernelGGL(k_start_cycle, dim3(nseg_), dim3(256), 0, st_, L.d(), S.ks, stencil_range(L),
+        hipLaunchKernelGGL(k_start_cycle, dim3(nseg_), dim3(256), 0, st_, L.d(), S.ks, rng,
                            (const double*)nullptr, (double*)nullptr, (const int*)active_);
       }
       for (int j = 0; j < S.k; ++j) {

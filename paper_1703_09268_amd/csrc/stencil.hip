@@ -396,6 +396,214 @@ __global__ __launch_bounds__(256) void k_h7p(const Seg* __restrict__ segs, const
 }
 
 // ---------------------------------------------------------------------------
+// complex64 compact 27-point operator with pair tiles (same tiles, layout
+// requirements and out-of-plane handling as k_h7p).  Each x plane is read
+// once per lane -- the 3 x 4 (y, z) window around its pair -- and reduced to
+// its contributions to the outputs of planes i-1, i and i+1.  With C the
+// point, E the sum of its four in-plane face neighbours and F of its four
+// in-plane diagonal neighbours:
+//   same plane:       S0 = w0 C + w1 E + w2 F
+//   neighbour planes: S1 = w1 C + w2 E + w3 F
+// (class weights by the number of nonzero offsets), so a row of the compact
+// Laplacian is S1(i-1) + S0(i) + S1(i+1) and the 27-point mass sum has the
+// same form.  Layer rows take the 7-point stretched row from the tables.
+//   forward:  out = (interior ? L27 x : L7 x) + omega^2 A (m . x)
+//   adjoint:  out = L27 (mask . x) + L7^H ((1 - mask) . x) + omega^2 m . (A x)
+// (mask = interior rows; L27 and A are symmetric).  Planes are consumed
+// in order and each output is stored once its plane i+1 has been read.
+// ---------------------------------------------------------------------------
+template <bool ADJ, bool RESID, bool NORM>
+__global__ __launch_bounds__(256) void k_h27p(const Seg* __restrict__ segs, const int* __restrict__ smap,
+                                              const int* __restrict__ slocal, const c32* __restrict__ x,
+                                              const double* __restrict__ xs, const c32* __restrict__ b,
+                                              const double* __restrict__ bs, c32* __restrict__ out,
+                                              double* __restrict__ part, const int* __restrict__ active) {
+  __shared__ double red[16];
+  const int wg = xcd_logical(blockIdx.x, gridDim.x);
+  const int sid = smap[wg];
+  const int local = slocal[wg];
+  const Seg& S = segs[sid];
+  double* const pslot = NORM ? part + (int64_t)(S.sblk0 + local) * PSTRIDE : nullptr;
+  if (active && !active[sid]) {
+    if (NORM && threadIdx.x == 0) *pslot = 0.0;
+    return;
+  }
+  const int nx = S.n[0], ny = S.n[1], nz = S.n[2], pz = S.pz;
+  const int plane = ny * pz;  // even
+  const int npair = plane >> 1;
+  const int xc = local / S.plane_blocks;
+  const int pb = local - xc * S.plane_blocks;
+  const int q0 = pb * 256 + threadIdx.x;
+  const bool in = q0 < npair;
+  const int e0 = 2 * (in ? q0 : npair - 1);
+  const int j = e0 / pz, k0 = e0 - j * pz;  // k0 even, k0 + 1 < pz
+  const bool pad1 = k0 + 1 >= nz;
+  const Int27& I27 = S.in27;
+  const Tab7<float> tab = seg_tables<float>(S);
+  // window rows j-1, j, j+1 (clamped addresses; values outside the grid are zero)
+  int ro[3];
+  bool vr[3], my[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const int jj = j + r - 1;
+    vr[r] = jj >= 0 && jj < ny;
+    ro[r] = (vr[r] ? jj : j) * pz;
+    my[r] = jj >= I27.lo[1] && jj <= I27.hi[1];
+  }
+  // window columns k0-1 .. k0+2
+  bool vc[4], mz[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int kk = k0 - 1 + c;
+    vc[c] = kk >= 0 && kk < nz;
+    mz[c] = kk >= I27.lo[2] && kk <= I27.hi[2];
+  }
+  const int cl = k0 > 0 ? k0 - 1 : k0;
+  const int cr = k0 + 2 < pz ? k0 + 2 : k0 + 1;
+  const float lw0 = (float)I27.lw[0], lw1 = (float)I27.lw[1], lw2 = (float)I27.lw[2], lw3 = (float)I27.lw[3];
+  const float mw0 = (float)I27.mw[0], mw1 = (float)I27.mw[1], mw2 = (float)I27.mw[2], mw3 = (float)I27.mw[3];
+  const c32 ay = tab.al[1][j], by = tab.be[1][j], dy = tab.de[1][j];
+  c32 az[2], bz[2], dz[2];
+  az[0] = tab.al[2][k0];
+  bz[0] = tab.be[2][k0];
+  dz[0] = tab.de[2][k0];
+  az[1] = pad1 ? czero<float>() : tab.al[2][k0 + 1];
+  bz[1] = pad1 ? czero<float>() : tab.be[2][k0 + 1];
+  dz[1] = pad1 ? czero<float>() : tab.de[2][k0 + 1];
+  const float w2 = (float)S.w2;
+  const float* __restrict__ m = reinterpret_cast<const float*>(S.m);
+  const c32* __restrict__ xr = x + S.off;
+  const float sx = xs ? (float)xs[sid] : 1.0f;
+  float sb = 1.0f;
+  if (RESID) sb = bs ? (float)bs[sid] : 1.0f;
+  const double wn = in ? 1.0 : 0.0;
+  const int i0 = xc * S.xchunk;
+  const int i1 = min(nx, i0 + S.xchunk);
+  // running sums per element: output plane ip (cur) and ip+1 (next)
+  c32 aL[2], aM[2], aP[2], nL[2], nM[2], xcp[2];
+  float mcur[2] = {0.f, 0.f};
+#pragma unroll
+  for (int e = 0; e < 2; ++e) aL[e] = aM[e] = aP[e] = nL[e] = nM[e] = xcp[e] = czero<float>();
+  double nrm = 0.0;
+  for (int ip = i0 - 1; ip <= i1; ++ip) {
+    const bool pin = ip >= 0 && ip < nx;
+    const int ipc = pin ? ip : (ip < 0 ? 0 : nx - 1);
+    const int64_t pl = (int64_t)ipc * plane;
+    // the window of plane ip: X[r][c], zero outside the grid
+    c32 X[3][4];
+    float M[3][4];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const c32x2 pr = *reinterpret_cast<const c32x2*>(xr + pl + ro[r] + k0);
+      const c32 lft = xr[pl + ro[r] + cl], rgt = xr[pl + ro[r] + cr];
+      X[r][0] = lft;
+      X[r][1] = mk(pr.a, pr.b);
+      X[r][2] = mk(pr.c, pr.d);
+      X[r][3] = rgt;
+      if (!ADJ) {
+        const float2 mp = *reinterpret_cast<const float2*>(m + pl + ro[r] + k0);
+        M[r][0] = m[pl + ro[r] + cl];
+        M[r][1] = mp.x;
+        M[r][2] = mp.y;
+        M[r][3] = m[pl + ro[r] + cr];
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (!(pin && vr[r] && vc[c])) X[r][c] = czero<float>();
+    }
+    const bool mx = pin && ip >= I27.lo[0] && ip <= I27.hi[0];
+    c32 ax = czero<float>(), bx = ax, dx = ax;
+    if (pin) {
+      bx = uload(tab.be[0], ipc);
+      dx = uload(tab.de[0], ipc);
+    }
+    if (ip - 1 >= 0 && ip - 1 < nx) ax = uload(tab.al[0], ip - 1);
+    c32 fin[2] = {czero<float>(), czero<float>()};
+    float mown[2] = {0.f, 0.f};
+    if (ADJ) {
+      const float2 mp = *reinterpret_cast<const float2*>(m + pl + ro[1] + k0);
+      mown[0] = mp.x;
+      mown[1] = mp.y;
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      // inputs of the three parts at the window of element e (columns e .. e+2)
+      auto xl = [&](int r, int c) {  // Laplacian input
+        if (!ADJ) return X[r][c];
+        return (mx && my[r] && mz[c]) ? X[r][c] : czero<float>();
+      };
+      auto xp = [&](int r, int c) {  // layer-row input
+        if (!ADJ) return X[r][c];
+        return (mx && my[r] && mz[c]) ? czero<float>() : X[r][c];
+      };
+      auto xa = [&](int r, int c) {  // mass input
+        if (ADJ) return X[r][c];
+        return M[r][c] * X[r][c];
+      };
+      const c32 CL = xl(1, e + 1);
+      const c32 EL = xl(1, e) + xl(1, e + 2) + xl(0, e + 1) + xl(2, e + 1);
+      const c32 FL = xl(0, e) + xl(0, e + 2) + xl(2, e) + xl(2, e + 2);
+      const c32 CA = xa(1, e + 1);
+      const c32 EA = xa(1, e) + xa(1, e + 2) + xa(0, e + 1) + xa(2, e + 1);
+      const c32 FA = xa(0, e) + xa(0, e + 2) + xa(2, e) + xa(2, e + 2);
+      const c32 S0L = lw0 * CL + lw1 * EL + lw2 * FL, S1L = lw1 * CL + lw2 * EL + lw3 * FL;
+      const c32 S0M = mw0 * CA + mw1 * EA + mw2 * FA, S1M = mw1 * CA + mw2 * EA + mw3 * FA;
+      // layer row, in-plane part, for output ip
+      const c32 xcn = xp(1, e + 1);
+      c32 pin_e = (dx + dy + dz[e]) * xcn;
+      pin_e = cfma(ay, xp(2, e + 1) - xcn, pin_e);
+      pin_e = cfma(by, xp(0, e + 1) - xcn, pin_e);
+      pin_e = cfma(az[e], xp(1, e + 2) - xcn, pin_e);
+      pin_e = cfma(bz[e], xp(1, e) - xcn, pin_e);
+      // output ip - 1 is complete
+      if (ip - 1 >= i0) {
+        const c32 L = aL[e] + S1L, Mm = aM[e] + S1M;
+        const c32 P = cfma(ax, xcn - xcp[e], aP[e]);
+        c32 o;
+        if (!ADJ) {
+          const bool own = (ip - 1) >= I27.lo[0] && (ip - 1) <= I27.hi[0] && my[1] && mz[e + 1];
+          o = (own ? L : P) + w2 * Mm;
+        } else {
+          o = L + P + (w2 * mcur[e]) * Mm;
+        }
+        fin[e] = sx * o;
+      }
+      // output ip starts; ip + 1 is seeded
+      aP[e] = cfma(bx, xcp[e] - xcn, pin_e);
+      xcp[e] = xcn;
+      aM[e] = nM[e] + S0M;
+      nM[e] = S1M;
+      aL[e] = nL[e] + S0L;
+      nL[e] = S1L;
+    }
+    if (ip - 1 >= i0) {
+      c32 o0 = fin[0], o1 = fin[1];
+      const int64_t po = (int64_t)(ip - 1) * plane;
+      if (RESID) {
+        const c32x2 bv = *reinterpret_cast<const c32x2*>(b + S.off + po + e0);
+        o0 = sb * mk(bv.a, bv.b) - o0;
+        o1 = sb * mk(bv.c, bv.d) - o1;
+      }
+      if (pad1) o1 = czero<float>();
+      c32x2 ov;
+      ov.a = o0.re; ov.b = o0.im; ov.c = o1.re; ov.d = o1.im;
+      *reinterpret_cast<c32x2*>(out + S.off + po + e0) = ov;
+      if (NORM)
+        nrm += wn * ((double)o0.re * (double)o0.re + (double)o0.im * (double)o0.im +
+                     ((double)o1.re * (double)o1.re + (double)o1.im * (double)o1.im));
+    }
+    if (ADJ) {
+      mcur[0] = mown[0];
+      mcur[1] = mown[1];
+    }
+  }
+  if (NORM) {
+    const double s = block_sum(nrm, red);
+    if (threadIdx.x == 0) *pslot = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // compact 27-point operator (one output point per lane, neighbours through
 // the vector cache).  Interior rows: L27 = sum over the 27 offsets of the
 // class weight; layer rows: the 7-point stretched row from the tables.  Mass
@@ -422,18 +630,21 @@ __global__ __launch_bounds__(256) void k_h27(const Seg* __restrict__ segs, const
     if (NORM && threadIdx.x == 0) part[(int64_t)wg * PSTRIDE] = 0.0;
     return;
   }
-  const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
+  const int nx = S.n[0], ny = S.n[1], nz = S.n[2], pz = S.pz;
   const int64_t N = S.N;
   const int64_t p = (int64_t)(wg - S.tblk0) * 256 + threadIdx.x;
   const bool adj = S.dir != 0;
+  const int64_t plane = (int64_t)ny * pz;
   double nrm = 0.0;
-  if (p < N) {
+  if (p < N && (int)(p % pz) >= nz) {
+    out[S.off + p] = czero<TO>();  // pitch pad
+  } else if (p < N) {
     const Tab7<TC> tab = seg_tables<TC>(S);
     const TC w2 = (TC)S.w2;
     const TM* __restrict__ m = reinterpret_cast<const TM*>(S.m);
-    const int k = (int)(p % nz);
-    const int j = (int)((p / nz) % ny);
-    const int i = (int)(p / ((int64_t)ny * nz));
+    const int k = (int)(p % pz);
+    const int j = (int)((p / pz) % ny);
+    const int i = (int)(p / plane);
     const cx<TX>* xr = x + S.off;
     const TC sx = xs ? (TC)xs[sid] : TC(1);
     const Int27& in27 = S.in27;
@@ -455,7 +666,7 @@ __global__ __launch_bounds__(256) void k_h27(const Seg* __restrict__ segs, const
           const int kk = k + dk;
           if (kk < 0 || kk >= nz) continue;
           const int cls = (di != 0) + (dj != 0) + (dk != 0);
-          const int64_t q = p + (int64_t)di * ny * nz + (int64_t)dj * nz + dk;
+          const int64_t q = p + (int64_t)di * plane + (int64_t)dj * pz + dk;
           const cx<TC> xq = (cls == 0) ? xcur : ld<TX, TC>(xr + q);
           if (!adj) {
             if (own_int) lap = cfma(mk<TC>(lw[cls], 0), xq, lap);
@@ -474,10 +685,10 @@ __global__ __launch_bounds__(256) void k_h27(const Seg* __restrict__ segs, const
     }
     if (!adj) {
       if (!own_int) {
-        const cx<TC> xmx = i > 0 ? ld<TX, TC>(xr + p - (int64_t)ny * nz) : czero<TC>();
-        const cx<TC> xpx = i + 1 < nx ? ld<TX, TC>(xr + p + (int64_t)ny * nz) : czero<TC>();
-        const cx<TC> xmy = j > 0 ? ld<TX, TC>(xr + p - nz) : czero<TC>();
-        const cx<TC> xpy = j + 1 < ny ? ld<TX, TC>(xr + p + nz) : czero<TC>();
+        const cx<TC> xmx = i > 0 ? ld<TX, TC>(xr + p - plane) : czero<TC>();
+        const cx<TC> xpx = i + 1 < nx ? ld<TX, TC>(xr + p + plane) : czero<TC>();
+        const cx<TC> xmy = j > 0 ? ld<TX, TC>(xr + p - pz) : czero<TC>();
+        const cx<TC> xpy = j + 1 < ny ? ld<TX, TC>(xr + p + pz) : czero<TC>();
         const cx<TC> xmz = k > 0 ? ld<TX, TC>(xr + p - 1) : czero<TC>();
         const cx<TC> xpz = k + 1 < nz ? ld<TX, TC>(xr + p + 1) : czero<TC>();
         const cx<TC> d = tab.de[0][i] + tab.de[1][j] + tab.de[2][k];
