@@ -13,7 +13,12 @@ per step), inputs resident in HBM.
 Also measured in the same run:
 * the stencil kernel alone (helm_apply on the same grid with 16 right-hand
   sides) timed with HIP events on the launch stream, reported against the
-  8 TB/s HBM peak with the algorithmic bytes 16*S + 4 per grid point;
+  8 TB/s HBM peak with the algorithmic bytes 16*S + 4 per grid point, next
+  to a plain device copy (the practical ceiling);
+* the compact 27-point operator on the 320x320x160 salt workload (8
+  right-hand sides), the same way;
+* batched vs plain solves of uneven problems (helm_solve_batched vs
+  helm_solve one at a time);
 * the FP64 CPU oracle on a bounded sample of the same workload (rank 0).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -48,7 +53,60 @@ def parse():
     p.add_argument("--no-batch", action="store_true")
     p.add_argument("--stencil-only", action="store_true",
                    help="only the stencil measurement (for hardware-counter runs)")
+    p.add_argument("--sweep", action="store_true",
+                   help="only the stencil size sweep (7-point 64^3..512^3, 27-point), one JSON line per size")
+    p.add_argument("--no-stencil27", action="store_true")
     return p.parse_args()
+
+
+def apply_timing(hx, torch, grid, m_t, omega, S, reps, dev):
+    """Average helm_apply launch time (S right-hand sides, HIP events on the
+    launch stream, two input/output pairs alternating) and its algorithmic
+    GB/s ((16 S + 4) B per grid point)."""
+    n = tuple(grid.n)
+    xs = [torch.randn((S,) + n, dtype=torch.complex64, device=dev) for _ in range(2)]
+    ys = [torch.empty_like(xs[0]) for _ in range(2)]
+    for i in range(3):
+        hx.helm_apply(grid, m_t, omega, xs[i % 2], out=ys[i % 2])
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for i in range(reps):
+        hx.helm_apply(grid, m_t, omega, xs[i % 2], out=ys[i % 2])
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    npts = n[0] * n[1] * n[2]
+    return ms, (16 * S + 4) * npts / (ms * 1e-3) / 1e9
+
+
+def stencil27_timing(hx, torch, workloads, reps, dev):
+    """The 27-point operator on the 320x320x160 salt workload, 8 right-hand
+    sides (its sources), complex64."""
+    w = workloads.c5_salt()
+    grid = hx.Grid(n=w.n, h=w.h, npml=w.npml, v_ref=w.v_ref, stencil="27pt", dtype="c64", w27=w.w27)
+    m_t = torch.tensor(w.m, dtype=torch.float32, device=dev)
+    ms, gbs = apply_timing(hx, torch, grid, m_t, w.omega, len(w.src), reps, dev)
+    return {"kernel": "k_h27p<false,false,false> (helm_apply: complex64 compact 27-point, pair tiles, 8 rhs)",
+            "workload": "320x320x160 salt model, h=15 m, 10 Hz", "ms_per_launch": round(ms, 5),
+            "GB_s": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_point": "16*8+4"}
+
+
+def sweep(hx, torch, reps, dev):
+    """Stencil GB/s over grid sizes (layered-free constant model; the cost of
+    the operator does not depend on the model values)."""
+    cases = [((64, 64, 64), 16, "7pt"), ((128, 128, 128), 1, "7pt"), ((128, 128, 128), 16, "7pt"),
+             ((256, 256, 256), 1, "7pt"), ((256, 256, 256), 8, "7pt"), ((512, 512, 512), 1, "7pt"),
+             ((320, 320, 160), 8, "7pt"), ((128, 128, 128), 16, "27pt"), ((320, 320, 160), 8, "27pt")]
+    for n, S, sten in cases:
+        grid = hx.Grid(n=n, h=15.0, npml=10, v_ref=4500.0, stencil=sten, dtype="c64",
+                       w27=(0.5, 0.3, 0.2, 0.6, 0.04, 0.01, 0.005) if sten == "27pt" else (1, 0, 0, 1, 0, 0, 0))
+        m_t = torch.full(n, 1.0 / 3000.0 ** 2, dtype=torch.float32, device=dev)
+        ms, gbs = apply_timing(hx, torch, grid, m_t, 2 * np.pi * 8.0, S, reps, dev)
+        print(json.dumps({"grid": list(n), "rhs": S, "stencil": sten, "us_per_launch": round(ms * 1e3, 1),
+                          "GB_s": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}), flush=True)
+        torch.cuda.empty_cache()
 
 
 def batched_vs_plain(hx, torch, workloads, count, dev):
@@ -211,6 +269,9 @@ def main():
     import workloads
 
     dev = torch.device("cuda:0")
+    if args.sweep:
+        sweep(hx, torch, args.stencil_reps, dev)
+        return
     w = workloads.c2_layered()
     if args.stencil_only:
         grid = hx.Grid(n=w.n, h=w.h, npml=w.npml, v_ref=w.v_ref, dtype="c64")
@@ -262,6 +323,7 @@ def main():
     st_ms, gbs = stencil_timing(hx, torch, grid, m_t, w, S, args.stencil_reps, dev)
     cp_ms, cp_gbs = copy_timing(torch, S * w.N, args.stencil_reps, dev)
     traffic = measured_traffic()
+    st27 = None if args.no_stencil27 else stencil27_timing(hx, torch, workloads, args.stencil_reps, dev)
     batch = None if args.no_batch else batched_vs_plain(hx, torch, workloads, args.batch_count, dev)
 
     out = {
@@ -298,6 +360,7 @@ def main():
             "algorithmic_bytes_per_launch": (16 * S + 4) * w.N,
             "copy_ceiling_GB_s": round(cp_gbs, 1),
         },
+        "stencil27": st27,
         "roofline": {
             "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
