@@ -373,11 +373,11 @@ class Hierarchy {
   }
 
   // Stencil workgroup layout of level l for x chunk `xchunk`: segment ranges,
-  // workgroup -> (segment, tile) maps, uploaded.  When every segment of the
-  // level has the same geometry and model (the sources of one frequency),
-  // the segments of one tile get consecutive workgroup ids (segment
-  // fastest), so they run together on one XCD and read that tile of the
-  // model once into its L2.
+  // workgroup -> (segment, tile) maps, uploaded.  When every segment of a
+  // small level has the same geometry and model (the sources of one
+  // frequency), the segments of one tile get consecutive workgroup ids
+  // (segment fastest), so they run together on one XCD and read that tile of
+  // the model once into its L2.
   void layout_stencil(int l, int xchunk) {
     LevelSet& L = *lev_[l];
     const int ns = (int)L.host.size();
@@ -395,7 +395,11 @@ class Hierarchy {
     L.nsblk = sb;
     L.xchunk = xchunk;
     std::vector<int> smap(std::max(sb, 1)), slocal(std::max(sb, 1));
-    bool shared = (stencil_ == 0 || L.pair) && ns > 1;
+    // (measured: pays on small levels, where the model tile is most of a
+    // tile's distinct data; on 128^3 and larger, keeping one right-hand
+    // side's neighbouring tiles on one XCD is worth more)
+    bool shared = (stencil_ == 0 || L.pair) && ns > 1 && L.host[0].N <= ((int64_t)1 << 20) &&
+                  !std::getenv("HELM_NO_INTERLEAVE");
     for (int s = 1; s < ns && shared; ++s)
       shared = L.host[s].m == L.host[0].m && L.host[s].n[0] == L.host[0].n[0] &&
                L.host[s].n[1] == L.host[0].n[1] && L.host[s].n[2] == L.host[0].n[2];

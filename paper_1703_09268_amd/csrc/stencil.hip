@@ -471,8 +471,13 @@ __global__ __launch_bounds__(256) void k_h27p(const Seg* __restrict__ segs, cons
   bz[1] = pad1 ? czero<float>() : tab.be[2][k0 + 1];
   dz[1] = pad1 ? czero<float>() : tab.de[2][k0 + 1];
   const float w2 = (float)S.w2;
-  const float* __restrict__ m = reinterpret_cast<const float*>(S.m);
+  const HELM_GLOBAL float* __restrict__ m = (const HELM_GLOBAL float*)S.m;
   const c32* __restrict__ xr = x + S.off;
+  // Interior rows touch the grid boundary only without a layer on some axis;
+  // otherwise out-of-grid window values reach the sums only through the
+  // forward mass term (zeroed via the model) or through zero couplings.
+  const bool edge = I27.lo[0] == 0 || I27.lo[1] == 0 || I27.lo[2] == 0 || I27.hi[0] == nx - 1 ||
+                    I27.hi[1] == ny - 1 || I27.hi[2] == nz - 1;
   const float sx = xs ? (float)xs[sid] : 1.0f;
   float sb = 1.0f;
   if (RESID) sb = bs ? (float)bs[sid] : 1.0f;
@@ -501,15 +506,20 @@ __global__ __launch_bounds__(256) void k_h27p(const Seg* __restrict__ segs, cons
       X[r][2] = mk(pr.c, pr.d);
       X[r][3] = rgt;
       if (!ADJ) {
-        const float2 mp = *reinterpret_cast<const float2*>(m + pl + ro[r] + k0);
+        const float2 mp = *(const HELM_GLOBAL float2*)(m + pl + ro[r] + k0);
         M[r][0] = m[pl + ro[r] + cl];
         M[r][1] = mp.x;
         M[r][2] = mp.y;
         M[r][3] = m[pl + ro[r] + cr];
-      }
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
-        if (!(pin && vr[r] && vc[c])) X[r][c] = czero<float>();
+        for (int c = 0; c < 4; ++c)
+          if (!(pin && vr[r] && vc[c])) M[r][c] = 0.0f;
+      }
+      if (ADJ || edge) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          if (!(pin && vr[r] && vc[c])) X[r][c] = czero<float>();
+      }
     }
     const bool mx = pin && ip >= I27.lo[0] && ip <= I27.hi[0];
     c32 ax = czero<float>(), bx = ax, dx = ax;
@@ -521,7 +531,7 @@ __global__ __launch_bounds__(256) void k_h27p(const Seg* __restrict__ segs, cons
     c32 fin[2] = {czero<float>(), czero<float>()};
     float mown[2] = {0.f, 0.f};
     if (ADJ) {
-      const float2 mp = *reinterpret_cast<const float2*>(m + pl + ro[1] + k0);
+      const float2 mp = *(const HELM_GLOBAL float2*)(m + pl + ro[1] + k0);
       mown[0] = mp.x;
       mown[1] = mp.y;
     }
