@@ -226,8 +226,10 @@ struct VecPtrs {
 // part[(sblk0 + local) * PSTRIDE + 2t (+1)] (re, im).  This replaces a
 // separate pass that would read the output back.  With npart, the input scale
 // is derived in the kernel from the partial norms of the pass that wrote x
-// (the Givens step of the previous column then runs later).
-template <bool RESID, bool NORM, int NMEM, bool SELF>
+// (the Givens step of the previous column then runs later).  The plain
+// operator (no inner products, no residual) keeps two planes of loads in
+// flight (DEEP); the heavier variants one, to stay within their registers.
+template <bool RESID, bool NORM, int NMEM, bool SELF, bool DEEP = (!RESID && !NORM && NMEM == 0 && !SELF)>
 __global__ __launch_bounds__(256) void k_h7p(const Seg* __restrict__ segs, const int* __restrict__ smap,
                                              const int* __restrict__ slocal, const c32* __restrict__ x,
                                              const double* __restrict__ xs, const c32* __restrict__ b,
@@ -350,28 +352,58 @@ __global__ __launch_bounds__(256) void k_h7p(const Seg* __restrict__ segs, const
       }
     }
   };
-  // Step i: the loads of plane i+1 and of x plane i+2 go out, then plane i
-  // is computed from loads issued one step earlier.  Unrolled by four over a
-  // four-register ring of x planes and two load sets, so that no loaded
-  // value is copied between registers (a copy would wait for the load).
-  auto step = [&](int i, const c32x2& qm, const c32x2& qc, const c32x2& qp, c32x2& qn, const Yp& Yc, Yp& Yn) {
-    load(min(i + 1, nx - 1), Yn);
-    qn = L2(min(i + 2, nx - 1), e0);
-    compute(i, qm, qc, qp, Yc);
-  };
-  c32x2 r0 = L2(max(i0 - 1, 0), e0), r1 = L2(i0, e0), r2 = L2(min(i0 + 1, nx - 1), e0), r3;
-  Yp YA, YB;
-  load(i0, YA);
-  int i = i0;
-  for (; i + 4 <= i1; i += 4) {
-    step(i, r0, r1, r2, r3, YA, YB);
-    step(i + 1, r1, r2, r3, r0, YB, YA);
-    step(i + 2, r2, r3, r0, r1, YA, YB);
-    step(i + 3, r3, r0, r1, r2, YB, YA);
+  if (DEEP) {
+    // Step i: the loads of plane i+2 and of x plane i+3 go out, then plane i
+    // is computed from loads issued two steps earlier (six-register ring of x
+    // planes, three load sets, unrolled by six: no loaded value is copied
+    // between registers, since a copy would wait for the load).
+    auto step = [&](int i, const c32x2& qm, const c32x2& qc, const c32x2& qp, c32x2& qn, const Yp& Yc, Yp& Yn) {
+      load(min(i + 2, nx - 1), Yn);
+      qn = L2(min(i + 3, nx - 1), e0);
+      compute(i, qm, qc, qp, Yc);
+    };
+    c32x2 r0 = L2(max(i0 - 1, 0), e0), r1 = L2(i0, e0), r2 = L2(min(i0 + 1, nx - 1), e0),
+          r3 = L2(min(i0 + 2, nx - 1), e0), r4, r5;
+    Yp YA, YB, YC;
+    load(i0, YA);
+    load(min(i0 + 1, nx - 1), YB);
+    int i = i0;
+    for (; i + 6 <= i1; i += 6) {
+      step(i, r0, r1, r2, r4, YA, YC);
+      step(i + 1, r1, r2, r3, r5, YB, YA);
+      step(i + 2, r2, r3, r4, r0, YC, YB);
+      step(i + 3, r3, r4, r5, r1, YA, YC);
+      step(i + 4, r4, r5, r0, r2, YB, YA);
+      step(i + 5, r5, r0, r1, r3, YC, YB);
+    }
+    if (i < i1) step(i++, r0, r1, r2, r4, YA, YC);
+    if (i < i1) step(i++, r1, r2, r3, r5, YB, YA);
+    if (i < i1) step(i++, r2, r3, r4, r0, YC, YB);
+    if (i < i1) step(i++, r3, r4, r5, r1, YA, YC);
+    if (i < i1) step(i++, r4, r5, r0, r2, YB, YA);
+  } else {
+    // Step i: the loads of plane i+1 and of x plane i+2 go out, then plane i
+    // is computed from loads issued one step earlier (four-register ring of x
+    // planes, two load sets, unrolled by four).
+    auto step = [&](int i, const c32x2& qm, const c32x2& qc, const c32x2& qp, c32x2& qn, const Yp& Yc, Yp& Yn) {
+      load(min(i + 1, nx - 1), Yn);
+      qn = L2(min(i + 2, nx - 1), e0);
+      compute(i, qm, qc, qp, Yc);
+    };
+    c32x2 r0 = L2(max(i0 - 1, 0), e0), r1 = L2(i0, e0), r2 = L2(min(i0 + 1, nx - 1), e0), r3;
+    Yp YA, YB;
+    load(i0, YA);
+    int i = i0;
+    for (; i + 4 <= i1; i += 4) {
+      step(i, r0, r1, r2, r3, YA, YB);
+      step(i + 1, r1, r2, r3, r0, YB, YA);
+      step(i + 2, r2, r3, r0, r1, YA, YB);
+      step(i + 3, r3, r0, r1, r2, YB, YA);
+    }
+    if (i < i1) step(i++, r0, r1, r2, r3, YA, YB);
+    if (i < i1) step(i++, r1, r2, r3, r0, YB, YA);
+    if (i < i1) step(i++, r2, r3, r0, r1, YA, YB);
   }
-  if (i < i1) step(i++, r0, r1, r2, r3, YA, YB);
-  if (i < i1) step(i++, r1, r2, r3, r0, YB, YA);
-  if (i < i1) step(i++, r2, r3, r0, r1, YA, YB);
   if (NORM) {
     const double s = block_sum(nrm, red);
     if (threadIdx.x == 0) *pslot = s;
