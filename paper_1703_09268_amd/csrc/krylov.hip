@@ -382,17 +382,6 @@ __global__ __launch_bounds__(256) void k_start_cycle(const Seg* __restrict__ seg
   }
 }
 
-// Finish Arnoldi column j (partials of the vector range of st.part).
-__global__ __launch_bounds__(256) void k_givens(const Seg* __restrict__ segs, KState st, int j,
-                                                const int* __restrict__ active) {
-  __shared__ double red[4];
-  const int sid = blockIdx.x;
-  if (active && !active[sid]) return;
-  const Seg& S = segs[sid];
-  const double s = seg_sum0(st.part, S.vblk0, S.vnblk, red);
-  if (threadIdx.x == 0) givens_column(st, sid, j, s);
-}
-
 // Back substitution R y = g (k x k upper triangular, zero pivots -> y_i = 0).
 __device__ __forceinline__ void solve_upper(const KState& st, int sid, int k, double2* y) {
   const int ns = st.nseg;
@@ -410,32 +399,51 @@ __device__ __forceinline__ void solve_upper(const KState& st, int sid, int k, do
   }
 }
 
+// Finish Arnoldi column j (partials of the vector range of st.part).  With
+// solve_k > 0 (the cycle's last column, solve_k = j + 1) also solve R y = g
+// and leave y_i * s_i in coef (s = basis scale, or 1 for a flexible space)
+// for the update of the iterate.
+__global__ __launch_bounds__(256) void k_givens(const Seg* __restrict__ segs, KState st, int j, int solve_k,
+                                                int use_scale, const int* __restrict__ active) {
+  __shared__ double red[4];
+  const int sid = blockIdx.x;
+  if (active && !active[sid]) return;
+  const Seg& S = segs[sid];
+  const double s = seg_sum0(st.part, S.vblk0, S.vnblk, red);
+  if (threadIdx.x == 0) {
+    givens_column(st, sid, j, s);
+    if (solve_k > 0) {
+      double2 y[KMAX];
+      solve_upper(st, sid, solve_k, y);
+      for (int i = 0; i < solve_k; ++i) {
+        const double sc = use_scale ? st.scale[i * st.nseg + sid] : 1.0;
+        st.coef[i * st.nseg + sid] = d2(y[i].x * sc, y[i].y * sc);
+      }
+    }
+  }
+}
+
+
 // x += sum_j y_j * s_j * D_j, with D = V (GMRES, s = scale) or Z (FGMRES,
-// s = 1).  y from R y = g solved per workgroup.  x may be of higher
-// precision than D (mixed-precision outer iterate).
+// s = 1); y_j s_j were left in coef by the cycle's last Givens step.  x may
+// be of higher precision than D (mixed-precision outer iterate).
 template <typename TX, typename T, int KM, bool EXACT>
 __global__ __launch_bounds__(256) void k_update_x(const Seg* __restrict__ segs, const int* __restrict__ vmap,
-                                                 VecList<T> D, int k, bool use_scale, KState st,
-                                                 cx<TX>* __restrict__ x, const int* __restrict__ active) {
-  __shared__ double2 ys[KMAX];
+                                                 VecList<T> D, int k, KState st, cx<TX>* __restrict__ x,
+                                                 const int* __restrict__ active) {
   const int wg = blockIdx.x;
   const int sid = vmap[wg];
   if (active && !active[sid]) return;
   const Seg& S = segs[sid];
   if (EXACT) k = KM;
-  if (threadIdx.x == 0) {
-    double2 y[KMAX];
-    solve_upper(st, sid, k, y);
-    for (int j = 0; j < k; ++j) {
-      const double s = use_scale ? st.scale[j * st.nseg + sid] : 1.0;
-      ys[j] = d2(y[j].x * s, y[j].y * s);
-    }
-  }
-  __syncthreads();
   cx<TX> c[KM];
 #pragma unroll
-  for (int j = 0; j < KM; ++j)
-    if (EXACT || j < k) c[j] = mk<TX>((TX)ys[j].x, (TX)ys[j].y);
+  for (int j = 0; j < KM; ++j) {
+    if (EXACT || j < k) {
+      const double2 ys = st.coef[j * st.nseg + sid];
+      c[j] = mk<TX>((TX)ys.x, (TX)ys.y);
+    }
+  }
   const int64_t N = S.N, off = S.off;
   const int64_t stride = (int64_t)S.vnblk * 256;
   auto upd = [&](cx<TX> acc, const cx<T>* d) {

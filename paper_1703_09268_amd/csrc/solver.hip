@@ -398,7 +398,8 @@ class Solver {
     hipLaunchKernelGGL((k_axpy_norm<T, NV, EXACT>), dim3(L.nvblk), dim3(256), 0, st_, L.d(),
                        L.vmap.as<const int>(), vl, nv, w, S.ks, (const int*)active_);
     if (!defer)
-      hipLaunchKernelGGL(k_givens, dim3(nseg_), dim3(256), 0, st_, L.d(), S.ks, j, (const int*)active_);
+      hipLaunchKernelGGL(k_givens, dim3(nseg_), dim3(256), 0, st_, L.d(), S.ks, j, j + 1 == S.k ? S.k : 0,
+                         S.flex ? 0 : 1, (const int*)active_);
   }
 
   // Whether step j of space S runs the fused stencil + inner-product pass.
@@ -471,9 +472,8 @@ class Solver {
     const dim3 grid(L.nvblk);
     const int* vm = L.vmap.as<const int>();
     const int* act = active_;
-    const bool sc = !S.flex;
 #define HELM_UPD(KM, EX) \
-  hipLaunchKernelGGL((k_update_x<TX, T, KM, EX>), grid, dim3(256), 0, st_, L.d(), vm, D, S.k, sc, S.ks, x, act)
+  hipLaunchKernelGGL((k_update_x<TX, T, KM, EX>), grid, dim3(256), 0, st_, L.d(), vm, D, S.k, S.ks, x, act)
     switch (S.k) {
       case 1: HELM_UPD(1, true); break;
       case 2: HELM_UPD(2, true); break;
