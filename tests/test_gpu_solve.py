@@ -151,3 +151,32 @@ def test_warm_start_from_solution_stops_immediately(n):
     u2, info2 = hx.helm_solve(grid, m_t, w.omega, q_t, u=u_t.clone(),
                               opts=hx.SolverOpts(tol=1e-5, warm_start=True))
     assert info2[0].cycles == 0 and info2[0].status == 0
+
+
+def test_empty_inputs_are_rejected_through_the_abi():
+    """Zero right-hand sides, an empty batch and zero sources or receivers are
+    invalid arguments (HELM_E_INVAL, nothing enqueued), not silent no-ops."""
+    import ctypes as C
+    from paper_1703_09268_amd import _lib as L
+    lib = L.load()
+    ctx = C.c_void_p()
+    assert lib.helm_create(C.byref(ctx), 0) == L.HELM_OK
+    try:
+        grid = hx.Grid(n=(16, 16, 16), h=10.0, npml=2, v_ref=2000.0)
+        g = grid.c_struct()
+        m_t = torch.ones((16, 16, 16), dtype=torch.float32, device=DEV)
+        x_t = torch.zeros((16, 16, 16), dtype=torch.complex64, device=DEV)
+        mp, xp = C.c_void_p(m_t.data_ptr()), C.c_void_p(x_t.data_ptr())
+        assert lib.helm_apply(ctx, C.byref(g), mp, 1.0, 0, 0, xp, xp, None) == L.HELM_E_INVAL
+        o = L.helm_solver_opts()
+        lib.helm_default_opts(C.byref(o))
+        assert lib.helm_solve(ctx, C.byref(g), mp, 1.0, 0, 0, xp, xp, C.byref(o), None, None) == L.HELM_E_INVAL
+        assert lib.helm_solve_batched(ctx, 0, None, 0, C.byref(o), None, None) == L.HELM_E_INVAL
+        idx = (C.c_int32 * 3)(8, 8, 8)
+        f = C.c_double(0.0)
+        st = lib.misfit_gradient(ctx, C.byref(g), mp, 1.0, 0, idx, None, 1, idx, xp, C.byref(f), None, None, 0,
+                                 C.byref(o), None, None)
+        assert st == L.HELM_E_INVAL
+        assert b"nsrc" in lib.helm_last_error(ctx)
+    finally:
+        lib.helm_destroy(ctx)
