@@ -56,6 +56,9 @@ def parse():
     p.add_argument("--sweep", action="store_true",
                    help="only the stencil size sweep (7-point 64^3..512^3, 27-point), one JSON line per size")
     p.add_argument("--no-stencil27", action="store_true")
+    p.add_argument("--c5", action="store_true",
+                   help="also time the 320x320x160 27-point misfit + gradient (about 75 s more)")
+    p.add_argument("--c5-only", action="store_true")
     return p.parse_args()
 
 
@@ -91,6 +94,39 @@ def stencil27_timing(hx, torch, workloads, reps, dev):
     return {"kernel": "k_h27p<false,false,false> (helm_apply: complex64 compact 27-point, pair tiles, 8 rhs)",
             "workload": "320x320x160 salt model, h=15 m, 10 Hz", "ms_per_launch": round(ms, 5),
             "GB_s": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_point": "16*8+4"}
+
+
+def c5_gradient(hx, torch, workloads, dev):
+    """The 320x320x160 27-point salt case: one misfit + gradient evaluation
+    (8 forward + 8 adjoint ML-GMRES solves to 1e-6 and the gradient) on the
+    smoothed model, with observed data from the sharp model (synthesised
+    first, untimed).  Timed warm (the first evaluation builds the solver)."""
+    w = workloads.c5_salt()
+    grid = hx.Grid(n=w.n, h=w.h, npml=w.npml, v_ref=w.v_ref, stencil="27pt", dtype="c64", w27=w.w27)
+    opts = hx.SolverOpts(tol=1e-6, max_cycles=30)
+    nsrc = len(w.src)
+    mt_t = torch.tensor(w.m_true, dtype=torch.float32, device=dev)
+    u = torch.empty((nsrc,) + w.n, dtype=torch.complex64, device=dev)
+    hx.misfit_gradient(grid, mt_t, w.omega, w.src, w.rec,
+                       torch.zeros((nsrc, len(w.rec)), dtype=torch.complex64, device=dev),
+                       u_store=u, forward_only=True, opts=opts)
+    ridx = torch.tensor(w.rec.astype(np.int64), device=dev)
+    d_t = u[:, ridx[:, 0], ridx[:, 1], ridx[:, 2]].contiguous()
+    del u, mt_t
+    torch.cuda.empty_cache()
+    m_t = torch.tensor(w.m, dtype=torch.float32, device=dev)
+    grad = torch.empty(w.n, dtype=torch.float32, device=dev)
+    hx.misfit_gradient(grid, m_t, w.omega, w.src, w.rec, d_t, grad=grad, opts=opts)  # build + warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f, _, infos = hx.misfit_gradient(grid, m_t, w.omega, w.src, w.rec, d_t, grad=grad, opts=opts)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"workload": "320x320x160 salt model, 27-point, h=15 m, 10 Hz, 8 sources, 300x300 receivers, "
+                        "misfit + gradient (8 forward + 8 adjoint ML-GMRES solves to rel.res 1e-6)",
+            "solves_per_s": round(2 * nsrc / dt, 4), "s_per_evaluation": round(dt, 3),
+            "max_relres_fp64": max(i.relres_fp64 for i in infos),
+            "mean_outer_cycles": float(np.mean([i.cycles for i in infos])), "misfit": f}
 
 
 def sweep(hx, torch, reps, dev):
@@ -272,6 +308,9 @@ def main():
     if args.sweep:
         sweep(hx, torch, args.stencil_reps, dev)
         return
+    if args.c5_only:
+        print(json.dumps(c5_gradient(hx, torch, workloads, dev)), flush=True)
+        return
     w = workloads.c2_layered()
     if args.stencil_only:
         grid = hx.Grid(n=w.n, h=w.h, npml=w.npml, v_ref=w.v_ref, dtype="c64")
@@ -324,6 +363,7 @@ def main():
     cp_ms, cp_gbs = copy_timing(torch, S * w.N, args.stencil_reps, dev)
     traffic = measured_traffic()
     st27 = None if args.no_stencil27 else stencil27_timing(hx, torch, workloads, args.stencil_reps, dev)
+    c5 = c5_gradient(hx, torch, workloads, dev) if args.c5 else None
     batch = None if args.no_batch else batched_vs_plain(hx, torch, workloads, args.batch_count, dev)
 
     out = {
@@ -361,6 +401,7 @@ def main():
             "copy_ceiling_GB_s": round(cp_gbs, 1),
         },
         "stencil27": st27,
+        "c5_27pt_gradient": c5,
         "roofline": {
             "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
