@@ -40,7 +40,8 @@ def test_c2_full_multisource_solve_is_certified():
     g = ops.make_grid(w.n, w.h, w.npml, w.omega, w.v_ref)
     m_used = m_t.cpu().numpy().astype(np.float64)
     for s in (0, 7, 15):
-        q = fwi.point_source(g, tuple(w.src[s]))
+        # the library injects the source in complex64: the oracle uses that value
+        q = fwi.point_source(g, tuple(w.src[s])).astype(np.complex64).astype(np.complex128)
         rel = _relres(g, m_used, u[s].cpu().numpy(), q)
         assert rel <= 1e-6
         assert abs(rel - infos[s].relres_fp64) <= 1e-3 * rel
@@ -93,3 +94,28 @@ def test_c4_full_size_members_batched_and_plain():
         assert ip[0].status == 0 and ip[0].relres_fp64 <= 1e-6
         for u in (ub[k], up):
             assert _relres(g, m_used, u.cpu().numpy().astype(np.complex128), q) <= 1e-4
+
+
+def test_c5_full_27pt_solve_is_certified():
+    """320x320x160 salt model, compact 27-point operator: two of the eight
+    sources solved together (forward, FP64 fields returned) satisfy the
+    oracle's FP64 residual ||q - H u|| / ||q|| <= 1e-6."""
+    print("case full c5 320x320x160 27pt solve x 2", flush=True)
+    w = workloads.c5_salt()
+    grid = hx.Grid(n=w.n, h=w.h, npml=w.npml, v_ref=w.v_ref, stencil="27pt", dtype="c64", w27=w.w27)
+    m_t = torch.tensor(w.m, dtype=torch.float32, device=DEV)
+    src = w.src[[0, 5]]
+    rec = w.rec[:16]
+    d = torch.zeros((2, len(rec)), dtype=torch.complex64, device=DEV)
+    u = torch.empty((2,) + w.n, dtype=torch.complex128, device=DEV)
+    _, _, infos = hx.misfit_gradient(grid, m_t, w.omega, src, rec, d, u_store=u, forward_only=True, u_fp64=True,
+                                     opts=hx.SolverOpts(tol=1e-6, max_cycles=30))
+    assert all(i.status == 0 and i.relres_fp64 <= 1e-6 for i in infos[:2])
+    g = ops.make_grid(w.n, w.h, w.npml, w.omega, w.v_ref)
+    m_used = m_t.cpu().numpy().astype(np.float64)
+    for s in range(2):
+        # the library injects the source in complex64: the oracle uses that value
+        q = fwi.point_source(g, tuple(src[s])).astype(np.complex64).astype(np.complex128)
+        rel = _relres(g, m_used, u[s].cpu().numpy(), q, stencil="27pt", w27=w.w27)
+        assert rel <= 1e-6
+        assert abs(rel - infos[s].relres_fp64) <= 1e-3 * rel
