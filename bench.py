@@ -59,6 +59,7 @@ def parse():
     p.add_argument("--c5", action="store_true",
                    help="also time the 320x320x160 27-point misfit + gradient (about 75 s more)")
     p.add_argument("--c5-only", action="store_true")
+    p.add_argument("--batch-only", action="store_true", help="only batched vs plain")
     return p.parse_args()
 
 
@@ -310,6 +311,9 @@ def main():
         return
     if args.c5_only:
         print(json.dumps(c5_gradient(hx, torch, workloads, dev)), flush=True)
+        return
+    if args.batch_only:
+        print(json.dumps(batched_vs_plain(hx, torch, workloads, args.batch_count, dev)), flush=True)
         return
     w = workloads.c2_layered()
     if args.stencil_only:
