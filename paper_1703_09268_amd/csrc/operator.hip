@@ -650,14 +650,23 @@ void tune_tiles_apply(Hierarchy& H, const cx<T>* a, cx<T>* b, hipStream_t st) {
 template <int NMEM, bool SELF>
 void launch_h_dots_n(const LevelSet& L, const c32* x, const double* xs, const double* npart, c32* out,
                      const VecPtrs& D, double* part, const int* active, hipStream_t st) {
-  hipLaunchKernelGGL((k_h7p<false, false, NMEM, SELF>), dim3(L.nsblk), dim3(256), 0, st, L.d(),
-                     L.smap.as<const int>(), L.slocal.as<const int>(), x, xs, (const c32*)nullptr,
-                     (const double*)nullptr, out, part, active, D, npart);
+  const dim3 grid(L.nsblk), block(256);
+  const int* sm = L.smap.as<const int>();
+  const int* sl = L.slocal.as<const int>();
+  if (L.stencil == 0)
+    hipLaunchKernelGGL((k_h7p<false, false, NMEM, SELF>), grid, block, 0, st, L.d(), sm, sl, x, xs,
+                       (const c32*)nullptr, (const double*)nullptr, out, part, active, D, npart);
+  else if (L.host[0].dir)
+    hipLaunchKernelGGL((k_h27p<true, false, false, NMEM, SELF>), grid, block, 0, st, L.d(), sm, sl, x, xs,
+                       (const c32*)nullptr, (const double*)nullptr, out, part, active, D, npart);
+  else
+    hipLaunchKernelGGL((k_h27p<false, false, false, NMEM, SELF>), grid, block, 0, st, L.d(), sm, sl, x, xs,
+                       (const c32*)nullptr, (const double*)nullptr, out, part, active, D, npart);
 }
 
 // whether launch_h_dots can run on this level with nmem memory vectors
 inline bool can_fuse_dots(const LevelSet& L, int nmem, bool self) {
-  return L.stencil == 0 && L.pair && nmem >= 0 && nmem <= 5 && nmem + (self ? 1 : 0) >= 1;
+  return L.pair && nmem >= 0 && nmem <= 5 && nmem + (self ? 1 : 0) >= 1;
 }
 
 // npart (optional): the input scale is 1/||x|| from these vector-range

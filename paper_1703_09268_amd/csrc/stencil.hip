@@ -452,21 +452,27 @@ __global__ __launch_bounds__(256) void k_h7p(const Seg* __restrict__ segs, const
 //   adjoint:  out = L27 (mask . x) + L7^H ((1 - mask) . x) + omega^2 m . (A x)
 // (mask = interior rows; L27 and A are symmetric).  Planes are consumed
 // in order and each output is stored once its plane i+1 has been read.
+// NMEM / SELF / npart: the Arnoldi inner products and input scale, as in
+// k_h7p.
 // ---------------------------------------------------------------------------
-template <bool ADJ, bool RESID, bool NORM>
+template <bool ADJ, bool RESID, bool NORM, int NMEM = 0, bool SELF = false>
 __global__ __launch_bounds__(256) void k_h27p(const Seg* __restrict__ segs, const int* __restrict__ smap,
                                               const int* __restrict__ slocal, const c32* __restrict__ x,
                                               const double* __restrict__ xs, const c32* __restrict__ b,
                                               const double* __restrict__ bs, c32* __restrict__ out,
-                                              double* __restrict__ part, const int* __restrict__ active) {
-  __shared__ double red[16];
+                                              double* __restrict__ part, const int* __restrict__ active,
+                                              VecPtrs Vd = VecPtrs{}, const double* __restrict__ npart = nullptr) {
+  constexpr int ND = NMEM + (SELF ? 1 : 0);
+  static_assert(!(ND > 0 && (RESID || NORM)), "inner products only with the plain operator");
+  __shared__ double red[ND > 0 ? 4 * 2 * ND : 16];
   const int wg = xcd_logical(blockIdx.x, gridDim.x);
   const int sid = smap[wg];
   const int local = slocal[wg];
   const Seg& S = segs[sid];
-  double* const pslot = NORM ? part + (int64_t)(S.sblk0 + local) * PSTRIDE : nullptr;
+  double* const pslot = (NORM || ND > 0) ? part + (int64_t)(S.sblk0 + local) * PSTRIDE : nullptr;
   if (active && !active[sid]) {
     if (NORM && threadIdx.x == 0) *pslot = 0.0;
+    if (ND > 0 && threadIdx.x < 2 * ND) pslot[threadIdx.x] = 0.0;
     return;
   }
   const int nx = S.n[0], ny = S.n[1], nz = S.n[2], pz = S.pz;
@@ -519,10 +525,16 @@ __global__ __launch_bounds__(256) void k_h27p(const Seg* __restrict__ segs, cons
   // forward mass term (zeroed via the model) or through zero couplings.
   const bool edge = I27.lo[0] == 0 || I27.lo[1] == 0 || I27.lo[2] == 0 || I27.hi[0] == nx - 1 ||
                     I27.hi[1] == ny - 1 || I27.hi[2] == nz - 1;
-  const float sx = xs ? (float)xs[sid] : 1.0f;
+  float sx = xs ? (float)xs[sid] : 1.0f;
+  if (npart) sx = (float)basis_scale(seg_sum0(npart, S.vblk0, S.vnblk, red));
   float sb = 1.0f;
   if (RESID) sb = bs ? (float)bs[sid] : 1.0f;
   const double wn = in ? 1.0 : 0.0;
+  const float wf = in ? 1.0f : 0.0f;
+  double dr[ND > 0 ? ND : 1], di[ND > 0 ? ND : 1];
+#pragma unroll
+  for (int t = 0; t < ND; ++t) dr[t] = di[t] = 0.0;
+  c32x2 xself = {0.f, 0.f, 0.f, 0.f};  // stored input at the output plane (SELF)
   const int i0 = xc * S.xchunk;
   const int i1 = min(nx, i0 + S.xchunk);
   // running sums per element: output plane ip (cur) and ip+1 (next)
@@ -538,9 +550,11 @@ __global__ __launch_bounds__(256) void k_h27p(const Seg* __restrict__ segs, cons
     // the window of plane ip: X[r][c], zero outside the grid
     c32 X[3][4];
     float M[3][4];
+    c32x2 xcen;
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
       const c32x2 pr = *reinterpret_cast<const c32x2*>(xr + pl + ro[r] + k0);
+      if (r == 1) xcen = pr;
       const c32 lft = xr[pl + ro[r] + cl], rgt = xr[pl + ro[r] + cr];
       X[r][0] = lft;
       X[r][1] = mk(pr.a, pr.b);
@@ -642,7 +656,19 @@ __global__ __launch_bounds__(256) void k_h27p(const Seg* __restrict__ segs, cons
       if (NORM)
         nrm += wn * ((double)o0.re * (double)o0.re + (double)o0.im * (double)o0.im +
                      ((double)o1.re * (double)o1.re + (double)o1.im * (double)o1.im));
+      if (ND > 0) {
+        const c32 u0 = wf * o0, u1 = wf * o1;  // duplicates count zero
+#pragma unroll
+        for (int t = 0; t < ND; ++t) {
+          const c32x2 v = (SELF && t == ND - 1)
+                              ? xself
+                              : *reinterpret_cast<const c32x2*>(Vd.v[t < NMEM ? t : 0] + S.off + po + e0);
+          dr[t] += (double)v.a * u0.re + (double)v.b * u0.im + ((double)v.c * u1.re + (double)v.d * u1.im);
+          di[t] += (double)v.a * u0.im - (double)v.b * u0.re + ((double)v.c * u1.im - (double)v.d * u1.re);
+        }
+      }
     }
+    xself = xcen;
     if (ADJ) {
       mcur[0] = mown[0];
       mcur[1] = mown[1];
@@ -651,6 +677,23 @@ __global__ __launch_bounds__(256) void k_h27p(const Seg* __restrict__ segs, cons
   if (NORM) {
     const double s = block_sum(nrm, red);
     if (threadIdx.x == 0) *pslot = s;
+  }
+  if (ND > 0) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();  // red may still be read by the prologue's reduction
+#pragma unroll
+    for (int t = 0; t < ND; ++t) {
+      const double sr = wave_sum(dr[t]);
+      const double si = wave_sum(di[t]);
+      if (lane == 0) {
+        red[wid * 2 * ND + 2 * t] = sr;
+        red[wid * 2 * ND + 2 * t + 1] = si;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * ND)
+      pslot[threadIdx.x] = red[threadIdx.x] + red[2 * ND + threadIdx.x] + red[4 * ND + threadIdx.x] +
+                           red[6 * ND + threadIdx.x];
   }
 }
 
