@@ -59,6 +59,8 @@ def parse():
     p.add_argument("--c5", action="store_true",
                    help="also time the 320x320x160 27-point misfit + gradient (about 75 s more)")
     p.add_argument("--c5-only", action="store_true")
+    p.add_argument("--stencil27-only", action="store_true",
+                   help="only the 27-point operator timing on the 320x320x160 workload")
     p.add_argument("--batch-only", action="store_true", help="only batched vs plain")
     return p.parse_args()
 
@@ -311,6 +313,9 @@ def main():
         return
     if args.c5_only:
         print(json.dumps(c5_gradient(hx, torch, workloads, dev)), flush=True)
+        return
+    if args.stencil27_only:
+        print(json.dumps(stencil27_timing(hx, torch, workloads, args.stencil_reps, dev)), flush=True)
         return
     if args.batch_only:
         print(json.dumps(batched_vs_plain(hx, torch, workloads, args.batch_count, dev)), flush=True)

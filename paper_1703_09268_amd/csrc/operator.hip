@@ -297,7 +297,7 @@ class Hierarchy {
         S.N = (int64_t)S.n[0] * S.n[1] * S.pz;
         S.off = off;
         off += S.N;
-        pair = pair && (S.pz % 2 == 0);
+        pair = pair && (S.pz % 2 == 0) && (int64_t)S.n[1] * S.pz < ((int64_t)1 << 28);  // 32-bit plane offsets
         S.w2 = probs[s].omega * probs[s].omega;
         const OpTables& T = *tl[tab_of[s]];
         S.tabf = T.tabf.p;
@@ -398,8 +398,9 @@ class Hierarchy {
     // (measured: pays on small levels, where the model tile is most of a
     // tile's distinct data; on 128^3 and larger, keeping one right-hand
     // side's neighbouring tiles on one XCD is worth more)
-    bool shared = (stencil_ == 0 || L.pair) && ns > 1 && L.host[0].N <= ((int64_t)1 << 20) &&
-                  !std::getenv("HELM_NO_INTERLEAVE");
+    const char* il = std::getenv("HELM_INTERLEAVE");  // 1 / 0: force on / off (tile experiments)
+    bool shared = (stencil_ == 0 || L.pair) && ns > 1 &&
+                  (il ? il[0] == '1' : L.host[0].N <= ((int64_t)1 << 20));
     for (int s = 1; s < ns && shared; ++s)
       shared = L.host[s].m == L.host[0].m && L.host[s].n[0] == L.host[0].n[0] &&
                L.host[s].n[1] == L.host[0].n[1] && L.host[s].n[2] == L.host[0].n[2];

@@ -29,6 +29,8 @@
 #pragma once
 
 #include "common.h"
+#include <type_traits>
+
 #include "krylov.hip"
 #include "segment.h"
 
@@ -212,6 +214,38 @@ __global__ __launch_bounds__(256) void k_h7(const Seg* __restrict__ segs, const 
 struct alignas(16) c32x2 {
   float a, b, c, d;  // (re, im) of element 0, then of element 1
 };
+
+// Buffer access to one plane of a level vector: a resource built from the
+// workgroup-uniform plane address (raw buffer, 32-bit words), addressed by
+// the lanes with 32-bit byte offsets, so no access needs 64-bit address
+// arithmetic per lane.  The resource spans the plane; accesses beyond it
+// read zero and write nothing.
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef __amdgpu_buffer_rsrc_t prsrc;
+__device__ __forceinline__ prsrc plane_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float pld_f(prsrc r, uint32_t o) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0));
+}
+__device__ __forceinline__ c32 pld_c(prsrc r, uint32_t o) {
+  return __builtin_bit_cast(c32, __builtin_amdgcn_raw_buffer_load_b64(r, o, 0, 0));
+}
+__device__ __forceinline__ c32x2 pld_c2(prsrc r, uint32_t o) {
+  return __builtin_bit_cast(c32x2, __builtin_amdgcn_raw_buffer_load_b128(r, o, 0, 0));
+}
+__device__ __forceinline__ void pst_c2(c32x2 v, prsrc r, uint32_t o) {
+  typedef decltype(__builtin_amdgcn_raw_buffer_load_b128(r, o, 0, 0)) w4;
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(w4, v), r, o, 0, 0);
+}
+#else
+struct prsrc {};
+inline prsrc plane_rsrc(const void*, uint32_t) { return prsrc{}; }
+inline float pld_f(prsrc, uint32_t) { return 0.f; }
+inline c32 pld_c(prsrc, uint32_t) { return c32{}; }
+inline c32x2 pld_c2(prsrc, uint32_t) { return c32x2{}; }
+inline void pst_c2(c32x2, prsrc, uint32_t) {}
+#endif
 
 // level vectors an Arnoldi stencil pass takes inner products with
 struct VecPtrs {
@@ -487,42 +521,50 @@ __global__ __launch_bounds__(256) void k_h27p(const Seg* __restrict__ segs, cons
   const bool pad1 = k0 + 1 >= nz;
   const Int27& I27 = S.in27;
   const Tab7<float> tab = seg_tables<float>(S);
-  // window rows j-1, j, j+1 (clamped addresses; values outside the grid are zero)
-  int ro[3];
-  bool vr[3], my[3];
+  // The window of a plane: rows j-1, j, j+1 by columns k0-1 .. k0+2, read
+  // through byte offsets inside the plane (a plane holds fewer than 2^28
+  // points) from a plane resource that is the same for the whole workgroup.
+  // Entries outside the grid get an offset beyond every plane resource and
+  // so read zero.  The pair k0, k0+1 is always inside a row (k0+1 may be a
+  // pad column).
+  constexpr uint32_t kOut = 0x80000000u;
+  uint32_t obp[3], obl[3], obr[3];
+  bool my[3], mz[4];
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
     const int jj = j + r - 1;
-    vr[r] = jj >= 0 && jj < ny;
-    ro[r] = (vr[r] ? jj : j) * pz;
+    const bool vr = jj >= 0 && jj < ny;
     my[r] = jj >= I27.lo[1] && jj <= I27.hi[1];
+    const uint32_t rowp = (uint32_t)(jj * pz);
+    obp[r] = vr ? (rowp + (uint32_t)k0) * 8u : kOut;
+    obl[r] = vr && k0 > 0 ? (rowp + (uint32_t)k0 - 1u) * 8u : kOut;
+    obr[r] = vr && k0 + 2 < nz ? (rowp + (uint32_t)k0 + 2u) * 8u : kOut;
   }
-  // window columns k0-1 .. k0+2
-  bool vc[4], mz[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     const int kk = k0 - 1 + c;
-    vc[c] = kk >= 0 && kk < nz;
     mz[c] = kk >= I27.lo[2] && kk <= I27.hi[2];
   }
-  const int cl = k0 > 0 ? k0 - 1 : k0;
-  const int cr = k0 + 2 < pz ? k0 + 2 : k0 + 1;
+  const uint32_t obo = (uint32_t)e0 * 8u;  // the lane's output pair
   const float lw0 = (float)I27.lw[0], lw1 = (float)I27.lw[1], lw2 = (float)I27.lw[2], lw3 = (float)I27.lw[3];
   const float mw0 = (float)I27.mw[0], mw1 = (float)I27.mw[1], mw2 = (float)I27.mw[2], mw3 = (float)I27.mw[3];
-  const c32 ay = tab.al[1][j], by = tab.be[1][j], dy = tab.de[1][j];
-  c32 az[2], bz[2], dz[2];
-  az[0] = tab.al[2][k0];
-  bz[0] = tab.be[2][k0];
-  dz[0] = tab.de[2][k0];
-  az[1] = pad1 ? czero<float>() : tab.al[2][k0 + 1];
-  bz[1] = pad1 ? czero<float>() : tab.be[2][k0 + 1];
-  dz[1] = pad1 ? czero<float>() : tab.de[2][k0 + 1];
+  // layer rows: the stretched 7-point row with its diagonal folded,
+  //   (d_x + d_y + d_z - sum of couplings) x_c + sum of couplings x_n;
+  // the (y, z) part of the diagonal is fixed per lane, the x part per plane
+  const c32 ay = tab.al[1][j], by = tab.be[1][j];
+  c32 az[2], bz[2], cyz[2];
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const bool pe = e == 1 && pad1;
+    az[e] = pe ? czero<float>() : tab.al[2][k0 + e];
+    bz[e] = pe ? czero<float>() : tab.be[2][k0 + e];
+    const c32 dz = pe ? czero<float>() : tab.de[2][k0 + e];
+    cyz[e] = (tab.de[1][j] + dz) - ((ay + by) + (az[e] + bz[e]));
+  }
   const float w2 = (float)S.w2;
-  const HELM_GLOBAL float* __restrict__ m = (const HELM_GLOBAL float*)S.m;
-  const c32* __restrict__ xr = x + S.off;
-  // Interior rows touch the grid boundary only without a layer on some axis;
-  // otherwise out-of-grid window values reach the sums only through the
-  // forward mass term (zeroed via the model) or through zero couplings.
+  const char* const xseg = reinterpret_cast<const char*>(x + S.off);
+  const char* const mseg = reinterpret_cast<const char*>(S.m);
+  // interior rows reach the edge of the grid (no layer on some side)
   const bool edge = I27.lo[0] == 0 || I27.lo[1] == 0 || I27.lo[2] == 0 || I27.hi[0] == nx - 1 ||
                     I27.hi[1] == ny - 1 || I27.hi[2] == nz - 1;
   float sx = xs ? (float)xs[sid] : 1.0f;
@@ -543,90 +585,128 @@ __global__ __launch_bounds__(256) void k_h27p(const Seg* __restrict__ segs, cons
 #pragma unroll
   for (int e = 0; e < 2; ++e) aL[e] = aM[e] = aP[e] = nL[e] = nM[e] = xcp[e] = czero<float>();
   double nrm = 0.0;
-  for (int ip = i0 - 1; ip <= i1; ++ip) {
-    const bool pin = ip >= 0 && ip < nx;
-    const int ipc = pin ? ip : (ip < 0 ? 0 : nx - 1);
-    const int64_t pl = (int64_t)ipc * plane;
-    // the window of plane ip: X[r][c], zero outside the grid
+  // The pad column (k0 + 1 >= nz) holds zeros in every vector and model;
+  // inputs whose pad entries reach a sum (the Laplacian of interior rows at
+  // the grid edge, the adjoint's mass and layer inputs) are also zeroed
+  // there explicitly.
+  const bool zpad = pad1 && (ADJ || edge);
+  // the window of one plane as read (zero outside the grid)
+  struct Win {
     c32 X[3][4];
-    float M[3][4];
-    c32x2 xcen;
+    float M[3][4];  // forward: the model at the window
+    float mown[2];  // adjoint: the model at the pair
+  };
+  auto load = [&](const int ip) __attribute__((always_inline)) {
+    Win w;
+    const prsrc rx = plane_rsrc(xseg + (int64_t)ip * plane * 8, (uint32_t)plane * 8u);
+    const prsrc rm = plane_rsrc(mseg + (int64_t)ip * plane * 4, (uint32_t)plane * 4u);
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
-      const c32x2 pr = *reinterpret_cast<const c32x2*>(xr + pl + ro[r] + k0);
-      if (r == 1) xcen = pr;
-      const c32 lft = xr[pl + ro[r] + cl], rgt = xr[pl + ro[r] + cr];
-      X[r][0] = lft;
-      X[r][1] = mk(pr.a, pr.b);
-      X[r][2] = mk(pr.c, pr.d);
-      X[r][3] = rgt;
+      const c32x2 pr = pld_c2(rx, obp[r]);
+      w.X[r][0] = pld_c(rx, obl[r]);
+      w.X[r][1] = mk(pr.a, pr.b);
+      w.X[r][2] = mk(pr.c, pr.d);
+      w.X[r][3] = pld_c(rx, obr[r]);
       if (!ADJ) {
-        const float2 mp = *(const HELM_GLOBAL float2*)(m + pl + ro[r] + k0);
-        M[r][0] = m[pl + ro[r] + cl];
-        M[r][1] = mp.x;
-        M[r][2] = mp.y;
-        M[r][3] = m[pl + ro[r] + cr];
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-          if (!(pin && vr[r] && vc[c])) M[r][c] = 0.0f;
-      }
-      if (ADJ || edge) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-          if (!(pin && vr[r] && vc[c])) X[r][c] = czero<float>();
+        const c32 mp = pld_c(rm, obp[r] >> 1);
+        w.M[r][0] = pld_f(rm, obl[r] >> 1);
+        w.M[r][1] = mp.re;
+        w.M[r][2] = mp.im;
+        w.M[r][3] = pld_f(rm, obr[r] >> 1);
       }
     }
-    const bool mx = pin && ip >= I27.lo[0] && ip <= I27.hi[0];
-    c32 ax = czero<float>(), bx = ax, dx = ax;
-    if (pin) {
-      bx = uload(tab.be[0], ipc);
-      dx = uload(tab.de[0], ipc);
-    }
-    if (ip - 1 >= 0 && ip - 1 < nx) ax = uload(tab.al[0], ip - 1);
-    c32 fin[2] = {czero<float>(), czero<float>()};
-    float mown[2] = {0.f, 0.f};
     if (ADJ) {
-      const float2 mp = *(const HELM_GLOBAL float2*)(m + pl + ro[1] + k0);
-      mown[0] = mp.x;
-      mown[1] = mp.y;
+      const c32 mp = pld_c(rm, obp[1] >> 1);
+      w.mown[0] = mp.re;
+      w.mown[1] = mp.im;
     }
+    return w;
+  };
+  auto zero_win = [&]() __attribute__((always_inline)) {
+    Win w;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        w.X[r][c] = czero<float>();
+        w.M[r][c] = 0.0f;
+      }
+    w.mown[0] = w.mown[1] = 0.0f;
+    return w;
+  };
+  // Consume plane ip from its window w.  OUT: the plane lies outside the
+  // grid (all its values are zero); EMIT: output plane ip - 1 is complete
+  // after it.
+  auto step = [&](const int ip, const Win& w, auto out_c, auto emit_c) __attribute__((always_inline)) {
+    constexpr bool OUT = decltype(out_c)::value;
+    constexpr bool EMIT = decltype(emit_c)::value;
+    c32 X[3][4];
+    float M[3][4];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        X[r][c] = OUT ? czero<float>() : w.X[r][c];
+        M[r][c] = (OUT || ADJ) ? 0.0f : w.M[r][c];
+      }
+    c32x2 xcen;  // the stored pair of this plane (SELF)
+    xcen.a = X[1][1].re; xcen.b = X[1][1].im; xcen.c = X[1][2].re; xcen.d = X[1][2].im;
+    const float mown[2] = {OUT ? 0.0f : w.mown[0], OUT ? 0.0f : w.mown[1]};
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      if (zpad) X[r][2] = czero<float>();
+    c32 bx = czero<float>(), dxx = czero<float>();
+    bool mx = false;
+    if (!OUT) {
+      mx = (ip >= I27.lo[0]) & (ip <= I27.hi[0]);
+      bx = uload(tab.be[0], ip);
+      dxx = uload(tab.de[0], ip) - (uload(tab.al[0], ip) + bx);
+    }
+    // inputs of the Laplacian (XL), layer-row (XP) and mass (XA) parts
+    c32 XL[3][4], XP[3][4], XA[3][4];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const bool inr = mx & my[r] & mz[c];  // bitwise: no branch on the uniform mx
+        XL[r][c] = (!ADJ || inr) ? X[r][c] : czero<float>();
+        XP[r][c] = ADJ ? X[r][c] - XL[r][c] : X[r][c];  // exact: X - X or X - 0
+        XA[r][c] = ADJ ? X[r][c] : M[r][c] * X[r][c];
+      }
+    // column sums of rows j-1 and j+1 (shared by both elements)
+    c32 VL[4], VA[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      VL[c] = XL[0][c] + XL[2][c];
+      VA[c] = XA[0][c] + XA[2][c];
+    }
+    c32 ax = czero<float>();
+    if (EMIT) ax = uload(tab.al[0], ip - 1);
+    c32 fin[2];
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      // inputs of the three parts at the window of element e (columns e .. e+2)
-      auto xl = [&](int r, int c) {  // Laplacian input
-        if (!ADJ) return X[r][c];
-        return (mx && my[r] && mz[c]) ? X[r][c] : czero<float>();
-      };
-      auto xp = [&](int r, int c) {  // layer-row input
-        if (!ADJ) return X[r][c];
-        return (mx && my[r] && mz[c]) ? czero<float>() : X[r][c];
-      };
-      auto xa = [&](int r, int c) {  // mass input
-        if (ADJ) return X[r][c];
-        return M[r][c] * X[r][c];
-      };
-      const c32 CL = xl(1, e + 1);
-      const c32 EL = xl(1, e) + xl(1, e + 2) + xl(0, e + 1) + xl(2, e + 1);
-      const c32 FL = xl(0, e) + xl(0, e + 2) + xl(2, e) + xl(2, e + 2);
-      const c32 CA = xa(1, e + 1);
-      const c32 EA = xa(1, e) + xa(1, e + 2) + xa(0, e + 1) + xa(2, e + 1);
-      const c32 FA = xa(0, e) + xa(0, e + 2) + xa(2, e) + xa(2, e + 2);
+      const c32 CL = XL[1][e + 1];
+      const c32 EL = (XL[1][e] + XL[1][e + 2]) + VL[e + 1];
+      const c32 FL = VL[e] + VL[e + 2];
+      const c32 CA = XA[1][e + 1];
+      const c32 EA = (XA[1][e] + XA[1][e + 2]) + VA[e + 1];
+      const c32 FA = VA[e] + VA[e + 2];
       const c32 S0L = lw0 * CL + lw1 * EL + lw2 * FL, S1L = lw1 * CL + lw2 * EL + lw3 * FL;
       const c32 S0M = mw0 * CA + mw1 * EA + mw2 * FA, S1M = mw1 * CA + mw2 * EA + mw3 * FA;
-      // layer row, in-plane part, for output ip
-      const c32 xcn = xp(1, e + 1);
-      c32 pin_e = (dx + dy + dz[e]) * xcn;
-      pin_e = cfma(ay, xp(2, e + 1) - xcn, pin_e);
-      pin_e = cfma(by, xp(0, e + 1) - xcn, pin_e);
-      pin_e = cfma(az[e], xp(1, e + 2) - xcn, pin_e);
-      pin_e = cfma(bz[e], xp(1, e) - xcn, pin_e);
-      // output ip - 1 is complete
-      if (ip - 1 >= i0) {
+      // layer row ip: every term but the one of plane ip + 1
+      const c32 xcn = XP[1][e + 1];
+      c32 seed = (dxx + cyz[e]) * xcn;
+      seed = cfma(ay, XP[2][e + 1], seed);
+      seed = cfma(by, XP[0][e + 1], seed);
+      seed = cfma(az[e], XP[1][e + 2], seed);
+      seed = cfma(bz[e], XP[1][e], seed);
+      seed = cfma(bx, xcp[e], seed);
+      if (EMIT) {  // output ip - 1 is complete
         const c32 L = aL[e] + S1L, Mm = aM[e] + S1M;
-        const c32 P = cfma(ax, xcn - xcp[e], aP[e]);
+        const c32 P = cfma(ax, xcn, aP[e]);
         c32 o;
         if (!ADJ) {
-          const bool own = (ip - 1) >= I27.lo[0] && (ip - 1) <= I27.hi[0] && my[1] && mz[e + 1];
+          const bool own = ((ip - 1) >= I27.lo[0]) & ((ip - 1) <= I27.hi[0]) & my[1] & mz[e + 1];
           o = (own ? L : P) + w2 * Mm;
         } else {
           o = L + P + (w2 * mcur[e]) * Mm;
@@ -634,25 +714,26 @@ __global__ __launch_bounds__(256) void k_h27p(const Seg* __restrict__ segs, cons
         fin[e] = sx * o;
       }
       // output ip starts; ip + 1 is seeded
-      aP[e] = cfma(bx, xcp[e] - xcn, pin_e);
+      aP[e] = seed;
       xcp[e] = xcn;
       aM[e] = nM[e] + S0M;
       nM[e] = S1M;
       aL[e] = nL[e] + S0L;
       nL[e] = S1L;
     }
-    if (ip - 1 >= i0) {
+    if (EMIT) {
       c32 o0 = fin[0], o1 = fin[1];
-      const int64_t po = (int64_t)(ip - 1) * plane;
+      const int64_t pob = (int64_t)(ip - 1) * plane * 8;
+      const uint32_t pbytes = (uint32_t)plane * 8u;
       if (RESID) {
-        const c32x2 bv = *reinterpret_cast<const c32x2*>(b + S.off + po + e0);
+        const c32x2 bv = pld_c2(plane_rsrc(reinterpret_cast<const char*>(b + S.off) + pob, pbytes), obo);
         o0 = sb * mk(bv.a, bv.b) - o0;
         o1 = sb * mk(bv.c, bv.d) - o1;
       }
       if (pad1) o1 = czero<float>();
       c32x2 ov;
       ov.a = o0.re; ov.b = o0.im; ov.c = o1.re; ov.d = o1.im;
-      *reinterpret_cast<c32x2*>(out + S.off + po + e0) = ov;
+      pst_c2(ov, plane_rsrc(reinterpret_cast<char*>(out + S.off) + pob, pbytes), obo);
       if (NORM)
         nrm += wn * ((double)o0.re * (double)o0.re + (double)o0.im * (double)o0.im +
                      ((double)o1.re * (double)o1.re + (double)o1.im * (double)o1.im));
@@ -660,9 +741,11 @@ __global__ __launch_bounds__(256) void k_h27p(const Seg* __restrict__ segs, cons
         const c32 u0 = wf * o0, u1 = wf * o1;  // duplicates count zero
 #pragma unroll
         for (int t = 0; t < ND; ++t) {
-          const c32x2 v = (SELF && t == ND - 1)
-                              ? xself
-                              : *reinterpret_cast<const c32x2*>(Vd.v[t < NMEM ? t : 0] + S.off + po + e0);
+          const c32x2 v =
+              (SELF && t == ND - 1)
+                  ? xself
+                  : *reinterpret_cast<const c32x2*>(reinterpret_cast<const char*>(Vd.v[t < NMEM ? t : 0] + S.off) +
+                                                     pob + obo);
           dr[t] += (double)v.a * u0.re + (double)v.b * u0.im + ((double)v.c * u1.re + (double)v.d * u1.im);
           di[t] += (double)v.a * u0.im - (double)v.b * u0.re + ((double)v.c * u1.im - (double)v.d * u1.re);
         }
@@ -673,7 +756,18 @@ __global__ __launch_bounds__(256) void k_h27p(const Seg* __restrict__ segs, cons
       mcur[0] = mown[0];
       mcur[1] = mown[1];
     }
-  }
+  };
+  // planes max(i0-1, 0) .. i1 complete outputs i0 .. i1-1; plane -1 is
+  // outside the grid and adds nothing to the zero start, plane nx only
+  // completes output nx - 1.  (Reading the next plane's window ahead of
+  // the current one's sums measured no faster: the extra registers cost
+  // occupancy.)
+  for (int ip = i0 > 0 ? i0 - 1 : 0; ip <= i0; ++ip) step(ip, load(ip), std::false_type{}, std::false_type{});
+  for (int ip = i0 + 1; ip < i1; ++ip) step(ip, load(ip), std::false_type{}, std::true_type{});
+  if (i1 < nx)
+    step(i1, load(i1), std::false_type{}, std::true_type{});
+  else
+    step(i1, zero_win(), std::true_type{}, std::true_type{});
   if (NORM) {
     const double s = block_sum(nrm, red);
     if (threadIdx.x == 0) *pslot = s;
