@@ -183,12 +183,27 @@ struct LevelSet {
   int sblk_bound = 1;  // stencil workgroups at the smallest x chunk
   int xchunk = 0;      // current x chunk of the stencil tiles
   bool pair = false;   // every segment uses pair stencil tiles
+  int stage27 = 0;     // LDS bytes per workgroup of the staged 27-point pass (0: register path)
   int64_t total = 0;  // vector length (sum of N)
   std::vector<std::unique_ptr<DevBuf>> models;  // owned coarse models
   const Seg* d() const { return segs.as<const Seg>(); }
 };
 
 constexpr int kMinXchunk = 4;  // smallest x chunk of a stencil tile
+
+// LDS bytes per workgroup of the staged 27-point pair pass: two plane tiles
+// of (512 + 2 pz + 4) complex64 and float values plus 16 zero bytes each,
+// for the widest z pitch of the level; 0 (register path) when that exceeds
+// 40 KiB (four workgroups per CU must still fit) or with HELM_STAGE27=0.
+inline int stage27_bytes(const std::vector<Seg>& segs) {
+  if (const char* e = std::getenv("HELM_STAGE27"))
+    if (e[0] == '0') return 0;
+  int pzm = 0;
+  for (const Seg& S : segs) pzm = std::max(pzm, S.pz);
+  const int64_t tl = 512 + 2 * (int64_t)pzm + 4;
+  const int64_t buf = ((tl * 12 + 15) / 16) * 16 + 16;
+  return 2 * buf <= 40 * 1024 ? (int)(2 * buf) : 0;
+}
 
 // x-chunk (planes per stencil workgroup) for a level: about `target`
 // workgroups over the level (a few per wave slot of the chip), at least 4
@@ -312,6 +327,7 @@ class Hierarchy {
         S.plane_blocks = (int)ceil_div((int64_t)S.n[1] * S.pz, pair ? 512 : 256);
       }
       L.pair = pair;
+      L.stage27 = pair && stencil_ == 1 ? stage27_bytes(L.host) : 0;
       L.total = off;
       // models: level 0 borrows the caller's; coarse levels own one per distinct model
       std::vector<int> own(ns, 0);
@@ -542,13 +558,15 @@ int launch_h(const LevelSet& L, const cx<TX>* x, const double* xs, const cx<TB>*
   if (L.stencil == 1 && pair_ok) {
     const int adj = L.host[0].dir;  // one direction per level
     if (adj)
-      hipLaunchKernelGGL((k_h27p<true, RESID, NORM>), dim3(L.nsblk), dim3(256), 0, st, L.d(), L.smap.as<const int>(),
-                         L.slocal.as<const int>(), reinterpret_cast<const c32*>(x), xs,
-                         reinterpret_cast<const c32*>(b), bs, reinterpret_cast<c32*>(out), part, active);
-    else
-      hipLaunchKernelGGL((k_h27p<false, RESID, NORM>), dim3(L.nsblk), dim3(256), 0, st, L.d(),
+      hipLaunchKernelGGL((k_h27p<true, RESID, NORM>), dim3(L.nsblk), dim3(256), L.stage27, st, L.d(),
                          L.smap.as<const int>(), L.slocal.as<const int>(), reinterpret_cast<const c32*>(x), xs,
-                         reinterpret_cast<const c32*>(b), bs, reinterpret_cast<c32*>(out), part, active);
+                         reinterpret_cast<const c32*>(b), bs, reinterpret_cast<c32*>(out), part, active, VecPtrs{},
+                         (const double*)nullptr, L.stage27 > 0 ? 1 : 0);
+    else
+      hipLaunchKernelGGL((k_h27p<false, RESID, NORM>), dim3(L.nsblk), dim3(256), L.stage27, st, L.d(),
+                         L.smap.as<const int>(), L.slocal.as<const int>(), reinterpret_cast<const c32*>(x), xs,
+                         reinterpret_cast<const c32*>(b), bs, reinterpret_cast<c32*>(out), part, active, VecPtrs{},
+                         (const double*)nullptr, L.stage27 > 0 ? 1 : 0);
     return PR_STENCIL;
   } else if (L.stencil == 1) {
     hipLaunchKernelGGL((k_h27<TC, TX, TM, TB, TO, RESID, NORM>), dim3(L.ntblk), dim3(256), 0, st, L.d(),
@@ -658,11 +676,13 @@ void launch_h_dots_n(const LevelSet& L, const c32* x, const double* xs, const do
     hipLaunchKernelGGL((k_h7p<false, false, NMEM, SELF>), grid, block, 0, st, L.d(), sm, sl, x, xs,
                        (const c32*)nullptr, (const double*)nullptr, out, part, active, D, npart);
   else if (L.host[0].dir)
-    hipLaunchKernelGGL((k_h27p<true, false, false, NMEM, SELF>), grid, block, 0, st, L.d(), sm, sl, x, xs,
-                       (const c32*)nullptr, (const double*)nullptr, out, part, active, D, npart);
+    hipLaunchKernelGGL((k_h27p<true, false, false, NMEM, SELF>), grid, block, L.stage27, st, L.d(), sm, sl, x, xs,
+                       (const c32*)nullptr, (const double*)nullptr, out, part, active, D, npart,
+                       L.stage27 > 0 ? 1 : 0);
   else
-    hipLaunchKernelGGL((k_h27p<false, false, false, NMEM, SELF>), grid, block, 0, st, L.d(), sm, sl, x, xs,
-                       (const c32*)nullptr, (const double*)nullptr, out, part, active, D, npart);
+    hipLaunchKernelGGL((k_h27p<false, false, false, NMEM, SELF>), grid, block, L.stage27, st, L.d(), sm, sl, x, xs,
+                       (const c32*)nullptr, (const double*)nullptr, out, part, active, D, npart,
+                       L.stage27 > 0 ? 1 : 0);
 }
 
 // whether launch_h_dots can run on this level with nmem memory vectors

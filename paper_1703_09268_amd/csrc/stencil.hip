@@ -238,6 +238,16 @@ __device__ __forceinline__ void pst_c2(c32x2 v, prsrc r, uint32_t o) {
   typedef decltype(__builtin_amdgcn_raw_buffer_load_b128(r, o, 0, 0)) w4;
   __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(w4, v), r, o, 0, 0);
 }
+// Buffer load straight into LDS (no registers): lane i of the wave writes
+// its `bytes` at dst + i * bytes; dst must be the same for the whole wave.
+__device__ __forceinline__ void pld_lds16(prsrc r, void* dst, uint32_t o) {
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)dst, 16, o, 0, 0, 0);
+}
+__device__ __forceinline__ void pld_lds4(prsrc r, void* dst, uint32_t o) {
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)dst, 4, o, 0, 0, 0);
+}
+// every vector memory access of this wave (LDS fills included) has completed
+__device__ __forceinline__ void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 #else
 struct prsrc {};
 inline prsrc plane_rsrc(const void*, uint32_t) { return prsrc{}; }
@@ -245,6 +255,9 @@ inline float pld_f(prsrc, uint32_t) { return 0.f; }
 inline c32 pld_c(prsrc, uint32_t) { return c32{}; }
 inline c32x2 pld_c2(prsrc, uint32_t) { return c32x2{}; }
 inline void pst_c2(c32x2, prsrc, uint32_t) {}
+inline void pld_lds16(prsrc, void*, uint32_t) {}
+inline void pld_lds4(prsrc, void*, uint32_t) {}
+inline void wait_vmem() {}
 #endif
 
 // level vectors an Arnoldi stencil pass takes inner products with
@@ -495,10 +508,12 @@ __global__ __launch_bounds__(256) void k_h27p(const Seg* __restrict__ segs, cons
                                               const double* __restrict__ xs, const c32* __restrict__ b,
                                               const double* __restrict__ bs, c32* __restrict__ out,
                                               double* __restrict__ part, const int* __restrict__ active,
-                                              VecPtrs Vd = VecPtrs{}, const double* __restrict__ npart = nullptr) {
+                                              VecPtrs Vd = VecPtrs{}, const double* __restrict__ npart = nullptr,
+                                              int stage = 0) {
   constexpr int ND = NMEM + (SELF ? 1 : 0);
   static_assert(!(ND > 0 && (RESID || NORM)), "inner products only with the plain operator");
   __shared__ double red[ND > 0 ? 4 * 2 * ND : 16];
+  extern __shared__ __attribute__((aligned(16))) char stage_lds[];
   const int wg = xcd_logical(blockIdx.x, gridDim.x);
   const int sid = smap[wg];
   const int local = slocal[wg];
@@ -759,15 +774,105 @@ __global__ __launch_bounds__(256) void k_h27p(const Seg* __restrict__ segs, cons
   };
   // planes max(i0-1, 0) .. i1 complete outputs i0 .. i1-1; plane -1 is
   // outside the grid and adds nothing to the zero start, plane nx only
-  // completes output nx - 1.  (Reading the next plane's window ahead of
-  // the current one's sums measured no faster: the extra registers cost
-  // occupancy.)
-  for (int ip = i0 > 0 ? i0 - 1 : 0; ip <= i0; ++ip) step(ip, load(ip), std::false_type{}, std::false_type{});
-  for (int ip = i0 + 1; ip < i1; ++ip) step(ip, load(ip), std::false_type{}, std::true_type{});
-  if (i1 < nx)
-    step(i1, load(i1), std::false_type{}, std::true_type{});
-  else
-    step(i1, zero_win(), std::true_type{}, std::true_type{});
+  // completes output nx - 1.
+  const int ip0 = i0 > 0 ? i0 - 1 : 0;
+  if (stage) {
+    // Staged planes: the tile of a plane -- the workgroup's 512 points with
+    // one row and two points of halo on each side -- is copied into LDS by
+    // buffer loads that write LDS directly, one plane ahead into the other
+    // of two buffers, while the current plane's sums run from LDS.  Tile
+    // entries outside the plane read zero; window columns outside the row
+    // read a zero slot.
+    const int T0 = pb * 512 - pz - 2;  // first tile point (even)
+    const int TL = 512 + 2 * pz + 4;   // tile points (even)
+    const uint32_t zoff = ((uint32_t)TL * 12u + 15u) & ~15u;
+    const uint32_t bstride = zoff + 16u;  // one buffer: x tile, m tile, zero slot
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (threadIdx.x < 2) *reinterpret_cast<c32x2*>(stage_lds + threadIdx.x * bstride + zoff) = c32x2{0.f, 0.f, 0.f, 0.f};
+    uint32_t lxp[3], lxl[3], lxr[3], lmp[3], lml[3], lmr[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const uint32_t it = (uint32_t)(e0 - T0 + (r - 1) * pz);
+      const uint32_t mt = (uint32_t)TL * 8u;
+      lxp[r] = it * 8u;
+      lxl[r] = k0 > 0 ? (it - 1u) * 8u : zoff;
+      lxr[r] = k0 + 2 < nz ? (it + 2u) * 8u : zoff;
+      lmp[r] = mt + it * 4u;
+      lml[r] = k0 > 0 ? mt + (it - 1u) * 4u : zoff;
+      lmr[r] = k0 + 2 < nz ? mt + (it + 2u) * 4u : zoff;
+    }
+    auto fill = [&](const int ip, const uint32_t boff) __attribute__((always_inline)) {
+      const prsrc rx = plane_rsrc(xseg + (int64_t)ip * plane * 8, (uint32_t)plane * 8u);
+      const prsrc rm = plane_rsrc(mseg + (int64_t)ip * plane * 4, (uint32_t)plane * 4u);
+      for (int c0 = 0; c0 < TL / 2; c0 += 256) {  // x: 16-byte chunks (two points)
+        const int c = c0 + (int)threadIdx.x;
+        if (c < TL / 2)
+          pld_lds16(rx, stage_lds + boff + (uint32_t)(c0 + wave * 64) * 16u, (uint32_t)((T0 + 2 * c) * 8));
+      }
+      for (int c0 = 0; c0 < TL; c0 += 256) {  // m: one point per lane
+        const int c = c0 + (int)threadIdx.x;
+        if (c < TL)
+          pld_lds4(rm, stage_lds + boff + (uint32_t)TL * 8u + (uint32_t)(c0 + wave * 64) * 4u,
+                   (uint32_t)((T0 + c) * 4));
+      }
+    };
+    auto read_win = [&](const uint32_t boff) __attribute__((always_inline)) {
+      Win w;
+      const char* const lb = stage_lds + boff;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const c32x2 pr = *reinterpret_cast<const c32x2*>(lb + lxp[r]);
+        w.X[r][0] = *reinterpret_cast<const c32*>(lb + lxl[r]);
+        w.X[r][1] = mk(pr.a, pr.b);
+        w.X[r][2] = mk(pr.c, pr.d);
+        w.X[r][3] = *reinterpret_cast<const c32*>(lb + lxr[r]);
+        if (!ADJ) {
+          const c32 mp = *reinterpret_cast<const c32*>(lb + lmp[r]);
+          w.M[r][0] = *reinterpret_cast<const float*>(lb + lml[r]);
+          w.M[r][1] = mp.re;
+          w.M[r][2] = mp.im;
+          w.M[r][3] = *reinterpret_cast<const float*>(lb + lmr[r]);
+        }
+      }
+      if (ADJ) {
+        const c32 mp = *reinterpret_cast<const c32*>(lb + lmp[1]);
+        w.mown[0] = mp.re;
+        w.mown[1] = mp.im;
+      }
+      return w;
+    };
+    auto settle = [&]() __attribute__((always_inline)) {
+      wait_vmem();
+      __syncthreads();
+    };
+    uint32_t cur = 0;
+    fill(ip0, cur);
+    settle();
+    int ip = ip0;
+    for (; ip <= i0; ++ip) {
+      if (ip + 1 < nx) fill(ip + 1, bstride - cur);
+      step(ip, read_win(cur), std::false_type{}, std::false_type{});
+      settle();
+      cur = bstride - cur;
+    }
+    for (; ip < i1; ++ip) {
+      if (ip + 1 < nx) fill(ip + 1, bstride - cur);
+      step(ip, read_win(cur), std::false_type{}, std::true_type{});
+      settle();
+      cur = bstride - cur;
+    }
+    if (i1 < nx)
+      step(i1, read_win(cur), std::false_type{}, std::true_type{});
+    else
+      step(i1, zero_win(), std::true_type{}, std::true_type{});
+  } else {
+    for (int ip = ip0; ip <= i0; ++ip) step(ip, load(ip), std::false_type{}, std::false_type{});
+    for (int ip = i0 + 1; ip < i1; ++ip) step(ip, load(ip), std::false_type{}, std::true_type{});
+    if (i1 < nx)
+      step(i1, load(i1), std::false_type{}, std::true_type{});
+    else
+      step(i1, zero_win(), std::true_type{}, std::true_type{});
+  }
   if (NORM) {
     const double s = block_sum(nrm, red);
     if (threadIdx.x == 0) *pslot = s;
