@@ -31,7 +31,7 @@ def _to_dev(a, dtype):
 @pytest.mark.parametrize("adjoint", [False, True])
 @pytest.mark.parametrize("n,npml,nrhs", [((70, 37, 67), 6, 2), ((9, 13, 20), 2, 3),
                                          ((33, 17, 129), 5, 1), ((21, 35, 46), 4, 2),
-                                         ((7, 11, 4), 0, 2)])
+                                         ((7, 11, 4), 0, 2), ((6, 5, 600), 1, 2)])
 def test_apply_matches_oracle(dtype, stencil, adjoint, n, npml, nrhs):
     print(f"case apply dtype={dtype} stencil={stencil} adj={adjoint} n={n}", flush=True)
     rng, m, vref, omega, h = _case(n, npml, seed=sum(n) + nrhs)

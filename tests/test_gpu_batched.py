@@ -83,3 +83,33 @@ def test_batched_adjoint():
         assert inf.status == 0
         ue = fwi.LUSolver(g, m_t.cpu().numpy().astype(np.float64))(q, adjoint=True)
         assert np.linalg.norm(u.cpu().numpy() - ue) <= 1e-5 * np.linalg.norm(ue)
+
+
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_batched_27pt_uneven_matches_oracle(adjoint):
+    """Uneven compact 27-point members (even and odd nz, so different z
+    pitches and staged tile sizes in one launch) against the oracle's exact
+    solutions."""
+    print(f"case batched 27-point uneven adjoint={adjoint}", flush=True)
+    w27 = workloads.W27_DEFAULT
+    rng = np.random.default_rng(44)
+    shapes = [(22, 18, 26), (17, 24, 19), (20, 20, 31)]
+    probs, refs = [], []
+    for n in shapes:
+        v = 1800.0 + 1200.0 * rng.random(n)
+        m = 1.0 / v ** 2
+        omega, h, npml = 2 * np.pi * 5.0, 20.0, 4
+        grid = hx.Grid(n=n, h=h, npml=npml, v_ref=float(v.max()), stencil="27pt", dtype="c64", w27=w27)
+        g = ops.make_grid(n, h, npml, omega, float(v.max()))
+        m_t = torch.tensor(m, dtype=torch.float32, device=DEV)
+        q = fwi.point_source(g, (n[0] // 2, n[1] // 2, n[2] // 2))
+        q_t = torch.tensor(q, dtype=torch.complex64, device=DEV)
+        probs.append((grid, m_t, omega, q_t))
+        m_used = m_t.cpu().numpy().astype(np.float64)
+        q_used = q_t.cpu().numpy().astype(np.complex128)
+        refs.append(fwi.LUSolver(g, m_used, "27pt", w27)(q_used, adjoint=adjoint))
+    us, infos = hx.helm_solve_batched(probs, adjoint=adjoint, opts=hx.SolverOpts(tol=1e-8, max_cycles=80))
+    for u, info, ue in zip(us, infos, refs):
+        assert info.status == 0 and info.relres_fp64 <= 1e-8
+        ub = u.cpu().numpy().astype(np.complex128)
+        assert np.linalg.norm(ub - ue) <= 1e-5 * np.linalg.norm(ue)
