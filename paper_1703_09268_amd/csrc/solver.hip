@@ -103,6 +103,8 @@ class Solver {
   // Solve with every segment in direction `dir` (0: H, 1: H^H).  q, u:
   // level-0 vectors (segment s at offset Seg::off).  Returns the worst status.
   int solve(int dir, const cx<T>* q, cx<T>* u, SolveInfo* info) {
+    HELM_REQUIRE(dir == 0 || dir == 1, "direction must be 0 (H) or 1 (H^H)");
+    dir_ = dir;
     H_->set_dir(dir);
     H_->refresh_fine_models();
     H_->template inject_models<T>();
@@ -311,13 +313,16 @@ class Solver {
     active_ = reinterpret_cast<int*>(sc);
   }
 
-  // Arnoldi steps + update of one outer cycle: replayed from a graph.
+  // Arnoldi steps + update of one outer cycle: replayed from a graph, one
+  // per direction (the launches of H and of H^H may differ: the compact
+  // 27-point passes are separate kernels for the two).
   void run_cycle_body() {
     if (!graphs_enabled()) {
       cycle_body();
       return;
     }
-    if (!exec_) {
+    const int d = dir_;
+    if (!exec_[d]) {
       const int64_t mv0 = fine_mv_;
       HELM_HIP_CHECK(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
       try {
@@ -328,20 +333,22 @@ class Solver {
         if (g) (void)hipGraphDestroy(g);
         throw;
       }
-      HELM_HIP_CHECK(hipStreamEndCapture(st_, &graph_));
-      HELM_HIP_CHECK(hipGraphInstantiate(&exec_, graph_, nullptr, nullptr, 0));
-      body_mv_ = fine_mv_ - mv0;
+      HELM_HIP_CHECK(hipStreamEndCapture(st_, &graph_[d]));
+      HELM_HIP_CHECK(hipGraphInstantiate(&exec_[d], graph_[d], nullptr, nullptr, 0));
+      body_mv_[d] = fine_mv_ - mv0;
       fine_mv_ = mv0;
     }
-    HELM_HIP_CHECK(hipGraphLaunch(exec_, st_));
-    fine_mv_ += body_mv_;
+    HELM_HIP_CHECK(hipGraphLaunch(exec_[d], st_));
+    fine_mv_ += body_mv_[d];
   }
 
   void drop_graph() {
-    if (exec_) (void)hipGraphExecDestroy(exec_);
-    if (graph_) (void)hipGraphDestroy(graph_);
-    exec_ = nullptr;
-    graph_ = nullptr;
+    for (int d = 0; d < 2; ++d) {
+      if (exec_[d]) (void)hipGraphExecDestroy(exec_[d]);
+      if (graph_[d]) (void)hipGraphDestroy(graph_[d]);
+      exec_[d] = nullptr;
+      graph_[d] = nullptr;
+    }
   }
 
   void cycle_body() {
@@ -554,10 +561,11 @@ class Solver {
   Space outer_;
   std::vector<Space> smooth_, coarse_;
   std::vector<cx<T>*> R_, B_, Xc_;
-  int64_t fine_mv_ = 0, body_mv_ = 0;
+  int64_t fine_mv_ = 0, body_mv_[2] = {0, 0};
+  int dir_ = 0;  // direction of the current solve (0: H, 1: H^H)
   bool fused_dots_ = fused_dots_enabled();
-  hipGraph_t graph_ = nullptr;
-  hipGraphExec_t exec_ = nullptr;
+  hipGraph_t graph_[2] = {nullptr, nullptr};
+  hipGraphExec_t exec_[2] = {nullptr, nullptr};
 };
 
 }  // namespace helm

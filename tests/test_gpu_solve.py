@@ -185,3 +185,28 @@ def test_empty_inputs_are_rejected_through_the_abi():
         assert b"nsrc" in lib.helm_last_error(ctx)
     finally:
         lib.helm_destroy(ctx)
+
+
+def test_27pt_adjoint_after_forward_on_one_solver():
+    """A forward and then an adjoint solve through the same cached solver
+    (same grid, model and frequency): the adjoint solve runs the adjoint
+    passes, so it takes exactly the cycles of an adjoint solve on a solver
+    that never ran forward, and both match the oracle's exact solution."""
+    print("case 27pt adjoint after forward", flush=True)
+    w = workloads.layered_random_workload((26, 24, 30), 20.0, 5, 6.0, nsrc_xy=(2, 1), seed=13)
+    w.stencil = "27pt"
+    w.w27 = workloads.W27_DEFAULT
+    grid, g, m_t, m_used, cdt = _setup(w, "c64")
+    q, q_t = _sources(g, w.src, cdt)
+    opts = hx.SolverOpts(tol=1e-8, max_cycles=60)
+    hx.helm_solve(grid, m_t, w.omega, q_t, opts=opts)
+    u_a, info_a = hx.helm_solve(grid, m_t, w.omega, q_t, adjoint=True, opts=opts)
+    m2 = m_t.clone()  # another model buffer: a solver of its own
+    u_b, info_b = hx.helm_solve(grid, m2, w.omega, q_t, adjoint=True, opts=opts)
+    assert [i.cycles for i in info_a] == [i.cycles for i in info_b]
+    assert torch.linalg.norm(u_a - u_b).item() <= 1e-6 * torch.linalg.norm(u_b).item()
+    lu = fwi.LUSolver(g, m_used, "27pt", w.w27)
+    u = u_a.cpu().numpy().astype(np.complex128)
+    for s in range(len(w.src)):
+        ue = lu(q[s], adjoint=True)
+        assert np.linalg.norm(u[s] - ue) <= 1e-5 * np.linalg.norm(ue)
