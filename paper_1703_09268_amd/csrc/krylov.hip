@@ -174,22 +174,43 @@ __device__ __forceinline__ double basis_scale(double s) {
 // Finish Arnoldi column j of segment sid from s = ||w||^2 (sum of the
 // partials): h_{j+1,j} = sqrt(s); apply the previous rotations to column j,
 // build rotation j, update g, set scale_{j+1} = 1/h_{j+1,j} (0 on
-// breakdown).  One thread.
-__device__ __forceinline__ void givens_column(const KState& st, int sid, int j, double s) {
+// breakdown).  The whole workgroup first stages what this needs in LDS
+// (givens_stage: one memory round trip; a single thread's loads would each
+// wait behind its stores to the same arrays), then one thread finishes it
+// (givens_finish), leaving the rotated column and g_j in the stage.
+struct GivensStage {
+  double2 col[KMAX + 1];  // H[0..j][j]
+  double cs[KMAX];
+  double2 sn[KMAX];
+  double2 g[KMAX + 1];    // g_0..g_j
+};
+
+// all threads; a barrier must follow before givens_finish
+__device__ __forceinline__ void givens_stage(const KState& st, int sid, int j, int gcount, GivensStage& G) {
+  const int ns = st.nseg;
+  const int t = threadIdx.x;
+  if (t <= j) G.col[t] = st.H[(t * KMAX + j) * ns + sid];
+  if (t < j) {
+    G.cs[t] = st.cs[t * ns + sid];
+    G.sn[t] = st.sn[t * ns + sid];
+  }
+  if (t < gcount) G.g[t] = st.g[t * ns + sid];  // gcount >= j + 1
+}
+
+// one thread
+__device__ __forceinline__ void givens_finish(const KState& st, int sid, int j, double s, GivensStage& G) {
   const int ns = st.nseg;
   const double hn = sqrt(s);
   for (int i = 0; i < j; ++i) {
-    const double2 a = st.H[(i * KMAX + j) * ns + sid];
-    const double2 b = st.H[((i + 1) * KMAX + j) * ns + sid];
-    const double c = st.cs[i * ns + sid];
-    const double2 sn = st.sn[i * ns + sid];
+    const double2 a = G.col[i];
+    const double2 b = G.col[i + 1];
+    const double c = G.cs[i];
+    const double2 sn = G.sn[i];
     // [c, s; -conj(s), c] [a; b]
-    const double2 na = d2(c * a.x + (sn.x * b.x - sn.y * b.y), c * a.y + (sn.x * b.y + sn.y * b.x));
-    const double2 nb = d2(-(sn.x * a.x + sn.y * a.y) + c * b.x, -(sn.x * a.y - sn.y * a.x) + c * b.y);
-    st.H[(i * KMAX + j) * ns + sid] = na;
-    st.H[((i + 1) * KMAX + j) * ns + sid] = nb;
+    G.col[i] = d2(c * a.x + (sn.x * b.x - sn.y * b.y), c * a.y + (sn.x * b.y + sn.y * b.x));
+    G.col[i + 1] = d2(-(sn.x * a.x + sn.y * a.y) + c * b.x, -(sn.x * a.y - sn.y * a.x) + c * b.y);
   }
-  const double2 a = st.H[(j * KMAX + j) * ns + sid];
+  const double2 a = G.col[j];
   const double absa = hypot(a.x, a.y);
   double c;
   double2 sn, rr;
@@ -208,14 +229,17 @@ __device__ __forceinline__ void givens_column(const KState& st, int sid, int j, 
     sn = d2(ph.x * hn / nrm, ph.y * hn / nrm);  // (a/|a|) conj(b)/nrm, b real
     rr = d2(ph.x * nrm, ph.y * nrm);
   }
+  G.col[j] = rr;
+  for (int i = 0; i <= j; ++i) st.H[(i * KMAX + j) * ns + sid] = G.col[i];
+  st.H[((j + 1) * KMAX + j) * ns + sid] = d2(0.0, 0.0);
   st.cs[j * ns + sid] = c;
   st.sn[j * ns + sid] = sn;
-  st.H[(j * KMAX + j) * ns + sid] = rr;
-  st.H[((j + 1) * KMAX + j) * ns + sid] = d2(0.0, 0.0);
-  const double2 gj = st.g[j * ns + sid];
+  const double2 gj = G.g[j];
   // g_{j+1} = -conj(s) g_j ; g_j = c g_j
-  st.g[(j + 1) * ns + sid] = d2(-(sn.x * gj.x + sn.y * gj.y), -(sn.x * gj.y - sn.y * gj.x));
-  st.g[j * ns + sid] = d2(c * gj.x, c * gj.y);
+  const double2 g1 = d2(-(sn.x * gj.x + sn.y * gj.y), -(sn.x * gj.y - sn.y * gj.x));
+  G.g[j] = d2(c * gj.x, c * gj.y);
+  st.g[(j + 1) * ns + sid] = g1;
+  st.g[j * ns + sid] = G.g[j];
   st.scale[(j + 1) * ns + sid] = basis_scale(s);
 }
 
@@ -230,16 +254,24 @@ __global__ __launch_bounds__(256) void k_reduce_dots(const Seg* __restrict__ seg
                                                      int which, const double* __restrict__ src, int gprev,
                                                      const int* __restrict__ active) {
   __shared__ double red[4 * 2 * NVMAX > 4 ? 4 * 2 * NVMAX : 4];
+  __shared__ GivensStage G;
+  __shared__ double scl[NVMAX];
   const int sid = blockIdx.x;
   if (active && !active[sid]) return;
   const Seg& S = segs[sid];
   const int ns = st.nseg;
   if (EXACT) nv = NVMAX;
+  // the basis scales, loaded together (scale_j is set by the deferred step)
+  if ((int)threadIdx.x < nv) scl[threadIdx.x] = st.scale[threadIdx.x * ns + sid];
   if (gprev >= 0) {
-    const double sn = seg_sum0(st.part, S.vblk0, S.vnblk, red);
-    if (threadIdx.x == 0) givens_column(st, sid, gprev, sn);
-    __syncthreads();  // red is reused below
+    givens_stage(st, sid, gprev, gprev + 1, G);
+    const double sn = seg_sum0(st.part, S.vblk0, S.vnblk, red);  // (its barriers order the stage)
+    if (threadIdx.x == 0) {
+      givens_finish(st, sid, gprev, sn, G);
+      scl[gprev + 1] = basis_scale(sn);
+    }
   }
+  __syncthreads();  // red is reused below; scl complete
   int b0, nb;
   seg_range(S, which, b0, nb);
   double s[2 * NVMAX];
@@ -248,7 +280,7 @@ __global__ __launch_bounds__(256) void k_reduce_dots(const Seg* __restrict__ seg
 #pragma unroll
     for (int i = 0; i < NVMAX; ++i) {
       if (EXACT || i < nv) {
-        const double sc = st.scale[i * ns + sid];
+        const double sc = scl[i];
         const double2 h = d2(sc * s[2 * i], sc * s[2 * i + 1]);
         st.H[(i * KMAX + j) * ns + sid] = h;
         st.coef[i * ns + sid] = d2(h.x * sc, h.y * sc);
@@ -382,17 +414,17 @@ __global__ __launch_bounds__(256) void k_start_cycle(const Seg* __restrict__ seg
   }
 }
 
-// Back substitution R y = g (k x k upper triangular, zero pivots -> y_i = 0).
-__device__ __forceinline__ void solve_upper(const KState& st, int sid, int k, double2* y) {
-  const int ns = st.nseg;
+// Back substitution R y = g (k x k upper triangular, zero pivots -> y_i = 0)
+// from R and g staged in LDS.  One thread.
+__device__ __forceinline__ void solve_upper(const double2* R, const double2* g, int k, double2* y) {
   for (int i = k - 1; i >= 0; --i) {
-    double2 acc = st.g[i * ns + sid];
+    double2 acc = g[i];
     for (int l = i + 1; l < k; ++l) {
-      const double2 h = st.H[(i * KMAX + l) * ns + sid];
+      const double2 h = R[i * KMAX + l];
       acc.x -= h.x * y[l].x - h.y * y[l].y;
       acc.y -= h.x * y[l].y + h.y * y[l].x;
     }
-    const double2 d = st.H[(i * KMAX + i) * ns + sid];
+    const double2 d = R[i * KMAX + i];
     const double den = d.x * d.x + d.y * d.y;
     y[i] = den == 0.0 ? d2(0.0, 0.0)
                       : d2((acc.x * d.x + acc.y * d.y) / den, (acc.y * d.x - acc.x * d.y) / den);
@@ -402,23 +434,32 @@ __device__ __forceinline__ void solve_upper(const KState& st, int sid, int k, do
 // Finish Arnoldi column j (partials of the vector range of st.part).  With
 // solve_k > 0 (the cycle's last column, solve_k = j + 1) also solve R y = g
 // and leave y_i * s_i in coef (s = basis scale, or 1 for a flexible space)
-// for the update of the iterate.
+// for the update of the iterate.  Everything the step reads is staged in
+// LDS by the workgroup first.
 __global__ __launch_bounds__(256) void k_givens(const Seg* __restrict__ segs, KState st, int j, int solve_k,
                                                 int use_scale, const int* __restrict__ active) {
   __shared__ double red[4];
+  __shared__ GivensStage G;
+  __shared__ double2 R[KMAX * KMAX];  // columns 0..solve_k-2 of R (column j comes from G)
+  __shared__ double scl[KMAX];
   const int sid = blockIdx.x;
   if (active && !active[sid]) return;
   const Seg& S = segs[sid];
-  const double s = seg_sum0(st.part, S.vblk0, S.vnblk, red);
+  const int ns = st.nseg;
+  givens_stage(st, sid, j, j + 1, G);
+  for (int idx = threadIdx.x; idx < solve_k * j; idx += blockDim.x) {  // rows 0..solve_k-1, columns 0..j-1
+    const int i = idx / j, l = idx - (idx / j) * j;
+    if (l >= i) R[i * KMAX + l] = st.H[(i * KMAX + l) * ns + sid];
+  }
+  if ((int)threadIdx.x < solve_k) scl[threadIdx.x] = use_scale ? st.scale[threadIdx.x * ns + sid] : 1.0;
+  const double s = seg_sum0(st.part, S.vblk0, S.vnblk, red);  // (its barriers order the stage)
   if (threadIdx.x == 0) {
-    givens_column(st, sid, j, s);
+    givens_finish(st, sid, j, s, G);
     if (solve_k > 0) {
+      for (int i = 0; i <= j; ++i) R[i * KMAX + j] = G.col[i];
       double2 y[KMAX];
-      solve_upper(st, sid, solve_k, y);
-      for (int i = 0; i < solve_k; ++i) {
-        const double sc = use_scale ? st.scale[i * st.nseg + sid] : 1.0;
-        st.coef[i * st.nseg + sid] = d2(y[i].x * sc, y[i].y * sc);
-      }
+      solve_upper(R, G.g, solve_k, y);
+      for (int i = 0; i < solve_k; ++i) st.coef[i * ns + sid] = d2(y[i].x * scl[i], y[i].y * scl[i]);
     }
   }
 }
