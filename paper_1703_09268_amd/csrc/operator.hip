@@ -192,16 +192,17 @@ struct LevelSet {
 constexpr int kMinXchunk = 4;  // smallest x chunk of a stencil tile
 
 // LDS bytes per workgroup of the staged 27-point pair pass: two plane tiles
-// of (512 + 2 pz + 4) complex64 and float values plus 16 zero bytes each,
-// for the widest z pitch of the level; 0 (register path) when that exceeds
-// 40 KiB (four workgroups per CU must still fit) or with HELM_STAGE27=0.
+// of (512 + 2 pz + 4) complex64 and (up to 4 more) float values plus 16
+// zero bytes each, for the widest z pitch of the level; 0 (register path)
+// when that exceeds 40 KiB (four workgroups per CU must still fit) or with
+// HELM_STAGE27=0.
 inline int stage27_bytes(const std::vector<Seg>& segs) {
   if (const char* e = std::getenv("HELM_STAGE27"))
     if (e[0] == '0') return 0;
   int pzm = 0;
   for (const Seg& S : segs) pzm = std::max(pzm, S.pz);
   const int64_t tl = 512 + 2 * (int64_t)pzm + 4;
-  const int64_t buf = ((tl * 12 + 15) / 16) * 16 + 16;
+  const int64_t buf = ((tl * 8 + (tl + 4) * 4 + 15) / 16) * 16 + 16;
   return 2 * buf <= 40 * 1024 ? (int)(2 * buf) : 0;
 }
 

@@ -785,21 +785,25 @@ __global__ __launch_bounds__(256) void k_h27p(const Seg* __restrict__ segs, cons
     // read a zero slot.
     const int T0 = pb * 512 - pz - 2;  // first tile point (even)
     const int TL = 512 + 2 * pz + 4;   // tile points (even)
-    const uint32_t zoff = ((uint32_t)TL * 12u + 15u) & ~15u;
+    const int Tm0 = T0 & ~3;           // model tile from a multiple of 4 (16-byte chunks)
+    const int TLm = (T0 - Tm0 + TL + 3) & ~3;
+    const uint32_t mt = (uint32_t)TL * 8u;  // model tile offset (16-byte aligned)
+    const uint32_t zoff = (mt + (uint32_t)TLm * 4u + 15u) & ~15u;
     const uint32_t bstride = zoff + 16u;  // one buffer: x tile, m tile, zero slot
+    const bool m16 = (plane & 3) == 0;    // no 16-byte model chunk straddles the plane's end
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if (threadIdx.x < 2) *reinterpret_cast<c32x2*>(stage_lds + threadIdx.x * bstride + zoff) = c32x2{0.f, 0.f, 0.f, 0.f};
     uint32_t lxp[3], lxl[3], lxr[3], lmp[3], lml[3], lmr[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
       const uint32_t it = (uint32_t)(e0 - T0 + (r - 1) * pz);
-      const uint32_t mt = (uint32_t)TL * 8u;
+      const uint32_t im = (uint32_t)(e0 - Tm0 + (r - 1) * pz);
       lxp[r] = it * 8u;
       lxl[r] = k0 > 0 ? (it - 1u) * 8u : zoff;
       lxr[r] = k0 + 2 < nz ? (it + 2u) * 8u : zoff;
-      lmp[r] = mt + it * 4u;
-      lml[r] = k0 > 0 ? mt + (it - 1u) * 4u : zoff;
-      lmr[r] = k0 + 2 < nz ? mt + (it + 2u) * 4u : zoff;
+      lmp[r] = mt + im * 4u;
+      lml[r] = k0 > 0 ? mt + (im - 1u) * 4u : zoff;
+      lmr[r] = k0 + 2 < nz ? mt + (im + 2u) * 4u : zoff;
     }
     auto fill = [&](const int ip, const uint32_t boff) __attribute__((always_inline)) {
       const prsrc rx = plane_rsrc(xseg + (int64_t)ip * plane * 8, (uint32_t)plane * 8u);
@@ -809,11 +813,18 @@ __global__ __launch_bounds__(256) void k_h27p(const Seg* __restrict__ segs, cons
         if (c < TL / 2)
           pld_lds16(rx, stage_lds + boff + (uint32_t)(c0 + wave * 64) * 16u, (uint32_t)((T0 + 2 * c) * 8));
       }
-      for (int c0 = 0; c0 < TL; c0 += 256) {  // m: one point per lane
-        const int c = c0 + (int)threadIdx.x;
-        if (c < TL)
-          pld_lds4(rm, stage_lds + boff + (uint32_t)TL * 8u + (uint32_t)(c0 + wave * 64) * 4u,
-                   (uint32_t)((T0 + c) * 4));
+      if (m16) {
+        for (int c0 = 0; c0 < TLm / 4; c0 += 256) {  // m: 16-byte chunks (four points)
+          const int c = c0 + (int)threadIdx.x;
+          if (c < TLm / 4)
+            pld_lds16(rm, stage_lds + boff + mt + (uint32_t)(c0 + wave * 64) * 16u, (uint32_t)((Tm0 + 4 * c) * 4));
+        }
+      } else {
+        for (int c0 = 0; c0 < TLm; c0 += 256) {  // m: one point per lane
+          const int c = c0 + (int)threadIdx.x;
+          if (c < TLm)
+            pld_lds4(rm, stage_lds + boff + mt + (uint32_t)(c0 + wave * 64) * 4u, (uint32_t)((Tm0 + c) * 4));
+        }
       }
     };
     auto read_win = [&](const uint32_t boff) __attribute__((always_inline)) {
