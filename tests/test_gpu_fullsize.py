@@ -119,3 +119,57 @@ def test_c5_full_27pt_solve_is_certified():
         rel = _relres(g, m_used, u[s].cpu().numpy(), q, stencil="27pt", w27=w.w27)
         assert rel <= 1e-6
         assert abs(rel - infos[s].relres_fp64) <= 1e-3 * rel
+
+
+def test_c3_full_fwi_gradient_directional_difference():
+    """96^3 FWI configuration at full size (64 sources in one multi-source
+    solve, 48x48 receivers, data from the true model, gradient at the
+    smoothed start): sampled forward fields certified by the oracle's FP64
+    residual, every solve converged, and the adjoint-state gradient against
+    a central difference of the misfit along a smooth random direction dm,
+    <g, dm> = (f(m + dm) - f(m - dm)) / 2, to 1e-3 relative.  The misfits
+    come from tight GPU solves (FP64 iterates); the quotient's own error is
+    of order |dm|^2."""
+    from scipy import ndimage
+    print("case full c3 96^3 x 64 sources gradient", flush=True)
+    w = workloads.c3_fwi()
+    grid = hx.Grid(n=w.n, h=w.h, npml=w.npml, v_ref=w.v_ref, dtype="c64")
+    nsrc = len(w.src)
+    tight = hx.SolverOpts(tol=1e-9, max_cycles=80)
+    mt_t = torch.tensor(w.m_true, dtype=torch.float32, device=DEV)
+    u = torch.empty((nsrc,) + w.n, dtype=torch.complex64, device=DEV)
+    hx.misfit_gradient(grid, mt_t, w.omega, w.src, w.rec,
+                       torch.zeros((nsrc, len(w.rec)), dtype=torch.complex64, device=DEV),
+                       u_store=u, forward_only=True, opts=tight)
+    ridx = torch.tensor(np.asarray(w.rec, np.int64), device=DEV)
+    d_t = u[:, ridx[:, 0], ridx[:, 1], ridx[:, 2]].contiguous()
+    del u, mt_t
+    m_t = torch.tensor(w.m, dtype=torch.float32, device=DEV)
+    uf = torch.empty((nsrc,) + w.n, dtype=torch.complex128, device=DEV)
+    f0, grad, infos = hx.misfit_gradient(grid, m_t, w.omega, w.src, w.rec, d_t, u_store=uf, u_fp64=True,
+                                         opts=tight)
+    assert len(infos) == 2 * nsrc and all(i.status == 0 and i.relres_fp64 <= 1e-9 for i in infos)
+    g = ops.make_grid(w.n, w.h, w.npml, w.omega, w.v_ref)
+    m_used = m_t.cpu().numpy().astype(np.float64)
+    for s in (0, 37, 63):
+        q = fwi.point_source(g, tuple(w.src[s])).astype(np.complex64).astype(np.complex128)
+        assert _relres(g, m_used, uf[s].cpu().numpy(), q) <= 2e-9
+    del uf
+    rng = np.random.default_rng(5)
+    dm = ndimage.gaussian_filter(rng.standard_normal(w.n), 3.0)
+    p = w.npml
+    mask = np.zeros(w.n)
+    mask[p:-p, p:-p, p:-p] = 1.0
+    dm = dm * mask
+    dm *= 1e-3 * m_used.min() / np.abs(dm).max()
+    mp = torch.tensor(m_used + dm, dtype=torch.float32, device=DEV)
+    mm = torch.tensor(m_used - dm, dtype=torch.float32, device=DEV)
+    fp, _, ip = hx.misfit_gradient(grid, mp, w.omega, w.src, w.rec, d_t, forward_only=True, opts=tight)
+    fm, _, im = hx.misfit_gradient(grid, mm, w.omega, w.src, w.rec, d_t, forward_only=True, opts=tight)
+    assert all(i.status == 0 for i in ip + im)
+    # the direction the GPU actually saw (both models rounded to float32)
+    dm_used = (mp.cpu().numpy().astype(np.float64) - mm.cpu().numpy().astype(np.float64)) / 2
+    lin = float(np.sum(grad.cpu().numpy().astype(np.float64) * dm_used))
+    fd = (fp - fm) / 2
+    print(f"c3 directional: <g,dm> = {lin:.6e}, central difference = {fd:.6e}", flush=True)
+    assert abs(fd - lin) <= 1e-3 * abs(lin)
