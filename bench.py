@@ -60,7 +60,8 @@ def parse():
                    help="also time the 320x320x160 27-point misfit + gradient (about 75 s more)")
     p.add_argument("--c5-only", action="store_true")
     p.add_argument("--stencil27-only", action="store_true",
-                   help="only the 27-point operator timing on the 320x320x160 workload")
+                   help="only the 27-point operator timing on the 320x320x160 workload (and a plain "
+                        "copy of the same size, the calibration of hardware-counter runs)")
     p.add_argument("--batch-only", action="store_true", help="only batched vs plain")
     return p.parse_args()
 
@@ -315,7 +316,11 @@ def main():
         print(json.dumps(c5_gradient(hx, torch, workloads, dev)), flush=True)
         return
     if args.stencil27_only:
-        print(json.dumps(stencil27_timing(hx, torch, workloads, args.stencil_reps, dev)), flush=True)
+        rec = stencil27_timing(hx, torch, workloads, args.stencil_reps, dev)
+        n27 = 8 * 320 * 320 * 160  # the 8 right-hand sides of the 320x320x160 grid
+        cms, cgbs = copy_timing(torch, n27, args.stencil_reps, dev)
+        rec.update({"copy_ms": cms, "copy_GB_s": cgbs, "copy_bytes_per_launch": 16 * n27})
+        print(json.dumps(rec), flush=True)
         return
     if args.batch_only:
         print(json.dumps(batched_vs_plain(hx, torch, workloads, args.batch_count, dev)), flush=True)

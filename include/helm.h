@@ -191,42 +191,67 @@ helm_status helm_solve_batched(helm_ctx* ctx, int nprob, const helm_problem* pro
 
 /* misfit_gradient flags */
 #define HELM_MG_FORWARD_ONLY 1 /* solve forward, return f; no gradient     */
-#define HELM_MG_REUSE_U 2      /* u_store already holds H^{-1} q_s         */
+#define HELM_MG_REUSE_U 2      /* u_store already holds H^{-1} q           */
 #define HELM_MG_ACCUMULATE 4   /* g += gradient instead of g = gradient    */
 #define HELM_MG_U_FP64 8       /* u_store holds complex128 fields (the FP64
-                                  outer iterates) even for HELM_C64 grids   */
+                                  outer iterates) even for HELM_C64 grids;
+                                  u_store must not be NULL                  */
+#define HELM_MG_RENORMALISE 16 /* f and g are divided by the number of
+                                  selected (frequency, source) pairs: the
+                                  average of the subsampled objective       */
 
-/* Least-squares misfit and its adjoint-state gradient for one frequency
- * (paper, Listing of PDEfunc, case OBJ; Table derivstuff rows u, V, grad f;
- * Appendix A, eq. dHadj):
- *   q_s = amp_s e_{src_s} / h^3            (on-node point source)
- *   u_s = H^{-1} q_s,   r_s = P_r u_s - d_s,   f = 1/2 sum_s ||r_s||^2
- *   v_s = -H^{-H} P_r^T r_s
- *   g   = sum_s Re(omega^2 conj(u_s) * (A^H v_s))   (real, N entries)
+/* Least-squares misfit and its adjoint-state gradient summed over the
+ * selected (frequency, source) pairs (paper: Preamble eq. mainprob, the sum
+ * over sources and frequencies; Listing of PDEfunc, case OBJ; Table
+ * derivstuff rows u, V, grad f; Appendix A, eq. dHadj; the source/frequency
+ * mask and the averaged subsampled objective of the Software Design and
+ * stochastic-inversion sections):
+ *   q_fs = amp_fs e_{src_s} / h^3                (on-node point source)
+ *   u_fs = H_f^{-1} q_fs,   r_fs = P_r u_fs - d_fs
+ *   f    = c * 1/2 sum_{(f,s) selected} ||r_fs||^2
+ *   v_fs = -H_f^{-H} P_r^T r_fs
+ *   g    = c * sum_{(f,s) selected} Re(omega_f^2 conj(u_fs) * (A^H v_fs))
+ * with H_f = H(m) at omega_f, c = 1 (c = 1/#selected with
+ * HELM_MG_RENORMALISE).  All selected pairs are solved together: one
+ * forward and one adjoint multi-right-hand-side solve whose right-hand
+ * sides may have different frequencies (every kernel covers all of them).
  * The receiver residual is formed from the FP64 outer iterate of the
  * forward solve (or from u_store with HELM_MG_REUSE_U; store the fields with
  * HELM_MG_U_FP64 to keep that residual accurate when r is much smaller than
  * u at the receivers).
  * Arguments:
  *   m        dev, N reals (float for C64, double for C128)
- *   nsrc     number of sources (>= 1), solved together as one block
- *   src_idx  host int32 [nsrc][3] node indices (i, j, k)
- *   src_amp  host double [nsrc][2] complex amplitudes (NULL = all 1)
+ *   nfreq    number of frequencies (>= 1); omega host double [nfreq],
+ *            angular frequencies, each > 0
+ *   nsrc     number of sources (>= 1); src_idx host int32 [nsrc][3] node
+ *            indices (i, j, k)
+ *   src_amp  host double [nfreq][nsrc][2] complex amplitudes (NULL = all 1)
+ *   mask     host uint8 [nfreq][nsrc]: nonzero selects the pair (NULL = all
+ *            pairs); unselected pairs are neither solved nor summed
  *   nrec     number of receivers (>= 1); rec_idx host int32 [nrec][3]
- *   d        dev, [nsrc][nrec] complex of g->dtype, observed data
+ *   d        dev, [nfreq][nsrc][nrec] complex of g->dtype, observed data
+ *            (rows of unselected pairs are not read)
  *   f        host, receives the misfit (FP64 accumulation)
  *   grad     dev, N reals (float for C64, double for C128); overwritten
  *            (or accumulated into with HELM_MG_ACCUMULATE); may be NULL
  *            with HELM_MG_FORWARD_ONLY
- *   u_store  dev, [nsrc][N] complex of g->dtype (complex128 with
- *            HELM_MG_U_FP64) or NULL: receives the forward fields (or
- *            supplies them with HELM_MG_REUSE_U)
+ *   u_store  dev, [nfreq][nsrc][N] complex of g->dtype (complex128 with
+ *            HELM_MG_U_FP64) or NULL: receives the forward fields of the
+ *            selected pairs (or supplies them with HELM_MG_REUSE_U); rows of
+ *            unselected pairs are left untouched
  *   flags    HELM_MG_* bits
- *   info     host, 2*nsrc entries (forward then adjoint solves) or NULL
- * Returns the worst status of the solves. */
+ *   info     host, 2*nfreq*nsrc entries or NULL: forward solve of pair
+ *            (f, s) at f*nsrc + s, adjoint solve at nfreq*nsrc + f*nsrc + s;
+ *            entries of unselected pairs and of solves not run are zero
+ * Invalid arguments (see the top of this file; also a NULL u_store with
+ * HELM_MG_REUSE_U or HELM_MG_U_FP64, unknown flag bits) return HELM_E_INVAL
+ * before any device work.  With no pair selected f = 0 and g = 0 (or
+ * unchanged with HELM_MG_ACCUMULATE).  Returns the worst status of the
+ * solves. */
 helm_status misfit_gradient(helm_ctx* ctx, const helm_grid* g, const void* m,
-                            double omega, int nsrc, const int32_t* src_idx,
-                            const double* src_amp, int nrec,
+                            int nfreq, const double* omega, int nsrc,
+                            const int32_t* src_idx, const double* src_amp,
+                            const uint8_t* mask, int nrec,
                             const int32_t* rec_idx, const void* d, double* f,
                             void* grad, void* u_store, int flags,
                             const helm_solver_opts* o, helm_solve_info* info,

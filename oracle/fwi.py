@@ -99,6 +99,53 @@ def misfit_gradient(g: ops.Grid, m, src, rec, d, amp=None, stencil="7pt",
     return f, gradient(g, us, vs, stencil, w27), us, vs
 
 
+def misfit_gradient_pairs(g: ops.Grid, m, omegas, src, rec, d, amp=None,
+                          mask=None, renormalise=False, stencil="7pt",
+                          w27=None):
+    """f and g summed over (frequency, source) pairs.
+
+    The reduced objective sums the least-squares misfit over every source and
+    frequency (Preamble, eq. mainprob: the double sum over i and j); a subset
+    of the pairs may be selected (the source/frequency mask of the Software
+    Design section), and the stochastic formulation averages over the
+    selected pairs, 1/|I| sum_{i in I} f_i (Stochastic FWI section):
+    ``renormalise`` divides f and g by the number of selected pairs.
+
+    omegas  angular frequencies, length nfreq (g.omega is not used)
+    d       observed data [nfreq][nsrc][nrec]
+    amp     source amplitudes [nfreq][nsrc] (default 1)
+    mask    bool [nfreq][nsrc] of the selected pairs (default: all)
+    Returns (f, g, us, vs) with us/vs dicts keyed by (frequency, source).
+    """
+    from dataclasses import replace
+    src = np.asarray(src)
+    nf, ns = len(omegas), len(src)
+    amp = np.ones((nf, ns), np.complex128) if amp is None else np.asarray(amp).reshape(nf, ns)
+    mask = np.ones((nf, ns), bool) if mask is None else np.asarray(mask, bool).reshape(nf, ns)
+    d = np.asarray(d).reshape(nf, ns, -1)
+    f_tot = 0.0
+    g_tot = np.zeros(g.n, dtype=np.float64)
+    us, vs = {}, {}
+    for fi, om in enumerate(omegas):
+        sel = np.nonzero(mask[fi])[0]
+        if len(sel) == 0:
+            continue
+        gf = replace(g, omega=float(om))
+        f, grad, uu, vv = misfit_gradient(gf, m, src[sel], rec, d[fi, sel],
+                                          amp=amp[fi, sel], stencil=stencil,
+                                          w27=w27)
+        f_tot += f
+        g_tot += grad
+        for k, s in enumerate(sel):
+            us[(fi, int(s))] = uu[k]
+            vs[(fi, int(s))] = vv[k]
+    npair = int(mask.sum())
+    if renormalise and npair > 0:
+        f_tot /= npair
+        g_tot /= npair
+    return f_tot, g_tot, us, vs
+
+
 def exact_central_difference(g: ops.Grid, m, k, eps, us, rs, rec, solve,
                              stencil="7pt", w27=None):
     """(f(m + eps e_k) - f(m - eps e_k)) / (2 eps) without cancellation.

@@ -27,6 +27,7 @@ HELM_MG_FORWARD_ONLY = 1
 HELM_MG_REUSE_U = 2
 HELM_MG_ACCUMULATE = 4
 HELM_MG_U_FP64 = 8
+HELM_MG_RENORMALISE = 16
 
 STATUS_NAMES = {
     HELM_OK: "HELM_OK",
@@ -97,9 +98,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.helm_apply.argtypes = [vp, G, vp, dbl, i32, i32, vp, vp, vp]
     lib.helm_solve.argtypes = [vp, G, vp, dbl, i32, i32, vp, vp, O, I, vp]
     lib.helm_solve_batched.argtypes = [vp, i32, C.POINTER(helm_problem), i32, O, I, vp]
-    lib.misfit_gradient.argtypes = [vp, G, vp, dbl, i32, C.POINTER(C.c_int32),
-                                    C.POINTER(C.c_double), i32,
-                                    C.POINTER(C.c_int32), vp,
+    lib.misfit_gradient.argtypes = [vp, G, vp, i32, C.POINTER(C.c_double), i32,
+                                    C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                    C.POINTER(C.c_uint8), i32, C.POINTER(C.c_int32), vp,
                                     C.POINTER(C.c_double), vp, vp, i32, O, I, vp]
     for name in ("helm_create", "helm_destroy", "helm_apply", "helm_solve",
                  "helm_solve_batched", "misfit_gradient"):

@@ -219,54 +219,72 @@ def helm_solve_batched(problems, adjoint: bool = False, opts: Optional[SolverOpt
     return outs, [SolveInfo(i.status, i.cycles, i.inner_its, i.matvecs, i.relres_fp64) for i in infos]
 
 
-def _idx_array(pos, name, grid):
-    a = np.ascontiguousarray(np.asarray(pos, dtype=np.int32).reshape(-1, 3))
-    return a
+def _idx_array(pos):
+    return np.ascontiguousarray(np.asarray(pos, dtype=np.int32).reshape(-1, 3))
 
 
-def misfit_gradient(grid: Grid, m: torch.Tensor, omega: float, src, rec, d: torch.Tensor,
-                    src_amp=None, grad: Optional[torch.Tensor] = None,
+def misfit_gradient(grid: Grid, m: torch.Tensor, omega, src, rec, d: torch.Tensor,
+                    src_amp=None, mask=None, grad: Optional[torch.Tensor] = None,
                     u_store: Optional[torch.Tensor] = None, forward_only: bool = False,
                     reuse_u: bool = False, accumulate: bool = False, u_fp64: bool = False,
-                    opts: Optional[SolverOpts] = None, raise_on_failure: bool = True):
-    """Misfit f = 1/2 sum_s ||P_r u_s - d_s||^2 and its gradient w.r.t. m.
+                    renormalise: bool = False, opts: Optional[SolverOpts] = None,
+                    raise_on_failure: bool = True):
+    """Misfit f = 1/2 sum ||P_r u - d||^2 over the selected (frequency,
+    source) pairs and its gradient w.r.t. m.
 
-    src, rec: (nsrc, 3) / (nrec, 3) integer node indices (host);
-    d: (nsrc, nrec) complex device tensor.  u_store (optional) receives or,
-    with reuse_u, supplies the forward fields; with u_fp64 it is complex128
-    (the FP64 outer iterates).  Returns (f, grad, infos)."""
+    omega: one angular frequency or a sequence of nfreq; src, rec: (nsrc, 3)
+    / (nrec, 3) integer node indices (host); d: complex device tensor of
+    nfreq * nsrc * nrec values ([frequency][source][receiver]); src_amp:
+    complex amplitudes broadcastable to (nfreq, nsrc); mask: booleans
+    (nfreq, nsrc) selecting the pairs (default all).  u_store (optional,
+    [nfreq][nsrc][N]) receives or, with reuse_u, supplies the forward fields;
+    with u_fp64 it is complex128 (the FP64 outer iterates).  renormalise
+    divides f and g by the number of selected pairs.  Returns (f, grad,
+    infos): infos per pair, forward solves then adjoint solves (only those
+    that ran), [frequency][source] order, zero entries for unselected pairs."""
+    if (u_fp64 or reuse_u) and u_store is None:
+        raise ValueError("u_fp64 and reuse_u need u_store")
     dev = m.device.index or 0
-    src_a = _idx_array(src, "src", grid)
-    rec_a = _idx_array(rec, "rec", grid)
+    om = np.ascontiguousarray(np.atleast_1d(np.asarray(omega, dtype=np.float64)).ravel())
+    nfreq = len(om)
+    src_a = _idx_array(src)
+    rec_a = _idx_array(rec)
     nsrc, nrec = len(src_a), len(rec_a)
     amp_p = None
     if src_amp is not None:
-        amp = np.ascontiguousarray(np.asarray(src_amp, np.complex128).reshape(nsrc))
-        amp_d = np.ascontiguousarray(np.stack([amp.real, amp.imag], axis=1).ravel())
+        amp = np.broadcast_to(np.asarray(src_amp, np.complex128), (nfreq, nsrc))
+        amp_d = np.ascontiguousarray(np.stack([amp.real, amp.imag], axis=-1).ravel())
         amp_p = amp_d.ctypes.data_as(C.POINTER(C.c_double))
+    mask_p = None
+    if mask is not None:
+        mask_a = np.ascontiguousarray(
+            np.broadcast_to(np.asarray(mask, bool), (nfreq, nsrc)).astype(np.uint8))
+        mask_p = mask_a.ctypes.data_as(C.POINTER(C.c_uint8))
     flags = (L.HELM_MG_FORWARD_ONLY if forward_only else 0) | \
         (L.HELM_MG_REUSE_U if reuse_u else 0) | (L.HELM_MG_ACCUMULATE if accumulate else 0) | \
-        (L.HELM_MG_U_FP64 if u_fp64 else 0)
+        (L.HELM_MG_U_FP64 if u_fp64 else 0) | (L.HELM_MG_RENORMALISE if renormalise else 0)
     u_dtype = torch.complex128 if u_fp64 else grid.complex_dtype
     if grad is None and not forward_only:
         grad = torch.empty(tuple(grid.n), dtype=grid.real_dtype, device=m.device)
     opts = opts or SolverOpts()
-    infos = (L.helm_solve_info * (2 * nsrc))()
+    npair = nfreq * nsrc
+    infos = (L.helm_solve_info * (2 * npair))()
     f = C.c_double(0.0)
     ctx = _context(dev)
     g, o = grid.c_struct(), opts.c_struct()
     st = L.load().misfit_gradient(
-        ctx, C.byref(g), _dev_tensor(m, grid.real_dtype, grid.N, "m"), float(omega), nsrc,
-        src_a.ctypes.data_as(C.POINTER(C.c_int32)), amp_p, nrec,
+        ctx, C.byref(g), _dev_tensor(m, grid.real_dtype, grid.N, "m"), nfreq,
+        om.ctypes.data_as(C.POINTER(C.c_double)), nsrc,
+        src_a.ctypes.data_as(C.POINTER(C.c_int32)), amp_p, mask_p, nrec,
         rec_a.ctypes.data_as(C.POINTER(C.c_int32)),
-        _dev_tensor(d, grid.complex_dtype, nsrc * nrec, "d"), C.byref(f),
+        _dev_tensor(d, grid.complex_dtype, npair * nrec, "d"), C.byref(f),
         None if grad is None else _dev_tensor(grad, grid.real_dtype, grid.N, "grad"),
-        None if u_store is None else _dev_tensor(u_store, u_dtype, nsrc * grid.N, "u_store"),
+        None if u_store is None else _dev_tensor(u_store, u_dtype, npair * grid.N, "u_store"),
         flags, C.byref(o), infos, _stream(dev))
     allow = (L.HELM_OK,) if raise_on_failure else (L.HELM_OK, L.HELM_NOT_CONVERGED, L.HELM_BREAKDOWN)
     _check(ctx, st, allow)
-    nsolve = nsrc if (forward_only or reuse_u) else 2 * nsrc
-    first = nsrc if reuse_u else 0
+    nsolve = npair if (forward_only or reuse_u) else 2 * npair
+    first = npair if reuse_u else 0
     inf = [SolveInfo(i.status, i.cycles, i.inner_its, i.matvecs, i.relres_fp64)
            for i in list(infos)[first:first + nsolve]]
     return f.value, grad, inf

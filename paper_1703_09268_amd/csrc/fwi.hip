@@ -1,19 +1,23 @@
 // Adjoint-state misfit / gradient kernels (arXiv:1703.09268, Listing of
 // PDEfunc case OBJ; Table derivstuff rows u, V, grad f; Appendix A eq.
-// dHadj):
-//   q_s = amp_s e_{src_s} / h^3                   (on-node point source)
-//   r_s = P_r u_s - d_s,  f = 1/2 sum_s ||r_s||^2  (FP64 accumulation)
-//   b_s = -P_r^T r_s                               (adjoint source)
-//   g   = sum_s Re(omega^2 conj(u_s) (A^H v_s))    (gradient w.r.t. real m)
-// Receivers that share a node are summed in a fixed order (node-sorted
-// receiver lists), so the adjoint source is deterministic.
+// dHadj), over a list of (frequency, source) pairs solved together:
+//   q_p = amp_p e_{src_p} / h^3                   (on-node point source)
+//   r_p = P_r u_p - d_p,  f = 1/2 sum_p ||r_p||^2  (FP64 accumulation)
+//   b_p = -P_r^T r_p                               (adjoint source)
+//   g   = sum_p Re(w_p conj(u_p) (A^H v_p))        (gradient w.r.t. real m,
+//                                                   w_p = omega_p^2 [/ #pairs])
+// Pair p's forward field starts at element uoff[p] of its array (the fields
+// may live in a caller's [frequency][source] store); right-hand sides,
+// adjoint fields and receiver residuals are contiguous per pair.  Receivers
+// that share a node are summed in a fixed order (node-sorted receiver
+// lists), so the adjoint source is deterministic.
 #pragma once
 
 #include "common.h"
 
 namespace helm {
 
-// q[s][p] = 0 except q[s][src_s] = amp_s / h^3
+// q[s][p] = 0 except q[s][src_s] = amp_s / h^3  (s: pair)
 template <typename T>
 __global__ __launch_bounds__(256) void k_point_sources(cx<T>* __restrict__ q, int64_t N,
                                                        const int64_t* __restrict__ src_lin,
@@ -27,22 +31,25 @@ __global__ __launch_bounds__(256) void k_point_sources(cx<T>* __restrict__ q, in
   }
 }
 
-// r[s][k] = u[s][rec_k] - d[s][k]; per-workgroup partial sum of |r|^2 in
-// part[s * gridDim.x + blk] (FP64).  u may be the FP64 outer iterate of the
-// solve (TU = double): the residual is a small difference of two fields, so
-// it is formed before the fields are rounded to the storage precision.
+// r[s][k] = u[uoff_s + rec_k] - d[drow_s][k] (s: pair); per-workgroup
+// partial sum of |r|^2 in part[s * gridDim.x + blk] (FP64).  u may be the
+// FP64 outer iterate of the solve (TU = double): the residual is a small
+// difference of two fields, so it is formed before the fields are rounded to
+// the storage precision.
 template <typename TU, typename T>
-__global__ __launch_bounds__(256) void k_sample_residual(const cx<TU>* __restrict__ u, int64_t N,
+__global__ __launch_bounds__(256) void k_sample_residual(const cx<TU>* __restrict__ u,
+                                                         const int64_t* __restrict__ uoff,
                                                          const int64_t* __restrict__ rec_lin, int nrec,
-                                                         const cx<T>* __restrict__ d, cx<T>* __restrict__ res,
-                                                         double* __restrict__ part) {
+                                                         const cx<T>* __restrict__ d,
+                                                         const int64_t* __restrict__ drow,
+                                                         cx<T>* __restrict__ res, double* __restrict__ part) {
   __shared__ double red[16];
   const int s = blockIdx.y;
   const int k = blockIdx.x * 256 + threadIdx.x;
   double acc = 0.0;
   if (k < nrec) {
-    const cx<TU> uv = u[s * N + rec_lin[k]];
-    const cx<T> dv = d[(int64_t)s * nrec + k];
+    const cx<TU> uv = u[uoff[s] + rec_lin[k]];
+    const cx<T> dv = d[drow[s] * nrec + k];
     const cx<double> rr = mk<double>((double)uv.re - (double)dv.re, (double)uv.im - (double)dv.im);
     res[(int64_t)s * nrec + k] = cast<T>(rr);
     acc = rr.re * rr.re + rr.im * rr.im;
@@ -69,13 +76,14 @@ __global__ __launch_bounds__(256) void k_adjoint_source(cx<T>* __restrict__ b, i
   b[s * N + node_lin[q]] = cast<T>(mk<double>(-acc.re, -acc.im));
 }
 
-// g[p] (+)= sum_s Re(omega^2 conj(u_s[p]) (A v_s)[p]) with A = I (7-point)
-// or the 27-point mass distribution (real symmetric, A^H = A).
+// g[p] (+)= sum_s Re(w_s conj(u_s[p]) (A v_s)[p]) over the pairs s, with
+// A = I (7-point) or the 27-point mass distribution (real symmetric,
+// A^H = A); u_s starts at u + uoff[s], v_s at v + s N.
 template <typename TU, typename T, typename TG, bool MASS27>
-__global__ __launch_bounds__(256) void k_gradient(const cx<TU>* __restrict__ u, const cx<T>* __restrict__ v,
-                                                  int nsrc, int nx, int ny, int nz, double w2,
-                                                  double mw0, double mw1, double mw2, double mw3,
-                                                  TG* __restrict__ g, bool accumulate) {
+__global__ __launch_bounds__(256) void k_gradient(const cx<TU>* __restrict__ u, const int64_t* __restrict__ uoff,
+                                                  const cx<T>* __restrict__ v, int npair, int nx, int ny, int nz,
+                                                  const double* __restrict__ w, double mw0, double mw1, double mw2,
+                                                  double mw3, TG* __restrict__ g, bool accumulate) {
   const int64_t N = (int64_t)nx * ny * nz;
   const int64_t stride = (int64_t)gridDim.x * 256;
   for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < N; p += stride) {
@@ -86,8 +94,8 @@ __global__ __launch_bounds__(256) void k_gradient(const cx<TU>* __restrict__ u, 
       j = (int)((p / nz) % ny);
       i = (int)(p / ((int64_t)ny * nz));
     }
-    for (int s = 0; s < nsrc; ++s) {
-      const cx<TU> us = u[s * N + p];
+    for (int s = 0; s < npair; ++s) {
+      const cx<TU> us = u[uoff[s] + p];
       cx<double> av;
       if (!MASS27) {
         av = cast<double>(v[s * N + p]);
@@ -107,11 +115,10 @@ __global__ __launch_bounds__(256) void k_gradient(const cx<TU>* __restrict__ u, 
           }
         }
       }
-      // Re(conj(u) * av)
-      acc += (double)us.re * av.re + (double)us.im * av.im;
+      // w Re(conj(u) * av)
+      acc += w[s] * ((double)us.re * av.re + (double)us.im * av.im);
     }
-    const double val = w2 * acc;
-    g[p] = accumulate ? (TG)((double)g[p] + val) : (TG)val;
+    g[p] = accumulate ? (TG)((double)g[p] + acc) : (TG)acc;
   }
 }
 

@@ -302,24 +302,54 @@ helm_status solve_batched_t(helm_ctx* ctx, int nprob, const helm_problem* probs,
   return (helm_status)worst;
 }
 
-// misfit + gradient for one frequency, element type T
+// misfit + gradient over the selected (frequency, source) pairs, element type T
 template <typename T>
-helm_status misfit_gradient_t(helm_ctx* ctx, const helm_grid* g, const void* m, double omega, int nsrc,
-                              const int32_t* src_idx, const double* src_amp, int nrec, const int32_t* rec_idx,
-                              const void* d, double* f, void* grad, void* u_store, int flags,
-                              const helm::SolveOpts& o, helm_solve_info* info, void* caller) {
+helm_status misfit_gradient_t(helm_ctx* ctx, const helm_grid* g, const void* m, int nfreq, const double* omega,
+                              int nsrc, const int32_t* src_idx, const double* src_amp, const uint8_t* mask,
+                              int nrec, const int32_t* rec_idx, const void* d, double* f, void* grad,
+                              void* u_store, int flags, const helm::SolveOpts& o, helm_solve_info* info,
+                              void* caller) {
   using namespace helm;
   hipStream_t st = solve_stream(ctx, caller);
   const int64_t N = (int64_t)g->n[0] * g->n[1] * g->n[2];
   const int64_t plane = (int64_t)g->n[1] * g->n[2];
   auto lin = [&](const int32_t* p) { return (int64_t)p[0] * plane + (int64_t)p[1] * g->n[2] + p[2]; };
-  // host index tables
-  std::vector<int64_t> src_lin(nsrc), rec_lin(nrec);
-  std::vector<double2> amp(nsrc);
-  for (int s = 0; s < nsrc; ++s) {
-    src_lin[s] = lin(src_idx + 3 * s);
-    amp[s] = src_amp ? make_double2(src_amp[2 * s], src_amp[2 * s + 1]) : make_double2(1.0, 0.0);
+  const bool fwd_only = (flags & HELM_MG_FORWARD_ONLY) != 0;
+  const bool reuse = (flags & HELM_MG_REUSE_U) != 0;
+  const bool acc = (flags & HELM_MG_ACCUMULATE) != 0;
+  const bool u64 = (flags & HELM_MG_U_FP64) != 0 && sizeof(T) == 4;
+  const int nall = nfreq * nsrc;
+  if (info)
+    for (int k = 0; k < 2 * nall; ++k) to_info(SolveInfo(), info + k);
+  // the selected pairs, frequency-major; row = f * nsrc + s
+  std::vector<int> prow;
+  for (int k = 0; k < nall; ++k)
+    if (!mask || mask[k]) prow.push_back(k);
+  const int np = (int)prow.size();
+  if (np == 0) {
+    *f = 0.0;
+    if (!fwd_only && !acc) HELM_HIP_CHECK(hipMemsetAsync(grad, 0, (size_t)N * sizeof(T), st));
+    HELM_HIP_CHECK(hipStreamSynchronize(st));
+    return HELM_OK;
   }
+  const double scale = (flags & HELM_MG_RENORMALISE) ? 1.0 / np : 1.0;
+  // host tables per pair
+  std::vector<int64_t> src_lin(np), drow(np), uoff_int(np), uoff_store(np);
+  std::vector<double2> amp(np);
+  std::vector<double> wgt(np);
+  std::vector<ProblemSpec> probs;
+  for (int p = 0; p < np; ++p) {
+    const int fi = prow[p] / nsrc, s = prow[p] % nsrc;
+    src_lin[p] = lin(src_idx + 3 * s);
+    const double* a = src_amp ? src_amp + 2 * (size_t)prow[p] : nullptr;
+    amp[p] = a ? make_double2(a[0], a[1]) : make_double2(1.0, 0.0);
+    drow[p] = prow[p];
+    uoff_int[p] = (int64_t)p * N;
+    uoff_store[p] = (int64_t)prow[p] * N;
+    wgt[p] = omega[fi] * omega[fi] * scale;
+    probs.push_back(shared_problems(g, m, omega[fi], 0, 1)[0]);
+  }
+  std::vector<int64_t> rec_lin(nrec);
   for (int k = 0; k < nrec; ++k) rec_lin[k] = lin(rec_idx + 3 * k);
   // distinct receiver nodes, ascending, each with its receivers in order
   std::vector<int> order(nrec);
@@ -337,21 +367,22 @@ helm_status misfit_gradient_t(helm_ctx* ctx, const helm_grid* g, const void* m, 
   }
   node_ptr.push_back(nrec);
   const int nnode = (int)node_lin.size();
-  // device scratch: Q (sources, then adjoint sources), V, and U when the
-  // forward fields are not written to the caller's u_store in the dtype
-  const bool u64 = (flags & HELM_MG_U_FP64) != 0 && sizeof(T) == 4;
-  const size_t fbytes = (size_t)nsrc * N * sizeof(cx<T>);
-  const bool own_u = (u_store == nullptr) || u64;
+  // Device scratch: Q (sources, then adjoint sources), V, and U unless the
+  // solve writes the caller's u_store directly (every pair selected, fields
+  // stored in the dtype).
+  const size_t fbytes = (size_t)np * N * sizeof(cx<T>);
+  const bool direct_u = u_store && !u64 && np == nall;
+  const bool own_u = !reuse && !direct_u;
   ctx->fwi_buf.ensure(fbytes * (own_u ? 3 : 2));
   char* base = (char*)ctx->fwi_buf.p;
-  cx<T>* U = own_u ? (cx<T>*)(base + 2 * fbytes) : (cx<T>*)u_store;
   cx<T>* Q = (cx<T>*)base;
   cx<T>* V = (cx<T>*)(base + fbytes);
+  cx<T>* U = direct_u ? (cx<T>*)u_store : own_u ? (cx<T>*)(base + 2 * fbytes) : nullptr;
   const int rblk = (int)ceil_div(nrec, 256);
   auto r256 = [](size_t b) { return (b + 255) / 256 * 256; };
-  const size_t small = r256(nsrc * sizeof(int64_t)) + r256(nrec * sizeof(int64_t)) +
-                       r256(nsrc * sizeof(double2)) + r256((size_t)nsrc * nrec * sizeof(cx<T>)) +
-                       r256((size_t)nsrc * rblk * sizeof(double)) + r256(nnode * sizeof(int64_t)) +
+  const size_t small = 4 * r256(np * sizeof(int64_t)) + r256(np * sizeof(double2)) + r256(np * sizeof(double)) +
+                       r256(nrec * sizeof(int64_t)) + r256((size_t)np * nrec * sizeof(cx<T>)) +
+                       r256((size_t)np * rblk * sizeof(double)) + r256(nnode * sizeof(int64_t)) +
                        r256((nnode + 1) * sizeof(int)) + r256(nrec * sizeof(int));
   ctx->fwi_small.ensure(small);
   char* sp = (char*)ctx->fwi_small.p;
@@ -362,77 +393,111 @@ helm_status misfit_gradient_t(helm_ctx* ctx, const helm_grid* g, const void* m, 
     if (sp > sp_end) throw Error{-3, "internal: misfit scratch layout overflow"};
     return (void*)p;
   };
-  int64_t* d_src = (int64_t*)carve(nsrc * sizeof(int64_t));
+  int64_t* d_src = (int64_t*)carve(np * sizeof(int64_t));
+  int64_t* d_drow = (int64_t*)carve(np * sizeof(int64_t));
+  int64_t* d_uoff_int = (int64_t*)carve(np * sizeof(int64_t));
+  int64_t* d_uoff_store = (int64_t*)carve(np * sizeof(int64_t));
+  double2* d_amp = (double2*)carve(np * sizeof(double2));
+  double* d_w = (double*)carve(np * sizeof(double));
   int64_t* d_rec = (int64_t*)carve(nrec * sizeof(int64_t));
-  double2* d_amp = (double2*)carve(nsrc * sizeof(double2));
-  cx<T>* d_res = (cx<T>*)carve((size_t)nsrc * nrec * sizeof(cx<T>));
-  double* d_part = (double*)carve((size_t)nsrc * rblk * sizeof(double));
+  cx<T>* d_res = (cx<T>*)carve((size_t)np * nrec * sizeof(cx<T>));
+  double* d_part = (double*)carve((size_t)np * rblk * sizeof(double));
   int64_t* d_node = (int64_t*)carve(nnode * sizeof(int64_t));
   int* d_nptr = (int*)carve((nnode + 1) * sizeof(int));
   int* d_nrec = (int*)carve(nrec * sizeof(int));
-  HELM_HIP_CHECK(hipMemcpyAsync(d_src, src_lin.data(), nsrc * sizeof(int64_t), hipMemcpyHostToDevice, st));
-  HELM_HIP_CHECK(hipMemcpyAsync(d_rec, rec_lin.data(), nrec * sizeof(int64_t), hipMemcpyHostToDevice, st));
-  HELM_HIP_CHECK(hipMemcpyAsync(d_amp, amp.data(), nsrc * sizeof(double2), hipMemcpyHostToDevice, st));
-  HELM_HIP_CHECK(hipMemcpyAsync(d_node, node_lin.data(), nnode * sizeof(int64_t), hipMemcpyHostToDevice, st));
-  HELM_HIP_CHECK(hipMemcpyAsync(d_nptr, node_ptr.data(), (nnode + 1) * sizeof(int), hipMemcpyHostToDevice, st));
-  HELM_HIP_CHECK(hipMemcpyAsync(d_nrec, node_rec.data(), nrec * sizeof(int), hipMemcpyHostToDevice, st));
+  auto up = [&](void* dst, const void* src, size_t b) {
+    HELM_HIP_CHECK(hipMemcpyAsync(dst, src, b, hipMemcpyHostToDevice, st));
+  };
+  up(d_src, src_lin.data(), np * sizeof(int64_t));
+  up(d_drow, drow.data(), np * sizeof(int64_t));
+  up(d_uoff_int, uoff_int.data(), np * sizeof(int64_t));
+  up(d_uoff_store, uoff_store.data(), np * sizeof(int64_t));
+  up(d_amp, amp.data(), np * sizeof(double2));
+  up(d_w, wgt.data(), np * sizeof(double));
+  up(d_rec, rec_lin.data(), nrec * sizeof(int64_t));
+  up(d_node, node_lin.data(), nnode * sizeof(int64_t));
+  up(d_nptr, node_ptr.data(), (nnode + 1) * sizeof(int));
+  up(d_nrec, node_rec.data(), nrec * sizeof(int));
 
-  Solver<T>& S = solver_for<T>(ctx, shared_problems(g, m, omega, 0, nsrc), o, st);
-  std::vector<SolveInfo> inf(nsrc);
+  Solver<T>& S = solver_for<T>(ctx, probs, o, st);
+  std::vector<SolveInfo> inf(np);
   int worst = 0;
-  const unsigned fb = std::min<unsigned>(65536, ceil_div((int64_t)nsrc * N, 256));
-  const bool reuse = (flags & HELM_MG_REUSE_U) != 0;
+  const unsigned fb = std::min<unsigned>(65536, ceil_div((int64_t)np * N, 256));
+  // where the gradient reads the forward fields: (pointer, per-pair offsets, FP64?)
+  const void* ug = U;
+  const int64_t* ug_off = d_uoff_int;
+  bool ug64 = false;
   if (!reuse) {
     const double inv_h3 = 1.0 / (g->h * g->h * g->h);
-    hipLaunchKernelGGL((k_point_sources<T>), dim3(std::min<unsigned>(DOT_BLOCKS, ceil_div(N, 256)), nsrc),
-                       dim3(256), 0, st, Q, N, (const int64_t*)d_src, (const double2*)d_amp, inv_h3);
+    hipLaunchKernelGGL((k_point_sources<T>), dim3(std::min<unsigned>(DOT_BLOCKS, ceil_div(N, 256)), np), dim3(256),
+                       0, st, Q, N, (const int64_t*)d_src, (const double2*)d_amp, inv_h3);
     worst = std::max(worst, S.solve(0, Q, U, inf.data()));
     if (info)
-      for (int s = 0; s < nsrc; ++s) to_info(inf[s], info + s);
-    if (u64)  // keep the FP64 iterates as the stored fields
-      hipLaunchKernelGGL((k_convert<double, double>), dim3(fb), dim3(256), 0, st, S.iterate(),
-                         (cx<double>*)u_store, N * nsrc);
-    hipLaunchKernelGGL((k_sample_residual<double, T>), dim3(rblk, nsrc), dim3(256), 0, st, S.iterate(), N,
-                       (const int64_t*)d_rec, nrec, (const cx<T>*)d, d_res, d_part);
-  } else if (u64) {
-    hipLaunchKernelGGL((k_sample_residual<double, T>), dim3(rblk, nsrc), dim3(256), 0, st,
-                       (const cx<double>*)u_store, N, (const int64_t*)d_rec, nrec, (const cx<T>*)d, d_res,
-                       d_part);
+      for (int p = 0; p < np; ++p) to_info(inf[p], info + prow[p]);
+    if (u64) {  // keep the FP64 iterates as the stored fields
+      if (np == nall) {
+        hipLaunchKernelGGL((k_convert<double, double>), dim3(fb), dim3(256), 0, st, S.iterate(),
+                           (cx<double>*)u_store, N * np);
+      } else {
+        const unsigned pb = std::min<unsigned>(65536, ceil_div(N, 256));
+        for (int p = 0; p < np; ++p)
+          hipLaunchKernelGGL((k_convert<double, double>), dim3(pb), dim3(256), 0, st, S.iterate() + p * N,
+                             (cx<double>*)u_store + prow[p] * N, N);
+      }
+      ug = u_store;
+      ug_off = d_uoff_store;
+      ug64 = true;
+    } else if (u_store && !direct_u) {
+      for (int p = 0; p < np; ++p)
+        HELM_HIP_CHECK(hipMemcpyAsync((cx<T>*)u_store + prow[p] * N, U + p * N, N * sizeof(cx<T>),
+                                      hipMemcpyDeviceToDevice, st));
+    }
+    hipLaunchKernelGGL((k_sample_residual<double, T>), dim3(rblk, np), dim3(256), 0, st, S.iterate(),
+                       (const int64_t*)d_uoff_int, (const int64_t*)d_rec, nrec, (const cx<T>*)d,
+                       (const int64_t*)d_drow, d_res, d_part);
   } else {
-    hipLaunchKernelGGL((k_sample_residual<T, T>), dim3(rblk, nsrc), dim3(256), 0, st, (const cx<T>*)U, N,
-                       (const int64_t*)d_rec, nrec, (const cx<T>*)d, d_res, d_part);
+    ug = u_store;
+    ug_off = d_uoff_store;
+    ug64 = u64;
+    if (u64)
+      hipLaunchKernelGGL((k_sample_residual<double, T>), dim3(rblk, np), dim3(256), 0, st,
+                         (const cx<double>*)u_store, (const int64_t*)d_uoff_store, (const int64_t*)d_rec, nrec,
+                         (const cx<T>*)d, (const int64_t*)d_drow, d_res, d_part);
+    else
+      hipLaunchKernelGGL((k_sample_residual<T, T>), dim3(rblk, np), dim3(256), 0, st, (const cx<T>*)u_store,
+                         (const int64_t*)d_uoff_store, (const int64_t*)d_rec, nrec, (const cx<T>*)d,
+                         (const int64_t*)d_drow, d_res, d_part);
   }
-  std::vector<double> hpart((size_t)nsrc * rblk);
+  std::vector<double> hpart((size_t)np * rblk);
   HELM_HIP_CHECK(hipMemcpyAsync(hpart.data(), d_part, hpart.size() * sizeof(double), hipMemcpyDeviceToHost, st));
   HELM_HIP_CHECK(hipStreamSynchronize(st));
   double fsum = 0.0;
   for (size_t i = 0; i < hpart.size(); ++i) fsum += hpart[i];
-  *f = 0.5 * fsum;
-  if (flags & HELM_MG_FORWARD_ONLY) return (helm_status)worst;
-  // adjoint sources b_s = -P_r^T r_s, then H^H v_s = b_s
-  hipLaunchKernelGGL((k_fill_zero<T>), dim3(fb), dim3(256), 0, st, Q, (int64_t)nsrc * N);
-  hipLaunchKernelGGL((k_adjoint_source<T>), dim3(ceil_div(nnode, 256), nsrc), dim3(256), 0, st, Q, N,
+  *f = 0.5 * fsum * scale;
+  if (fwd_only) return (helm_status)worst;
+  // adjoint sources b_p = -P_r^T r_p, then H^H v_p = b_p
+  hipLaunchKernelGGL((k_fill_zero<T>), dim3(fb), dim3(256), 0, st, Q, (int64_t)np * N);
+  hipLaunchKernelGGL((k_adjoint_source<T>), dim3(ceil_div(nnode, 256), np), dim3(256), 0, st, Q, N,
                      (const int64_t*)d_node, (const int*)d_nptr, (const int*)d_nrec, nnode, (const cx<T>*)d_res,
                      nrec);
   worst = std::max(worst, S.solve(1, Q, V, inf.data()));
   if (info)
-    for (int s = 0; s < nsrc; ++s) to_info(inf[s], info + nsrc + s);
+    for (int p = 0; p < np; ++p) to_info(inf[p], info + nall + prow[p]);
   // gradient
-  const bool acc = (flags & HELM_MG_ACCUMULATE) != 0;
-  const double w2 = omega * omega;
   const unsigned gb = std::min<unsigned>(4096, ceil_div(N, 256));
-  const double mw[4] = {g->stencil == HELM_27PT ? g->w27[3] : 1.0, g->stencil == HELM_27PT ? g->w27[4] : 0.0,
-                        g->stencil == HELM_27PT ? g->w27[5] : 0.0, g->stencil == HELM_27PT ? g->w27[6] : 0.0};
-#define HELM_GRAD(TU, UPTR, M27)                                                                        \
-  hipLaunchKernelGGL((k_gradient<TU, T, T, M27>), dim3(gb), dim3(256), 0, st, (const cx<TU>*)(UPTR),     \
-                     (const cx<T>*)V, nsrc, g->n[0], g->n[1], g->n[2], w2, mw[0], mw[1], mw[2], mw[3],  \
-                     (T*)grad, acc)
-  if (u64) {
-    if (g->stencil == HELM_27PT) HELM_GRAD(double, u_store, true);
-    else HELM_GRAD(double, u_store, false);
+  const bool m27 = g->stencil == HELM_27PT;
+  const double mw[4] = {m27 ? g->w27[3] : 1.0, m27 ? g->w27[4] : 0.0, m27 ? g->w27[5] : 0.0,
+                        m27 ? g->w27[6] : 0.0};
+#define HELM_GRAD(TU, M27)                                                                                \
+  hipLaunchKernelGGL((k_gradient<TU, T, T, M27>), dim3(gb), dim3(256), 0, st, (const cx<TU>*)ug, ug_off,  \
+                     (const cx<T>*)V, np, g->n[0], g->n[1], g->n[2], (const double*)d_w, mw[0], mw[1], mw[2], \
+                     mw[3], (T*)grad, acc)
+  if (ug64) {
+    if (m27) HELM_GRAD(double, true);
+    else HELM_GRAD(double, false);
   } else {
-    if (g->stencil == HELM_27PT) HELM_GRAD(T, U, true);
-    else HELM_GRAD(T, U, false);
+    if (m27) HELM_GRAD(T, true);
+    else HELM_GRAD(T, false);
   }
 #undef HELM_GRAD
   HELM_HIP_CHECK(hipGetLastError());
@@ -579,19 +644,23 @@ helm_status helm_solve_batched(helm_ctx* ctx, int nprob, const helm_problem* pro
   });
 }
 
-helm_status misfit_gradient(helm_ctx* ctx, const helm_grid* g, const void* m, double omega, int nsrc,
-                            const int32_t* src_idx, const double* src_amp, int nrec, const int32_t* rec_idx,
-                            const void* d, double* f, void* grad, void* u_store, int flags,
+helm_status misfit_gradient(helm_ctx* ctx, const helm_grid* g, const void* m, int nfreq, const double* omega,
+                            int nsrc, const int32_t* src_idx, const double* src_amp, const uint8_t* mask, int nrec,
+                            const int32_t* rec_idx, const void* d, double* f, void* grad, void* u_store, int flags,
                             const helm_solver_opts* o, helm_solve_info* info, void* stream) {
   return guarded(ctx, [&]() -> helm_status {
     check_grid(g);
     HELM_REQUIRE(m && d && f, "null pointer argument");
-    HELM_REQUIRE(omega > 0.0 && std::isfinite(omega), "omega must be positive");
+    HELM_REQUIRE(nfreq >= 1 && omega, "nfreq must be >= 1 with an omega array");
+    for (int k = 0; k < nfreq; ++k)
+      HELM_REQUIRE(omega[k] > 0.0 && std::isfinite(omega[k]), "omega must be positive");
     HELM_REQUIRE(nsrc >= 1 && nrec >= 1, "nsrc and nrec must be >= 1");
+    HELM_REQUIRE((int64_t)nfreq * nsrc <= (1 << 20), "too many (frequency, source) pairs");
     HELM_REQUIRE(src_idx && rec_idx, "null source / receiver index array");
     HELM_REQUIRE((flags & HELM_MG_FORWARD_ONLY) || grad, "null gradient");
     HELM_REQUIRE(!(flags & HELM_MG_REUSE_U) || u_store, "HELM_MG_REUSE_U needs u_store");
-    HELM_REQUIRE((flags & ~15) == 0, "unknown flag bits");
+    HELM_REQUIRE(!(flags & HELM_MG_U_FP64) || u_store, "HELM_MG_U_FP64 needs u_store");
+    HELM_REQUIRE((flags & ~31) == 0, "unknown flag bits");
     for (int s = 0; s < nsrc; ++s)
       for (int a = 0; a < 3; ++a)
         HELM_REQUIRE(src_idx[3 * s + a] >= 0 && src_idx[3 * s + a] < g->n[a], "source outside the grid");
@@ -601,10 +670,10 @@ helm_status misfit_gradient(helm_ctx* ctx, const helm_grid* g, const void* m, do
     const helm::SolveOpts so = opts_of(o);
     check_coarse_sizes(g, so);
     if (g->dtype == HELM_C64)
-      return misfit_gradient_t<float>(ctx, g, m, omega, nsrc, src_idx, src_amp, nrec, rec_idx, d, f, grad,
-                                      u_store, flags, so, info, stream);
-    return misfit_gradient_t<double>(ctx, g, m, omega, nsrc, src_idx, src_amp, nrec, rec_idx, d, f, grad,
-                                     u_store, flags, so, info, stream);
+      return misfit_gradient_t<float>(ctx, g, m, nfreq, omega, nsrc, src_idx, src_amp, mask, nrec, rec_idx, d, f,
+                                      grad, u_store, flags, so, info, stream);
+    return misfit_gradient_t<double>(ctx, g, m, nfreq, omega, nsrc, src_idx, src_amp, mask, nrec, rec_idx, d, f,
+                                     grad, u_store, flags, so, info, stream);
   });
 }
 

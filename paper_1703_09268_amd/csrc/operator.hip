@@ -94,6 +94,42 @@ struct OpTables {
   Int27 in27;
 };
 
+// 27-point description of one operator on one level: the interior range per
+// axis (rows whose +-1 neighbours are damping-free) and the class weights of
+// the compact Laplacian and of the mass distribution (7-point: no interior
+// rows used, mass = identity).
+inline Int27 interior27_desc(const GridSpec& g, const int n[3], double h, int stride) {
+  Int27 in27;
+  for (int a = 0; a < 3; ++a) {
+    int lo = 1, hi = 0;
+    bool found = false;
+    for (int i = 0; i < n[a]; ++i) {
+      const bool ok = layer_sigma(g, a, (double)(i - 1) * stride) == 0.0 &&
+                      layer_sigma(g, a, (double)(i + 1) * stride) == 0.0;
+      if (ok && !found) { lo = i; found = true; }
+      if (ok) hi = i;
+    }
+    in27.lo[a] = lo;
+    in27.hi[a] = found ? hi : lo - 1;
+  }
+  const double w1 = g.w27[0], w2 = g.w27[1], w3 = g.w27[2];
+  const double h2 = h * h;
+  if (g.stencil == 1) {
+    // L1 = h^-2 sum of axis second differences; L2 = L1/3 + (6h^2)^-1 sum
+    // over face diagonals; L3 = (4h^2)^-1 sum over body diagonals
+    in27.lw[0] = (w1 * -6.0 + w2 * (-6.0 / 3.0 - 12.0 / 6.0) + w3 * (-8.0 / 4.0)) / h2;
+    in27.lw[1] = (w1 * 1.0 + w2 * (1.0 / 3.0)) / h2;
+    in27.lw[2] = (w2 * (1.0 / 6.0)) / h2;
+    in27.lw[3] = (w3 * (1.0 / 4.0)) / h2;
+    for (int c = 0; c < 4; ++c) in27.mw[c] = g.w27[3 + c];
+  } else {
+    for (int c = 0; c < 4; ++c) in27.lw[c] = 0.0;
+    in27.mw[0] = 1.0;
+    in27.mw[1] = in27.mw[2] = in27.mw[3] = 0.0;
+  }
+  return in27;
+}
+
 inline std::unique_ptr<OpTables> build_tables(const GridSpec& g, double omega, const int n[3], double h,
                                               int stride, hipStream_t st) {
   typedef std::complex<double> C;
@@ -143,36 +179,23 @@ inline std::unique_ptr<OpTables> build_tables(const GridSpec& g, double omega, c
   HELM_HIP_CHECK(hipMemcpyAsync(T->tabd.p, hd.data(), hd.size() * sizeof(cx<double>), hipMemcpyHostToDevice, st));
   HELM_HIP_CHECK(hipMemcpyAsync(T->tabf.p, hf.data(), hf.size() * sizeof(cx<float>), hipMemcpyHostToDevice, st));
   HELM_HIP_CHECK(hipStreamSynchronize(st));  // the host vectors go out of scope
-  // 27-point interior range per axis: rows whose +-1 neighbours are damping-free
-  for (int a = 0; a < 3; ++a) {
-    int lo = 1, hi = 0;
-    bool found = false;
-    for (int i = 0; i < n[a]; ++i) {
-      const bool ok = layer_sigma(g, a, (double)(i - 1) * stride) == 0.0 &&
-                      layer_sigma(g, a, (double)(i + 1) * stride) == 0.0;
-      if (ok && !found) { lo = i; found = true; }
-      if (ok) hi = i;
-    }
-    T->in27.lo[a] = lo;
-    T->in27.hi[a] = found ? hi : lo - 1;
-  }
-  const double w1 = g.w27[0], w2 = g.w27[1], w3 = g.w27[2];
-  const double h2 = h * h;
-  if (g.stencil == 1) {
-    // L1 = h^-2 sum of axis second differences; L2 = L1/3 + (6h^2)^-1 sum
-    // over face diagonals; L3 = (4h^2)^-1 sum over body diagonals
-    T->in27.lw[0] = (w1 * -6.0 + w2 * (-6.0 / 3.0 - 12.0 / 6.0) + w3 * (-8.0 / 4.0)) / h2;
-    T->in27.lw[1] = (w1 * 1.0 + w2 * (1.0 / 3.0)) / h2;
-    T->in27.lw[2] = (w2 * (1.0 / 6.0)) / h2;
-    T->in27.lw[3] = (w3 * (1.0 / 4.0)) / h2;
-    for (int c = 0; c < 4; ++c) T->in27.mw[c] = g.w27[3 + c];
-  } else {
-    for (int c = 0; c < 4; ++c) T->in27.lw[c] = 0.0;
-    T->in27.mw[0] = 1.0;
-    T->in27.mw[1] = T->in27.mw[2] = T->in27.mw[3] = 0.0;
-  }
+  T->in27 = interior27_desc(g, n, h, stride);
   return T;
 }
+
+// What a stencil launch needs of a level: device descriptors and maps, and
+// the launch shape.
+struct LevelView {
+  const Seg* segs;
+  const int* smap;
+  const int* slocal;
+  const int* tmap;
+  int nsblk, ntblk;
+  int stencil;  // 0 7-point, 1 27-point
+  int dir;      // 0 H, 1 H^H (one direction per level)
+  bool pair;
+  int stage27;
+};
 
 // All segments of one level with their workgroup maps.
 struct LevelSet {
@@ -187,6 +210,10 @@ struct LevelSet {
   int64_t total = 0;  // vector length (sum of N)
   std::vector<std::unique_ptr<DevBuf>> models;  // owned coarse models
   const Seg* d() const { return segs.as<const Seg>(); }
+  LevelView view() const {
+    return LevelView{d(), smap.as<const int>(), slocal.as<const int>(), tmap.as<const int>(), nsblk, ntblk,
+                     stencil, host.empty() ? 0 : host[0].dir, pair, stage27};
+  }
 };
 
 constexpr int kMinXchunk = 4;  // smallest x chunk of a stencil tile
@@ -196,41 +223,50 @@ constexpr int kMinXchunk = 4;  // smallest x chunk of a stencil tile
 // zero bytes each, for the widest z pitch of the level; 0 (register path)
 // when that exceeds 40 KiB (four workgroups per CU must still fit) or with
 // HELM_STAGE27=0.
-inline int stage27_bytes(const std::vector<Seg>& segs) {
+inline int stage27_bytes_pz(int pzm) {
   if (const char* e = std::getenv("HELM_STAGE27"))
     if (e[0] == '0') return 0;
-  int pzm = 0;
-  for (const Seg& S : segs) pzm = std::max(pzm, S.pz);
   const int64_t tl = 512 + 2 * (int64_t)pzm + 4;
   const int64_t buf = ((tl * 8 + (tl + 4) * 4 + 15) / 16) * 16 + 16;
   return 2 * buf <= 40 * 1024 ? (int)(2 * buf) : 0;
+}
+inline int stage27_bytes(const std::vector<Seg>& segs) {
+  int pzm = 0;
+  for (const Seg& S : segs) pzm = std::max(pzm, S.pz);
+  return stage27_bytes_pz(pzm);
 }
 
 // x-chunk (planes per stencil workgroup) for a level: about `target`
 // workgroups over the level (a few per wave slot of the chip), at least 4
 // planes per workgroup.  The HELM_XCHUNK / HELM_STENCIL_WG environment
 // variables override the chunk / the target (tile experiments).
-inline int choose_xchunk(const std::vector<Seg>& segs) {
+// plane_blocks: workgroups of one x plane summed over the segments; nxmax:
+// the longest x extent.
+inline int choose_xchunk_for(int64_t plane_blocks, int nxmax, bool pair) {
   if (const char* e = std::getenv("HELM_XCHUNK")) {
     const int v = std::atoi(e);
     if (v >= kMinXchunk) return v;
   }
   // measured on 128^3 and 65x65x66 with 16 right-hand sides: pair tiles
   // prefer longer marches (2048 workgroups), one-point tiles 8192
-  int64_t target = (!segs.empty() && segs[0].pair) ? 2048 : 8192;
+  int64_t target = pair ? 2048 : 8192;
   if (const char* e = std::getenv("HELM_STENCIL_WG")) {
     const int v = std::atoi(e);
     if (v >= 1) target = v;
   }
+  nxmax = std::max(nxmax, 1);
+  const int64_t nxc = std::max<int64_t>(1, (target + plane_blocks - 1) / std::max<int64_t>(plane_blocks, 1));
+  int xchunk = (int)((nxmax + nxc - 1) / nxc);
+  return std::max(kMinXchunk, std::min(xchunk, nxmax));
+}
+inline int choose_xchunk(const std::vector<Seg>& segs) {
   int64_t plane = 0;
   int nxmax = 1;
   for (const Seg& s : segs) {
     plane += s.plane_blocks;
     nxmax = std::max(nxmax, s.n[0]);
   }
-  const int64_t nxc = std::max<int64_t>(1, (target + plane - 1) / std::max<int64_t>(plane, 1));
-  int xchunk = (int)((nxmax + nxc - 1) / nxc);
-  return std::max(4, std::min(xchunk, nxmax));
+  return choose_xchunk_for(plane, nxmax, !segs.empty() && segs[0].pair);
 }
 
 // Largest number of vector-kernel workgroups per segment (grid-stride over
@@ -550,40 +586,44 @@ inline bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 // Returns the partial-sum range a NORM launch wrote (PR_STENCIL: stencil
 // tiles; PR_POINT: point-wise workgroups).
 template <typename TC, typename TX, typename TM, typename TB, typename TO, bool RESID, bool NORM>
-int launch_h(const LevelSet& L, const cx<TX>* x, const double* xs, const cx<TB>* b, const double* bs,
+int launch_h(const LevelView& L, const cx<TX>* x, const double* xs, const cx<TB>* b, const double* bs,
              cx<TO>* out, double* part, const int* active, hipStream_t st) {
   constexpr bool all_f32 = std::is_same<TC, float>::value && std::is_same<TX, float>::value &&
                            std::is_same<TM, float>::value && std::is_same<TB, float>::value &&
                            std::is_same<TO, float>::value;
   const bool pair_ok = all_f32 && L.pair && aligned16(x) && aligned16(out) && (!RESID || aligned16(b));
   if (L.stencil == 1 && pair_ok) {
-    const int adj = L.host[0].dir;  // one direction per level
-    if (adj)
-      hipLaunchKernelGGL((k_h27p<true, RESID, NORM>), dim3(L.nsblk), dim3(256), L.stage27, st, L.d(),
-                         L.smap.as<const int>(), L.slocal.as<const int>(), reinterpret_cast<const c32*>(x), xs,
-                         reinterpret_cast<const c32*>(b), bs, reinterpret_cast<c32*>(out), part, active, VecPtrs{},
-                         (const double*)nullptr, L.stage27 > 0 ? 1 : 0);
+    if (L.dir)
+      hipLaunchKernelGGL((k_h27p<true, RESID, NORM>), dim3(L.nsblk), dim3(256), L.stage27, st, L.segs, L.smap,
+                         L.slocal, reinterpret_cast<const c32*>(x), xs, reinterpret_cast<const c32*>(b), bs,
+                         reinterpret_cast<c32*>(out), part, active, VecPtrs{}, (const double*)nullptr,
+                         L.stage27 > 0 ? 1 : 0);
     else
-      hipLaunchKernelGGL((k_h27p<false, RESID, NORM>), dim3(L.nsblk), dim3(256), L.stage27, st, L.d(),
-                         L.smap.as<const int>(), L.slocal.as<const int>(), reinterpret_cast<const c32*>(x), xs,
-                         reinterpret_cast<const c32*>(b), bs, reinterpret_cast<c32*>(out), part, active, VecPtrs{},
-                         (const double*)nullptr, L.stage27 > 0 ? 1 : 0);
+      hipLaunchKernelGGL((k_h27p<false, RESID, NORM>), dim3(L.nsblk), dim3(256), L.stage27, st, L.segs, L.smap,
+                         L.slocal, reinterpret_cast<const c32*>(x), xs, reinterpret_cast<const c32*>(b), bs,
+                         reinterpret_cast<c32*>(out), part, active, VecPtrs{}, (const double*)nullptr,
+                         L.stage27 > 0 ? 1 : 0);
     return PR_STENCIL;
   } else if (L.stencil == 1) {
-    hipLaunchKernelGGL((k_h27<TC, TX, TM, TB, TO, RESID, NORM>), dim3(L.ntblk), dim3(256), 0, st, L.d(),
-                       L.tmap.as<const int>(), x, xs, b, bs, out, part, active);
+    hipLaunchKernelGGL((k_h27<TC, TX, TM, TB, TO, RESID, NORM>), dim3(L.ntblk), dim3(256), 0, st, L.segs, L.tmap, x,
+                       xs, b, bs, out, part, active);
     return PR_POINT;
   } else if (pair_ok) {
-    hipLaunchKernelGGL((k_h7p<RESID, NORM, 0, false>), dim3(L.nsblk), dim3(256), 0, st, L.d(),
-                       L.smap.as<const int>(), L.slocal.as<const int>(), reinterpret_cast<const c32*>(x), xs,
-                       reinterpret_cast<const c32*>(b), bs, reinterpret_cast<c32*>(out), part, active,
-                       VecPtrs{}, (const double*)nullptr);
+    hipLaunchKernelGGL((k_h7p<RESID, NORM, 0, false>), dim3(L.nsblk), dim3(256), 0, st, L.segs, L.smap, L.slocal,
+                       reinterpret_cast<const c32*>(x), xs, reinterpret_cast<const c32*>(b), bs,
+                       reinterpret_cast<c32*>(out), part, active, VecPtrs{}, (const double*)nullptr);
     return PR_STENCIL;
   } else {
-    hipLaunchKernelGGL((k_h7<TC, TX, TM, TB, TO, RESID, NORM>), dim3(L.nsblk), dim3(256), 0, st, L.d(),
-                       L.smap.as<const int>(), L.slocal.as<const int>(), x, xs, b, bs, out, part, active);
+    hipLaunchKernelGGL((k_h7<TC, TX, TM, TB, TO, RESID, NORM>), dim3(L.nsblk), dim3(256), 0, st, L.segs, L.smap,
+                       L.slocal, x, xs, b, bs, out, part, active);
   }
   return PR_STENCIL;
+}
+
+template <typename TC, typename TX, typename TM, typename TB, typename TO, bool RESID, bool NORM>
+int launch_h(const LevelSet& L, const cx<TX>* x, const double* xs, const cx<TB>* b, const double* bs,
+             cx<TO>* out, double* part, const int* active, hipStream_t st) {
+  return launch_h<TC, TX, TM, TB, TO, RESID, NORM>(L.view(), x, xs, b, bs, out, part, active, st);
 }
 
 // Tile tuner (7-point levels): time a stencil launch for a few x chunks and

@@ -179,10 +179,25 @@ def test_empty_inputs_are_rejected_through_the_abi():
         assert lib.helm_solve_batched(ctx, 0, None, 0, C.byref(o), None, None) == L.HELM_E_INVAL
         idx = (C.c_int32 * 3)(8, 8, 8)
         f = C.c_double(0.0)
-        st = lib.misfit_gradient(ctx, C.byref(g), mp, 1.0, 0, idx, None, 1, idx, xp, C.byref(f), None, None, 0,
-                                 C.byref(o), None, None)
+        om = (C.c_double * 1)(1.0)
+        st = lib.misfit_gradient(ctx, C.byref(g), mp, 1, om, 0, idx, None, None, 1, idx, xp, C.byref(f), None,
+                                 None, 0, C.byref(o), None, None)
         assert st == L.HELM_E_INVAL
         assert b"nsrc" in lib.helm_last_error(ctx)
+        st = lib.misfit_gradient(ctx, C.byref(g), mp, 0, om, 1, idx, None, None, 1, idx, xp, C.byref(f), None,
+                                 None, 0, C.byref(o), None, None)
+        assert st == L.HELM_E_INVAL and b"nfreq" in lib.helm_last_error(ctx)
+        # FP64 field storage without a store: rejected before any device work
+        st = lib.misfit_gradient(ctx, C.byref(g), mp, 1, om, 1, idx, None, None, 1, idx, xp, C.byref(f), xp,
+                                 None, L.HELM_MG_U_FP64, C.byref(o), None, None)
+        assert st == L.HELM_E_INVAL and b"u_store" in lib.helm_last_error(ctx)
+        st = lib.misfit_gradient(ctx, C.byref(g), mp, 1, om, 1, idx, None, None, 1, idx, xp, C.byref(f), xp,
+                                 None, L.HELM_MG_REUSE_U, C.byref(o), None, None)
+        assert st == L.HELM_E_INVAL and b"u_store" in lib.helm_last_error(ctx)
+        bad = (C.c_double * 1)(-1.0)
+        st = lib.misfit_gradient(ctx, C.byref(g), mp, 1, bad, 1, idx, None, None, 1, idx, xp, C.byref(f), xp,
+                                 None, 0, C.byref(o), None, None)
+        assert st == L.HELM_E_INVAL and b"omega" in lib.helm_last_error(ctx)
     finally:
         lib.helm_destroy(ctx)
 

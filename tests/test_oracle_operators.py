@@ -122,6 +122,65 @@ def test_layer_profile_shape():
         assert np.all(np.imag(ops.stretch(g, a, i[:6])) > 0)
 
 
+def _stretched_row_error(scale):
+    """RMS error of the oracle's 1D layer rows (axis_coeffs: stretches at the
+    node and at the half nodes i +- 1/2) against the continuous operator
+    (1/s) d/dx ((1/s) du/dx) = u''/s^2 - s' u'/s^3, with s(x) = 1 + i
+    sigma(x)/omega written here in physical coordinates: a layer of fixed
+    width Lp = npml h on both ends of [0, 1], sigma = sigma_max (depth/Lp)^2,
+    sigma_max = 3 v ln(1/R) / (2 Lp)."""
+    npml, nint = 8 * scale, 24 * scale
+    n = nint + 2 * npml
+    h = 1.0 / (n - 1)
+    omega, vref = 2 * np.pi * 3.0, 2.0
+    g = ops.make_grid((n, 3, 3), h, npml, omega, vref)
+    cp, cm = ops.axis_coeffs(g, 0)
+    x = np.arange(n) * h
+    Lp = npml * h
+    smax = 3 * vref * np.log(1.0 / g.R) / (2 * Lp)
+    depth = np.maximum(0.0, np.maximum(Lp - x, x - (1.0 - Lp)))
+    sig = smax * (depth / Lp) ** 2
+    dsig = np.where(x < Lp, -2 * smax * (Lp - x) / Lp ** 2,
+                    np.where(x > 1.0 - Lp, 2 * smax * (x - (1.0 - Lp)) / Lp ** 2, 0.0))
+    s, ds = 1 + 1j * sig / omega, 1j * dsig / omega
+    k = 2.3
+    u = np.exp(1j * k * x) * (1 + x)
+    du = np.exp(1j * k * x) * (1j * k * (1 + x) + 1)
+    d2u = np.exp(1j * k * x) * (-k * k * (1 + x) + 2j * k)
+    exact = d2u / s ** 2 - ds * du / s ** 3
+    Lu = cp[1:-1] * (u[2:] - u[1:-1]) - cm[1:-1] * (u[1:-1] - u[:-2])
+    return np.sqrt(np.mean(np.abs(Lu - exact[1:-1]) ** 2))
+
+
+def test_layer_rows_converge_to_the_stretched_operator():
+    """The grid's own layer rows converge to the continuous stretched
+    operator (Preamble: d/dx -> (1/eta) d/dx).  sigma'' jumps where the layer
+    starts, so the RMS order is about 1.5; stretches taken at the nodes
+    i +- 1 or i instead of the half nodes leave an O(1) error (about 15 here)."""
+    e = [_stretched_row_error(s) for s in (2, 4, 8)]
+    assert e[2] < 0.05
+    assert e[0] / e[1] > 2.5 and e[1] / e[2] > 2.5
+
+
+def test_layer_reflection_coefficient_and_coarse_rediscretisation():
+    """(i) The damping profile integrates to the nominal normal-incidence
+    reflection: exp(-(2/v_ref) int_0^Lp sigma dx) = R (continuous layer
+    theory; pins sigma_max and the quadratic profile in fine-grid units).
+    (ii) The coarse level of a grid (coarse node I at fine node 2I, spacing
+    2h, profile at fine coordinates 2I and 2I +- 1) has the layer rows of the
+    same physical problem discretised directly at spacing 2h."""
+    from oracle import mlgmres  # noqa: F401  (coarsening lives with the hierarchy)
+    g = ops.make_grid((61, 41, 33), 12.5, 10, 2 * np.pi * 6.0, 3200.0)
+    t = np.linspace(0.0, 10.0, 200001)
+    integral = np.trapezoid(ops.layer_sigma(g, 0, t), t) * g.h
+    assert abs(np.exp(-2.0 * integral / g.v_ref) - g.R) <= 1e-8
+    gc = ops.coarsen(g)
+    direct = ops.make_grid(gc.n, 2 * g.h, 5, g.omega, g.v_ref)
+    for a in range(3):
+        for c_coarse, c_direct in zip(ops.axis_coeffs(gc, a), ops.axis_coeffs(direct, a)):
+            assert np.allclose(c_coarse, c_direct, rtol=1e-13, atol=0.0)
+
+
 def test_adjoint_identity_7pt():
     """<H x, y> = <x, H^H y> (paper's adjoint test), random complex x, y, with
     and without zeroing in the layer and on the original boundary."""
@@ -154,6 +213,31 @@ def test_apply27_matches_assembly_and_adjoint():
     a = np.vdot(y, ops.apply27(g, m, x, w))
     b = np.vdot(ops.apply27(g, m, y, w, True), x)
     assert abs(a - b) / (np.linalg.norm(hx) * np.linalg.norm(y)) <= 1e-12
+
+
+def test_interior27_mask_by_brute_force():
+    """Rows that take the compact 27-point Laplacian: the node and all 26
+    neighbours lie where no axis is damped (sigma = 0), checked node by node
+    and offset by offset on a small grid (on a coarse level too).  On those
+    rows every 7-point layer coefficient is the undamped 1/h^2."""
+    g0 = ops.make_grid((13, 11, 12), 10.0, 3, 2 * np.pi * 5.0, 2600.0)
+    for g in (g0, ops.coarsen(ops.make_grid((25, 21, 23), 5.0, 6, 2 * np.pi * 5.0, 2600.0))):
+        mask = ops.interior27_mask(g)
+        brute = np.zeros(g.n, bool)
+        for p in np.ndindex(*g.n):
+            ok = True
+            for d in ops.offsets27():
+                for a in range(3):
+                    if ops.layer_sigma(g, a, p[a] + d[a]) != 0.0:
+                        ok = False
+            brute[p] = ok
+        assert np.array_equal(mask, brute)
+        assert brute.any() and not brute.all()
+        coeffs = [ops.axis_coeffs(g, a) for a in range(3)]
+        for p in zip(*np.nonzero(mask)):
+            for a in range(3):
+                for c in coeffs[a]:
+                    assert c[p[a]] == 1.0 / g.h ** 2
 
 
 def test_apply27_reduces_to_7pt():
