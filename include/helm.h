@@ -149,6 +149,28 @@ helm_status helm_apply(helm_ctx* ctx, const helm_grid* g, const void* m,
                        double omega, int adjoint, int nrhs, const void* x,
                        void* y, void* stream);
 
+/* helm_apply for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, operator and results (bitwise) as helm_apply, which
+ * allocates its cached operator description on a cache miss; this variant
+ * builds that description (layer tables, right-hand-side descriptors,
+ * stencil workgroup maps) with one setup kernel into a fixed 8 MiB scratch
+ * array of the library, one copy per GPU, kept until the process ends.  It
+ * calls no allocation routine, copies nothing from the host and does not
+ * synchronise: two kernel launches on `stream`.  The x chunk of the stencil
+ * tiles is the library's heuristic (no tile timing).
+ * Limits: the description must fit in 8 MiB (about 2^20 stencil workgroups
+ * over all right-hand sides; for complex128 or odd-nz 27-point operators,
+ * which use one workgroup per 256 points, nrhs * N up to about 5 * 10^8);
+ * larger requests return HELM_E_INVAL before any device work.
+ * Every call on one GPU overwrites that GPU's scratch array: calls that
+ * overlap on one GPU (on different streams, or from different contexts or
+ * host threads) race; calls ordered on one stream do not. */
+helm_status helm_apply_noalloc(helm_ctx* ctx, const helm_grid* g,
+                               const void* m, double omega, int adjoint,
+                               int nrhs, const void* x, void* y,
+                               void* stream);
+
 /* Solve H(m) u = q (adjoint = 0) or H(m)^H u = q (adjoint = 1) for nrhs
  * right-hand sides sharing m and omega (the paper's H\Q, all sources of one
  * frequency as one block) with the solver in *o (NULL = defaults).

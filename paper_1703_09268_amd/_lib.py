@@ -42,7 +42,7 @@ STATUS_NAMES = {
 # every entry point declared in include/helm.h
 EXPORTS = ("helm_create", "helm_destroy", "helm_last_error", "helm_version",
            "helm_default_opts", "helm_workspace_bytes", "helm_apply",
-           "helm_solve", "helm_solve_batched", "misfit_gradient")
+           "helm_apply_noalloc", "helm_solve", "helm_solve_batched", "misfit_gradient")
 
 
 class helm_grid(C.Structure):
@@ -96,13 +96,14 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.helm_workspace_bytes.argtypes = [G, O, i32]
     lib.helm_workspace_bytes.restype = C.c_size_t
     lib.helm_apply.argtypes = [vp, G, vp, dbl, i32, i32, vp, vp, vp]
+    lib.helm_apply_noalloc.argtypes = [vp, G, vp, dbl, i32, i32, vp, vp, vp]
     lib.helm_solve.argtypes = [vp, G, vp, dbl, i32, i32, vp, vp, O, I, vp]
     lib.helm_solve_batched.argtypes = [vp, i32, C.POINTER(helm_problem), i32, O, I, vp]
     lib.misfit_gradient.argtypes = [vp, G, vp, i32, C.POINTER(C.c_double), i32,
                                     C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                     C.POINTER(C.c_uint8), i32, C.POINTER(C.c_int32), vp,
                                     C.POINTER(C.c_double), vp, vp, i32, O, I, vp]
-    for name in ("helm_create", "helm_destroy", "helm_apply", "helm_solve",
+    for name in ("helm_create", "helm_destroy", "helm_apply", "helm_apply_noalloc", "helm_solve",
                  "helm_solve_batched", "misfit_gradient"):
         getattr(lib, name).restype = C.c_int
     _lib = lib

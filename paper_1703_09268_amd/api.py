@@ -159,6 +159,22 @@ def helm_apply(grid: Grid, m: torch.Tensor, omega: float, x: torch.Tensor,
     return out
 
 
+def helm_apply_noalloc(grid: Grid, m: torch.Tensor, omega: float, x: torch.Tensor,
+                       out: torch.Tensor, adjoint: bool = False) -> torch.Tensor:
+    """helm_apply through the allocation-free entry point: ``out`` must be
+    given (the call allocates nothing, here or in the library)."""
+    dev = x.device.index or 0
+    nrhs = _nrhs(x, grid.N)
+    ctx = _context(dev)
+    g = grid.c_struct()
+    st = L.load().helm_apply_noalloc(
+        ctx, C.byref(g), _dev_tensor(m, grid.real_dtype, grid.N, "m"), float(omega),
+        int(bool(adjoint)), nrhs, _dev_tensor(x, grid.complex_dtype, nrhs * grid.N, "x"),
+        _dev_tensor(out, grid.complex_dtype, nrhs * grid.N, "out"), _stream(dev))
+    _check(ctx, st)
+    return out
+
+
 def helm_solve(grid: Grid, m: torch.Tensor, omega: float, q: torch.Tensor,
                adjoint: bool = False, opts: Optional[SolverOpts] = None,
                u: Optional[torch.Tensor] = None, raise_on_failure: bool = True):

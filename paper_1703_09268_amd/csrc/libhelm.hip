@@ -13,6 +13,7 @@
 
 #include "common.h"
 #include "fwi.hip"
+#include "noalloc.hip"
 #include "solver.hip"
 
 namespace {
@@ -520,6 +521,19 @@ helm_status helm_create(helm_ctx** ctx, int device) {
     (void)hipGetLastError();
     return fail(nullptr, HELM_E_HIP, "no such HIP device");
   }
+  // the device address of the allocation-free entry point's scratch array,
+  // resolved once per device with that device current
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  try {
+    HELM_HIP_CHECK(hipSetDevice(device));
+    (void)helm::scratch_address(device);
+  } catch (const helm::Error& err) {
+    (void)hipGetLastError();
+    (void)hipSetDevice(prev);
+    return fail(nullptr, err.code, err.msg);
+  }
+  (void)hipSetDevice(prev);
   helm_ctx* c = new (std::nothrow) helm_ctx();
   if (!c) return fail(nullptr, HELM_E_NOMEM, "out of host memory");
   c->device = device;
@@ -607,6 +621,23 @@ helm_status helm_apply(helm_ctx* ctx, const helm_grid* g, const void* m, double 
           L, (const helm::cx<double>*)x, nullptr, (const helm::cx<double>*)nullptr, nullptr,
           (helm::cx<double>*)y, nullptr, nullptr, st);
     HELM_HIP_CHECK(hipGetLastError());
+    return HELM_OK;
+  });
+}
+
+helm_status helm_apply_noalloc(helm_ctx* ctx, const helm_grid* g, const void* m, double omega, int adjoint,
+                               int nrhs, const void* x, void* y, void* stream) {
+  return guarded(ctx, [&]() -> helm_status {
+    check_grid(g);
+    HELM_REQUIRE(m && x && y, "null device pointer");
+    HELM_REQUIRE(omega > 0.0 && std::isfinite(omega), "omega must be positive");
+    HELM_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+    HELM_REQUIRE(x != y, "x and y must not overlap");
+    const helm::GridSpec s = spec_of(g);
+    if (g->dtype == HELM_C64)
+      helm::apply_noalloc<float>(ctx->device, s, m, omega, adjoint ? 1 : 0, nrhs, x, y, (hipStream_t)stream);
+    else
+      helm::apply_noalloc<double>(ctx->device, s, m, omega, adjoint ? 1 : 0, nrhs, x, y, (hipStream_t)stream);
     return HELM_OK;
   });
 }

@@ -130,55 +130,88 @@ inline Int27 interior27_desc(const GridSpec& g, const int n[3], double h, int st
   return in27;
 }
 
+// Layer-table arithmetic shared by every path that builds tables (one
+// device kernel, so the tables of every entry point are bitwise identical).
+// sigma at fine coordinate tf of an axis with nf fine nodes.
+__device__ __forceinline__ double table_sigma(double smax, int npml, int nf, double tf) {
+  if (npml == 0) return 0.0;
+  const double d = fmax(0.0, fmax(npml - tf, tf - (nf - 1 - npml)));
+  return smax * (d / npml) * (d / npml);
+}
+// 1 / (h^2 s(t) s(t + dt)) with s(t) = 1 + i sigma(t) / omega, level
+// coordinates t (fine coordinate t * stride).
+__device__ __forceinline__ cx<double> table_coef(double h, double smax, int npml, int nf, int stride,
+                                                 double omega, double t, double dt) {
+  const cx<double> s0 = mk(1.0, table_sigma(smax, npml, nf, t * stride) / omega);
+  const cx<double> s1 = mk(1.0, table_sigma(smax, npml, nf, (t + dt) * stride) / omega);
+  const cx<double> z = (h * h) * (s0 * s1);
+  const double den = z.re * z.re + z.im * z.im;
+  return mk(z.re / den, -z.im / den);
+}
+
+// Layer tables of one operator on one level, [dir][axis][alpha, beta,
+// delta][n_axis] in complex<double> (tabd) and complex<float> (tabf).  Per
+// axis, cp(i) = 1/(h^2 s(i) s(i+1/2)) and cm(i) = 1/(h^2 s(i) s(i-1/2)).
+// Forward row: alpha = cp, beta = cm, delta = 0; a coupling to a node outside
+// the grid (zero Dirichlet value) is folded into delta and the coupling itself
+// set to zero, so a kernel may read any finite value in place of the missing
+// neighbour.  Adjoint row: the conjugates of the transposed couplings
+// (already zero towards nodes outside the grid).  One thread per (axis, node).
+__global__ void k_layer_tables(cx<double>* tabd, cx<float>* tabf, int n0, int n1, int n2, int f0, int f1, int f2,
+                               double h, double smax, int npml, int stride, double omega) {
+  const int n[3] = {n0, n1, n2}, nfine[3] = {f0, f1, f2};
+  const int tdir = 3 * (n0 + n1 + n2);
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n0 + n1 + n2; t += gridDim.x * blockDim.x) {
+    const int a = t < n0 ? 0 : t < n0 + n1 ? 1 : 2;
+    const int i = t - (a > 0 ? n0 : 0) - (a > 1 ? n1 : 0);
+    const int na = n[a], nf = nfine[a];
+    const int pre = a == 0 ? 0 : a == 1 ? 3 * n0 : 3 * (n0 + n1);
+    auto cp = [&](int k) { return table_coef(h, smax, npml, nf, stride, omega, (double)k, 0.5); };
+    auto cm = [&](int k) { return table_coef(h, smax, npml, nf, stride, omega, (double)k, -0.5); };
+    const cx<double> z = czero<double>();
+    const cx<double> cpi = cp(i), cmi = cm(i);
+    const cx<double> al = (i + 1 < na) ? cpi : z;
+    const cx<double> be = (i > 0) ? cmi : z;
+    const cx<double> de = (i + 1 < na ? z : mk(-cpi.re, -cpi.im)) + (i > 0 ? z : mk(-cmi.re, -cmi.im));
+    const cx<double> cmn = cm(i + 1), cpp = cp(i - 1);
+    const cx<double> aal = (i + 1 < na) ? mk(cmn.re, -cmn.im) : z;
+    const cx<double> abe = (i > 0) ? mk(cpp.re, -cpp.im) : z;
+    const cx<double> sum = cpi + cmi;
+    const cx<double> ade = mk(-sum.re, sum.im) + aal + abe;
+    const cx<double> v[6] = {al, be, de, aal, abe, ade};
+    for (int r = 0; r < 6; ++r) {
+      const int64_t o = (r >= 3 ? tdir : 0) + pre + (r % 3) * na + i;
+      tabd[o] = v[r];
+      tabf[o] = cast<float>(v[r]);
+    }
+  }
+}
+
+// sigma_max of the layer profile (fine-grid units)
+inline double layer_smax(const GridSpec& g) {
+  if (g.npml == 0) return 0.0;
+  return 3.0 * g.vref * std::log(1.0 / g.R) / (2.0 * g.npml * g.h);
+}
+
+inline void launch_layer_tables(const GridSpec& g, double omega, const int n[3], double h, int stride,
+                                cx<double>* tabd, cx<float>* tabf, hipStream_t st) {
+  const int nt = n[0] + n[1] + n[2];
+  hipLaunchKernelGGL(k_layer_tables, dim3(ceil_div(nt, 256)), dim3(256), 0, st, tabd, tabf, n[0], n[1], n[2],
+                     g.n[0], g.n[1], g.n[2], h, layer_smax(g), g.npml, stride, omega);
+  HELM_HIP_CHECK(hipGetLastError());
+}
+
 inline std::unique_ptr<OpTables> build_tables(const GridSpec& g, double omega, const int n[3], double h,
                                               int stride, hipStream_t st) {
-  typedef std::complex<double> C;
   std::unique_ptr<OpTables> T(new OpTables());
   for (int a = 0; a < 3; ++a) T->n[a] = n[a];
   T->tdir = 3 * (n[0] + n[1] + n[2]);
   T->tpre[0] = 0;
   T->tpre[1] = 3 * n[0];
   T->tpre[2] = 3 * (n[0] + n[1]);
-  std::vector<cx<double>> hd(2 * (size_t)T->tdir);
-  for (int a = 0; a < 3; ++a) {
-    const int na = n[a];
-    auto s_at = [&](double t) { return C(1.0, layer_sigma(g, a, t * stride) / omega); };
-    std::vector<C> cp(na), cm(na);
-    for (int i = 0; i < na; ++i) {
-      const C s0 = s_at(i), sp = s_at(i + 0.5), sm = s_at(i - 0.5);
-      cp[i] = 1.0 / (h * h * s0 * sp);
-      cm[i] = 1.0 / (h * h * s0 * sm);
-    }
-    for (int i = 0; i < na; ++i) {
-      // forward: alpha = cp, beta = cm, delta = 0.  The coupling to a node
-      // outside the grid (zero Dirichlet value) is folded into delta and the
-      // coupling itself set to zero, so a kernel may read any finite value
-      // in place of the missing neighbour.
-      const size_t f0 = (size_t)T->tpre[a];
-      const C al = (i + 1 < na) ? cp[i] : C(0, 0);
-      const C be = (i > 0) ? cm[i] : C(0, 0);
-      const C de = (i + 1 < na ? C(0, 0) : -cp[i]) + (i > 0 ? C(0, 0) : -cm[i]);
-      hd[f0 + i] = mk<double>(al.real(), al.imag());
-      hd[f0 + na + i] = mk<double>(be.real(), be.imag());
-      hd[f0 + 2 * na + i] = mk<double>(de.real(), de.imag());
-      // adjoint: conjugates of the transposed couplings (already zero
-      // towards nodes outside the grid)
-      const C aal = (i + 1 < na) ? std::conj(cm[i + 1]) : C(0, 0);
-      const C abe = (i > 0) ? std::conj(cp[i - 1]) : C(0, 0);
-      const C ade = -std::conj(cp[i] + cm[i]) + aal + abe;
-      const size_t a0 = (size_t)T->tdir + T->tpre[a];
-      hd[a0 + i] = mk<double>(aal.real(), aal.imag());
-      hd[a0 + na + i] = mk<double>(abe.real(), abe.imag());
-      hd[a0 + 2 * na + i] = mk<double>(ade.real(), ade.imag());
-    }
-  }
-  std::vector<cx<float>> hf(hd.size());
-  for (size_t i = 0; i < hd.size(); ++i) hf[i] = cast<float>(hd[i]);
-  T->tabd.ensure(hd.size() * sizeof(cx<double>));
-  T->tabf.ensure(hf.size() * sizeof(cx<float>));
-  HELM_HIP_CHECK(hipMemcpyAsync(T->tabd.p, hd.data(), hd.size() * sizeof(cx<double>), hipMemcpyHostToDevice, st));
-  HELM_HIP_CHECK(hipMemcpyAsync(T->tabf.p, hf.data(), hf.size() * sizeof(cx<float>), hipMemcpyHostToDevice, st));
-  HELM_HIP_CHECK(hipStreamSynchronize(st));  // the host vectors go out of scope
+  T->tabd.ensure(2 * (size_t)T->tdir * sizeof(cx<double>));
+  T->tabf.ensure(2 * (size_t)T->tdir * sizeof(cx<float>));
+  launch_layer_tables(g, omega, n, h, stride, T->tabd.as<cx<double>>(), T->tabf.as<cx<float>>(), st);
   T->in27 = interior27_desc(g, n, h, stride);
   return T;
 }
