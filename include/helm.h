@@ -279,6 +279,59 @@ helm_status misfit_gradient(helm_ctx* ctx, const helm_grid* g, const void* m,
                             const helm_solver_opts* o, helm_solve_info* info,
                             void* stream);
 
+/* pde_derivative modes (the paper's PDEfunc cases of the same names) */
+#define HELM_JACOB_FORW 1 /* output = J dm                       */
+#define HELM_JACOB_ADJ 2  /* output = J^* y                      */
+#define HELM_HESS_GN 3    /* output = H_GN dm = J^* J dm         */
+#define HELM_HESS 4       /* output = (Hessian of the misfit) dm */
+
+/* Linearised modelling and second-order products of the least-squares
+ * misfit, summed over the selected (frequency, source) pairs (paper: Table
+ * derivstuff rows Du, J, T, T^*, DT^*, H_GN and the Hessian; Table
+ * derivcosts, 2 / 2 / 3 / 4 PDE solves per pair; the Listing of PDEfunc,
+ * cases JACOB_FORW, JACOB_ADJ, HESS_GN, HESS; Appendix A, eqs. dU2, dH,
+ * dHadj, DTadj).  Per selected pair (f, s), with H = H_f, u = H^{-1} q_fs
+ * (q_fs, P_r, mask, c and the pair arguments exactly as in
+ * misfit_gradient), real model perturbation dm and
+ *   T dm = omega_f^2 A (u * dm),   T^* z = omega_f^2 conj(u) * (A^H z):
+ *   HELM_JACOB_FORW  du = -H^{-1} T dm;          output[f][s] = P_r du
+ *   HELM_JACOB_ADJ   v = -H^{-H} P_r^T y_fs;     output = c sum Re(T^* v)
+ *   HELM_HESS_GN     w = -H^{-H} P_r^T P_r du;   output = c sum Re(T^* w)
+ *   HELM_HESS        v = -H^{-H} P_r^T (P_r u - d_fs),
+ *                    dv = H^{-H}(-omega_f^2 dm * (A v) - P_r^T P_r du);
+ *                    output = c sum Re(omega_f^2 conj(du) * (A v))
+ *                                   + Re(T^* dv)
+ * (the derivative of H^H v = -P_r^T r: the sign and the DH[dm]^H form of
+ * its first term follow from differentiating the adjoint equation).
+ * Arguments (the pair arguments as in misfit_gradient):
+ *   mode     HELM_JACOB_FORW / HELM_JACOB_ADJ / HELM_HESS_GN / HELM_HESS
+ *   input    dev: dm, N reals (float for C64, double for C128), or, for
+ *            HELM_JACOB_ADJ, y, [nfreq][nsrc][nrec] complex of g->dtype
+ *   d        dev [nfreq][nsrc][nrec] complex: observed data (HELM_HESS
+ *            only; may be NULL otherwise)
+ *   output   dev: HELM_JACOB_FORW [nfreq][nsrc][nrec] complex (rows of
+ *            unselected pairs are zeroed); otherwise N reals, overwritten
+ *            (added to with HELM_MG_ACCUMULATE)
+ *   u_store  dev or NULL: the forward fields, as in misfit_gradient
+ *   flags    HELM_MG_REUSE_U, HELM_MG_U_FP64, HELM_MG_ACCUMULATE,
+ *            HELM_MG_RENORMALISE (c = 1/#selected; applies to the
+ *            model-space outputs)
+ *   info     host, 4*nfreq*nsrc entries or NULL: solve k of pair (f, s) at
+ *            k*nfreq*nsrc + f*nsrc + s; k = 0 the forward fields (zero with
+ *            HELM_MG_REUSE_U), then in the order of the formulas above
+ *            (JACOB_FORW: du; JACOB_ADJ: v; HESS_GN: du, w; HESS: v, du,
+ *            dv); unused entries are zero
+ * Invalid arguments return HELM_E_INVAL before any device work.  Returns
+ * the worst status of the solves. */
+helm_status pde_derivative(helm_ctx* ctx, int mode, const helm_grid* g,
+                           const void* m, int nfreq, const double* omega,
+                           int nsrc, const int32_t* src_idx,
+                           const double* src_amp, const uint8_t* mask,
+                           int nrec, const int32_t* rec_idx, const void* input,
+                           const void* d, void* output, void* u_store,
+                           int flags, const helm_solver_opts* o,
+                           helm_solve_info* info, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -29,6 +29,11 @@ HELM_MG_ACCUMULATE = 4
 HELM_MG_U_FP64 = 8
 HELM_MG_RENORMALISE = 16
 
+HELM_JACOB_FORW = 1
+HELM_JACOB_ADJ = 2
+HELM_HESS_GN = 3
+HELM_HESS = 4
+
 STATUS_NAMES = {
     HELM_OK: "HELM_OK",
     HELM_NOT_CONVERGED: "HELM_NOT_CONVERGED",
@@ -42,7 +47,8 @@ STATUS_NAMES = {
 # every entry point declared in include/helm.h
 EXPORTS = ("helm_create", "helm_destroy", "helm_last_error", "helm_version",
            "helm_default_opts", "helm_workspace_bytes", "helm_apply",
-           "helm_apply_noalloc", "helm_solve", "helm_solve_batched", "misfit_gradient")
+           "helm_apply_noalloc", "helm_solve", "helm_solve_batched", "misfit_gradient",
+           "pde_derivative")
 
 
 class helm_grid(C.Structure):
@@ -103,8 +109,12 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                                     C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                     C.POINTER(C.c_uint8), i32, C.POINTER(C.c_int32), vp,
                                     C.POINTER(C.c_double), vp, vp, i32, O, I, vp]
+    lib.pde_derivative.argtypes = [vp, i32, G, vp, i32, C.POINTER(C.c_double), i32,
+                                   C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                   C.POINTER(C.c_uint8), i32, C.POINTER(C.c_int32), vp, vp,
+                                   vp, vp, i32, O, I, vp]
     for name in ("helm_create", "helm_destroy", "helm_apply", "helm_apply_noalloc", "helm_solve",
-                 "helm_solve_batched", "misfit_gradient"):
+                 "helm_solve_batched", "misfit_gradient", "pde_derivative"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib

@@ -306,6 +306,81 @@ def misfit_gradient(grid: Grid, m: torch.Tensor, omega, src, rec, d: torch.Tenso
     return f.value, grad, inf
 
 
+_MODES = {"jacobian": L.HELM_JACOB_FORW, "jacobian_adjoint": L.HELM_JACOB_ADJ,
+          "hessian_gn": L.HELM_HESS_GN, "hessian": L.HELM_HESS}
+
+
+def pde_derivative(mode: str, grid: Grid, m: torch.Tensor, omega, src, rec, input: torch.Tensor,
+                   d: Optional[torch.Tensor] = None, src_amp=None, mask=None,
+                   out: Optional[torch.Tensor] = None, u_store: Optional[torch.Tensor] = None,
+                   reuse_u: bool = False, u_fp64: bool = False, accumulate: bool = False,
+                   renormalise: bool = False, opts: Optional[SolverOpts] = None,
+                   raise_on_failure: bool = True):
+    """Linearised products over the selected (frequency, source) pairs.
+
+    mode: "jacobian" (J dm -> [nfreq][nsrc][nrec] complex), "jacobian_adjoint"
+    (J^* y, y [nfreq][nsrc][nrec] -> model), "hessian_gn" (J^* J dm) or
+    "hessian" (full Hessian of the misfit with observed data d, applied to
+    dm).  Other arguments as in misfit_gradient.  Returns (out, infos): infos
+    per solve (forward fields first, then the mode's solves), each
+    [frequency][source] (zero entries for unselected pairs / solves not run)."""
+    if mode not in _MODES:
+        raise ValueError(f"mode must be one of {sorted(_MODES)}")
+    md = _MODES[mode]
+    if (u_fp64 or reuse_u) and u_store is None:
+        raise ValueError("u_fp64 and reuse_u need u_store")
+    if md == L.HELM_HESS and d is None:
+        raise ValueError("the full Hessian needs the observed data d")
+    dev = m.device.index or 0
+    om = np.ascontiguousarray(np.atleast_1d(np.asarray(omega, dtype=np.float64)).ravel())
+    nfreq = len(om)
+    src_a = _idx_array(src)
+    rec_a = _idx_array(rec)
+    nsrc, nrec = len(src_a), len(rec_a)
+    npair = nfreq * nsrc
+    amp_p = None
+    if src_amp is not None:
+        amp = np.broadcast_to(np.asarray(src_amp, np.complex128), (nfreq, nsrc))
+        amp_d = np.ascontiguousarray(np.stack([amp.real, amp.imag], axis=-1).ravel())
+        amp_p = amp_d.ctypes.data_as(C.POINTER(C.c_double))
+    mask_p = None
+    if mask is not None:
+        mask_a = np.ascontiguousarray(
+            np.broadcast_to(np.asarray(mask, bool), (nfreq, nsrc)).astype(np.uint8))
+        mask_p = mask_a.ctypes.data_as(C.POINTER(C.c_uint8))
+    flags = (L.HELM_MG_REUSE_U if reuse_u else 0) | (L.HELM_MG_ACCUMULATE if accumulate else 0) | \
+        (L.HELM_MG_U_FP64 if u_fp64 else 0) | (L.HELM_MG_RENORMALISE if renormalise else 0)
+    if md == L.HELM_JACOB_ADJ:
+        in_p = _dev_tensor(input, grid.complex_dtype, npair * nrec, "input")
+    else:
+        in_p = _dev_tensor(input, grid.real_dtype, grid.N, "input")
+    if out is None:
+        out = (torch.empty((nfreq, nsrc, nrec), dtype=grid.complex_dtype, device=m.device)
+               if md == L.HELM_JACOB_FORW else
+               torch.empty(tuple(grid.n), dtype=grid.real_dtype, device=m.device))
+    out_p = (_dev_tensor(out, grid.complex_dtype, npair * nrec, "out") if md == L.HELM_JACOB_FORW
+             else _dev_tensor(out, grid.real_dtype, grid.N, "out"))
+    u_dtype = torch.complex128 if u_fp64 else grid.complex_dtype
+    opts = opts or SolverOpts()
+    infos = (L.helm_solve_info * (4 * npair))()
+    ctx = _context(dev)
+    g, o = grid.c_struct(), opts.c_struct()
+    st = L.load().pde_derivative(
+        ctx, md, C.byref(g), _dev_tensor(m, grid.real_dtype, grid.N, "m"), nfreq,
+        om.ctypes.data_as(C.POINTER(C.c_double)), nsrc,
+        src_a.ctypes.data_as(C.POINTER(C.c_int32)), amp_p, mask_p, nrec,
+        rec_a.ctypes.data_as(C.POINTER(C.c_int32)), in_p,
+        None if d is None else _dev_tensor(d, grid.complex_dtype, npair * nrec, "d"), out_p,
+        None if u_store is None else _dev_tensor(u_store, u_dtype, npair * grid.N, "u_store"),
+        flags, C.byref(o), infos, _stream(dev))
+    allow = (L.HELM_OK,) if raise_on_failure else (L.HELM_OK, L.HELM_NOT_CONVERGED, L.HELM_BREAKDOWN)
+    _check(ctx, st, allow)
+    nsolve = {L.HELM_JACOB_FORW: 2, L.HELM_JACOB_ADJ: 2, L.HELM_HESS_GN: 3, L.HELM_HESS: 4}[md]
+    inf = [[SolveInfo(i.status, i.cycles, i.inner_its, i.matvecs, i.relres_fp64)
+            for i in list(infos)[k * npair:(k + 1) * npair]] for k in range(nsolve)]
+    return out, inf
+
+
 def version() -> str:
     return L.load().helm_version().decode()
 

@@ -1,6 +1,7 @@
 // Adjoint-state misfit / gradient kernels (arXiv:1703.09268, Listing of
-// PDEfunc case OBJ; Table derivstuff rows u, V, grad f; Appendix A eq.
-// dHadj), over a list of (frequency, source) pairs solved together:
+// PDEfunc cases OBJ, JACOB_FORW, JACOB_ADJ, HESS_GN, HESS; Table derivstuff;
+// Appendix A eqs. dH, dHadj, DTadj), over a list of (frequency, source)
+// pairs solved together:
 //   q_p = amp_p e_{src_p} / h^3                   (on-node point source)
 //   r_p = P_r u_p - d_p,  f = 1/2 sum_p ||r_p||^2  (FP64 accumulation)
 //   b_p = -P_r^T r_p                               (adjoint source)
@@ -58,22 +59,89 @@ __global__ __launch_bounds__(256) void k_sample_residual(const cx<TU>* __restric
   if (threadIdx.x == 0) part[(int64_t)s * gridDim.x + blockIdx.x] = t;
 }
 
-// b[s] = -P_r^T r[s]: one lane per distinct receiver node, summing that node's
-// receivers (node_ptr/node_rec: CSR over distinct nodes, ascending).  b must
+// b[s] (+)= -P_r^T r[rrow_s]: one lane per distinct receiver node, summing
+// that node's receivers (node_ptr/node_rec: CSR over distinct nodes,
+// ascending).  rrow (row of pair s in r; null: row s).  Without ADD, b must
 // be zero beforehand.
-template <typename T>
+template <typename T, bool ADD = false>
 __global__ __launch_bounds__(256) void k_adjoint_source(cx<T>* __restrict__ b, int64_t N,
                                                         const int64_t* __restrict__ node_lin,
                                                         const int* __restrict__ node_ptr,
                                                         const int* __restrict__ node_rec, int nnode,
-                                                        const cx<T>* __restrict__ res, int nrec) {
+                                                        const cx<T>* __restrict__ res, int nrec,
+                                                        const int64_t* __restrict__ rrow = nullptr) {
   const int s = blockIdx.y;
   const int q = blockIdx.x * 256 + threadIdx.x;
   if (q >= nnode) return;
+  const int64_t row = rrow ? rrow[s] : s;
   cx<double> acc = czero<double>();
   for (int e = node_ptr[q]; e < node_ptr[q + 1]; ++e)
-    acc = acc + cast<double>(res[(int64_t)s * nrec + node_rec[e]]);
-  b[s * N + node_lin[q]] = cast<T>(mk<double>(-acc.re, -acc.im));
+    acc = acc + cast<double>(res[row * nrec + node_rec[e]]);
+  cx<T>* dst = b + s * N + node_lin[q];
+  if (ADD) acc = mk<double>(acc.re - (double)dst->re, acc.im - (double)dst->im);
+  *dst = cast<T>(mk<double>(-acc.re, -acc.im));
+}
+
+// out[orow_s][k] = u[uoff_s + rec_k]: receiver sampling P_r of pair s's field
+// (u may be an FP64 outer iterate).
+template <typename TU, typename T>
+__global__ __launch_bounds__(256) void k_sample(const cx<TU>* __restrict__ u, const int64_t* __restrict__ uoff,
+                                                const int64_t* __restrict__ rec_lin, int nrec,
+                                                cx<T>* __restrict__ out, const int64_t* __restrict__ orow) {
+  const int s = blockIdx.y;
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k < nrec) out[orow[s] * nrec + k] = cast<T>(u[uoff[s] + rec_lin[k]]);
+}
+
+// Right-hand sides of the linearised problems (Appendix A, eqs. dH and the
+// derivative of the adjoint equation), pair s, w_s = omega_s^2:
+//   DHADJ = false:  out_s = -w_s A (x_s * dm)     (-T dm, x = the forward field)
+//   DHADJ = true:   out_s = -w_s dm * (A x_s)     (-DH[dm]^H x, x = an adjoint field)
+// A = I (7-point) or the 27-point mass distribution (real symmetric, zero
+// outside the grid).  x_s starts at x + xoff[s]; out is contiguous per pair.
+template <typename TX, typename T, bool MASS27, bool DHADJ>
+__global__ __launch_bounds__(256) void k_born_source(const cx<TX>* __restrict__ x, const int64_t* __restrict__ xoff,
+                                                     const T* __restrict__ dm, int npair, int nx, int ny, int nz,
+                                                     const double* __restrict__ w, double mw0, double mw1,
+                                                     double mw2, double mw3, cx<T>* __restrict__ out) {
+  const int64_t N = (int64_t)nx * ny * nz;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  const int s = blockIdx.y;
+  const cx<TX>* xs = x + xoff[s];
+  const double ws = w[s];
+  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < N; p += stride) {
+    cx<double> acc;
+    if (!MASS27) {
+      acc = (double)dm[p] * cast<double>(xs[p]);
+    } else {
+      const int k = (int)(p % nz);
+      const int j = (int)((p / nz) % ny);
+      const int i = (int)(p / ((int64_t)ny * nz));
+      const double mw[4] = {mw0, mw1, mw2, mw3};
+      acc = czero<double>();
+      for (int di = -1; di <= 1; ++di) {
+        if (i + di < 0 || i + di >= nx) continue;
+        for (int dj = -1; dj <= 1; ++dj) {
+          if (j + dj < 0 || j + dj >= ny) continue;
+          for (int dk = -1; dk <= 1; ++dk) {
+            if (k + dk < 0 || k + dk >= nz) continue;
+            const int cls = (di != 0) + (dj != 0) + (dk != 0);
+            const int64_t q = p + (int64_t)di * ny * nz + (int64_t)dj * nz + dk;
+            const double f = DHADJ ? mw[cls] : mw[cls] * (double)dm[q];
+            acc = acc + f * cast<double>(xs[q]);
+          }
+        }
+      }
+      if (DHADJ) acc = (double)dm[p] * acc;
+    }
+    out[s * N + p] = cast<T>(mk<double>(-ws * acc.re, -ws * acc.im));
+  }
+}
+
+// x[0..n) = 0 (real)
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill_zero_real(T* __restrict__ x, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) x[i] = T(0);
 }
 
 // g[p] (+)= sum_s Re(w_s conj(u_s[p]) (A v_s)[p]) over the pairs s, with

@@ -303,52 +303,61 @@ helm_status solve_batched_t(helm_ctx* ctx, int nprob, const helm_problem* probs,
   return (helm_status)worst;
 }
 
-// misfit + gradient over the selected (frequency, source) pairs, element type T
+// The selected (frequency, source) pairs of a misfit or derivative call:
+// host tables, their device copies (in the context's small scratch) and the
+// receiver node lists.  Pair p is row prow[p] = f * nsrc + s of the caller's
+// [frequency][source] arrays; internal per-pair vectors are contiguous
+// (offset p * N).
 template <typename T>
-helm_status misfit_gradient_t(helm_ctx* ctx, const helm_grid* g, const void* m, int nfreq, const double* omega,
-                              int nsrc, const int32_t* src_idx, const double* src_amp, const uint8_t* mask,
-                              int nrec, const int32_t* rec_idx, const void* d, double* f, void* grad,
-                              void* u_store, int flags, const helm::SolveOpts& o, helm_solve_info* info,
-                              void* caller) {
-  using namespace helm;
-  hipStream_t st = solve_stream(ctx, caller);
-  const int64_t N = (int64_t)g->n[0] * g->n[1] * g->n[2];
-  const int64_t plane = (int64_t)g->n[1] * g->n[2];
-  auto lin = [&](const int32_t* p) { return (int64_t)p[0] * plane + (int64_t)p[1] * g->n[2] + p[2]; };
-  const bool fwd_only = (flags & HELM_MG_FORWARD_ONLY) != 0;
-  const bool reuse = (flags & HELM_MG_REUSE_U) != 0;
-  const bool acc = (flags & HELM_MG_ACCUMULATE) != 0;
-  const bool u64 = (flags & HELM_MG_U_FP64) != 0 && sizeof(T) == 4;
-  const int nall = nfreq * nsrc;
-  if (info)
-    for (int k = 0; k < 2 * nall; ++k) to_info(SolveInfo(), info + k);
-  // the selected pairs, frequency-major; row = f * nsrc + s
+struct Pairs {
+  int np = 0, nall = 0, nsrc = 0, nrec = 0, nnode = 0, rblk = 0;
+  int64_t N = 0;
+  double scale = 1.0;  // 1 / #pairs with HELM_MG_RENORMALISE, else 1
   std::vector<int> prow;
-  for (int k = 0; k < nall; ++k)
-    if (!mask || mask[k]) prow.push_back(k);
-  const int np = (int)prow.size();
-  if (np == 0) {
-    *f = 0.0;
-    if (!fwd_only && !acc) HELM_HIP_CHECK(hipMemsetAsync(grad, 0, (size_t)N * sizeof(T), st));
-    HELM_HIP_CHECK(hipStreamSynchronize(st));
-    return HELM_OK;
-  }
-  const double scale = (flags & HELM_MG_RENORMALISE) ? 1.0 / np : 1.0;
-  // host tables per pair
-  std::vector<int64_t> src_lin(np), drow(np), uoff_int(np), uoff_store(np);
+  std::vector<helm::ProblemSpec> probs;
+  // device tables
+  int64_t *src = nullptr, *drow = nullptr, *uoff_int = nullptr, *uoff_store = nullptr, *rec = nullptr,
+          *node = nullptr, *ident = nullptr;  // ident[p] = p
+  double2* amp = nullptr;
+  double *w2 = nullptr, *wg = nullptr;  // omega^2; omega^2 * scale (model-space sums)
+  helm::cx<T>* res = nullptr;           // [np][nrec] receiver values
+  double* part = nullptr;               // [np][rblk] partial sums
+  int *nptr = nullptr, *nrec_ord = nullptr;
+};
+
+template <typename T>
+Pairs<T> plan_pairs(helm_ctx* ctx, const helm_grid* g, const void* m, int nfreq, const double* omega, int nsrc,
+                    const int32_t* src_idx, const double* src_amp, const uint8_t* mask, int nrec,
+                    const int32_t* rec_idx, bool renormalise, hipStream_t st) {
+  using namespace helm;
+  Pairs<T> P;
+  P.N = (int64_t)g->n[0] * g->n[1] * g->n[2];
+  P.nsrc = nsrc;
+  P.nrec = nrec;
+  P.nall = nfreq * nsrc;
+  const int64_t plane = (int64_t)g->n[1] * g->n[2];
+  auto lin = [&](const int32_t* q) { return (int64_t)q[0] * plane + (int64_t)q[1] * g->n[2] + q[2]; };
+  for (int k = 0; k < P.nall; ++k)
+    if (!mask || mask[k]) P.prow.push_back(k);
+  P.np = (int)P.prow.size();
+  if (P.np == 0) return P;
+  const int np = P.np;
+  P.scale = renormalise ? 1.0 / np : 1.0;
+  std::vector<int64_t> src_lin(np), drow(np), uoff_int(np), uoff_store(np), ident(np);
   std::vector<double2> amp(np);
-  std::vector<double> wgt(np);
-  std::vector<ProblemSpec> probs;
+  std::vector<double> w2(np), wg(np);
   for (int p = 0; p < np; ++p) {
-    const int fi = prow[p] / nsrc, s = prow[p] % nsrc;
+    const int fi = P.prow[p] / nsrc, s = P.prow[p] % nsrc;
     src_lin[p] = lin(src_idx + 3 * s);
-    const double* a = src_amp ? src_amp + 2 * (size_t)prow[p] : nullptr;
+    const double* a = src_amp ? src_amp + 2 * (size_t)P.prow[p] : nullptr;
     amp[p] = a ? make_double2(a[0], a[1]) : make_double2(1.0, 0.0);
-    drow[p] = prow[p];
-    uoff_int[p] = (int64_t)p * N;
-    uoff_store[p] = (int64_t)prow[p] * N;
-    wgt[p] = omega[fi] * omega[fi] * scale;
-    probs.push_back(shared_problems(g, m, omega[fi], 0, 1)[0]);
+    drow[p] = P.prow[p];
+    uoff_int[p] = (int64_t)p * P.N;
+    uoff_store[p] = (int64_t)P.prow[p] * P.N;
+    ident[p] = p;
+    w2[p] = omega[fi] * omega[fi];
+    wg[p] = w2[p] * P.scale;
+    P.probs.push_back(shared_problems(g, m, omega[fi], 0, 1)[0]);
   }
   std::vector<int64_t> rec_lin(nrec);
   for (int k = 0; k < nrec; ++k) rec_lin[k] = lin(rec_idx + 3 * k);
@@ -367,133 +376,88 @@ helm_status misfit_gradient_t(helm_ctx* ctx, const helm_grid* g, const void* m, 
     node_rec[e] = k;
   }
   node_ptr.push_back(nrec);
-  const int nnode = (int)node_lin.size();
-  // Device scratch: Q (sources, then adjoint sources), V, and U unless the
-  // solve writes the caller's u_store directly (every pair selected, fields
-  // stored in the dtype).
-  const size_t fbytes = (size_t)np * N * sizeof(cx<T>);
-  const bool direct_u = u_store && !u64 && np == nall;
-  const bool own_u = !reuse && !direct_u;
-  ctx->fwi_buf.ensure(fbytes * (own_u ? 3 : 2));
-  char* base = (char*)ctx->fwi_buf.p;
-  cx<T>* Q = (cx<T>*)base;
-  cx<T>* V = (cx<T>*)(base + fbytes);
-  cx<T>* U = direct_u ? (cx<T>*)u_store : own_u ? (cx<T>*)(base + 2 * fbytes) : nullptr;
-  const int rblk = (int)ceil_div(nrec, 256);
+  P.nnode = (int)node_lin.size();
+  P.rblk = (int)ceil_div(nrec, 256);
   auto r256 = [](size_t b) { return (b + 255) / 256 * 256; };
-  const size_t small = 4 * r256(np * sizeof(int64_t)) + r256(np * sizeof(double2)) + r256(np * sizeof(double)) +
-                       r256(nrec * sizeof(int64_t)) + r256((size_t)np * nrec * sizeof(cx<T>)) +
-                       r256((size_t)np * rblk * sizeof(double)) + r256(nnode * sizeof(int64_t)) +
-                       r256((nnode + 1) * sizeof(int)) + r256(nrec * sizeof(int));
+  const size_t small = 5 * r256(np * sizeof(int64_t)) + r256(np * sizeof(double2)) +
+                       2 * r256(np * sizeof(double)) + r256(nrec * sizeof(int64_t)) +
+                       r256((size_t)np * nrec * sizeof(cx<T>)) + r256((size_t)np * P.rblk * sizeof(double)) +
+                       r256(P.nnode * sizeof(int64_t)) + r256((P.nnode + 1) * sizeof(int)) +
+                       r256(nrec * sizeof(int));
   ctx->fwi_small.ensure(small);
   char* sp = (char*)ctx->fwi_small.p;
   char* const sp_end = sp + small;
   auto carve = [&](size_t b) {
-    char* p = sp;
+    char* q = sp;
     sp += r256(b);
     if (sp > sp_end) throw Error{-3, "internal: misfit scratch layout overflow"};
-    return (void*)p;
+    return (void*)q;
   };
-  int64_t* d_src = (int64_t*)carve(np * sizeof(int64_t));
-  int64_t* d_drow = (int64_t*)carve(np * sizeof(int64_t));
-  int64_t* d_uoff_int = (int64_t*)carve(np * sizeof(int64_t));
-  int64_t* d_uoff_store = (int64_t*)carve(np * sizeof(int64_t));
-  double2* d_amp = (double2*)carve(np * sizeof(double2));
-  double* d_w = (double*)carve(np * sizeof(double));
-  int64_t* d_rec = (int64_t*)carve(nrec * sizeof(int64_t));
-  cx<T>* d_res = (cx<T>*)carve((size_t)np * nrec * sizeof(cx<T>));
-  double* d_part = (double*)carve((size_t)np * rblk * sizeof(double));
-  int64_t* d_node = (int64_t*)carve(nnode * sizeof(int64_t));
-  int* d_nptr = (int*)carve((nnode + 1) * sizeof(int));
-  int* d_nrec = (int*)carve(nrec * sizeof(int));
+  P.src = (int64_t*)carve(np * sizeof(int64_t));
+  P.drow = (int64_t*)carve(np * sizeof(int64_t));
+  P.uoff_int = (int64_t*)carve(np * sizeof(int64_t));
+  P.uoff_store = (int64_t*)carve(np * sizeof(int64_t));
+  P.ident = (int64_t*)carve(np * sizeof(int64_t));
+  P.amp = (double2*)carve(np * sizeof(double2));
+  P.w2 = (double*)carve(np * sizeof(double));
+  P.wg = (double*)carve(np * sizeof(double));
+  P.rec = (int64_t*)carve(nrec * sizeof(int64_t));
+  P.res = (cx<T>*)carve((size_t)np * nrec * sizeof(cx<T>));
+  P.part = (double*)carve((size_t)np * P.rblk * sizeof(double));
+  P.node = (int64_t*)carve(P.nnode * sizeof(int64_t));
+  P.nptr = (int*)carve((P.nnode + 1) * sizeof(int));
+  P.nrec_ord = (int*)carve(nrec * sizeof(int));
   auto up = [&](void* dst, const void* src, size_t b) {
     HELM_HIP_CHECK(hipMemcpyAsync(dst, src, b, hipMemcpyHostToDevice, st));
   };
-  up(d_src, src_lin.data(), np * sizeof(int64_t));
-  up(d_drow, drow.data(), np * sizeof(int64_t));
-  up(d_uoff_int, uoff_int.data(), np * sizeof(int64_t));
-  up(d_uoff_store, uoff_store.data(), np * sizeof(int64_t));
-  up(d_amp, amp.data(), np * sizeof(double2));
-  up(d_w, wgt.data(), np * sizeof(double));
-  up(d_rec, rec_lin.data(), nrec * sizeof(int64_t));
-  up(d_node, node_lin.data(), nnode * sizeof(int64_t));
-  up(d_nptr, node_ptr.data(), (nnode + 1) * sizeof(int));
-  up(d_nrec, node_rec.data(), nrec * sizeof(int));
-
-  Solver<T>& S = solver_for<T>(ctx, probs, o, st);
-  std::vector<SolveInfo> inf(np);
-  int worst = 0;
-  const unsigned fb = std::min<unsigned>(65536, ceil_div((int64_t)np * N, 256));
-  // where the gradient reads the forward fields: (pointer, per-pair offsets, FP64?)
-  const void* ug = U;
-  const int64_t* ug_off = d_uoff_int;
-  bool ug64 = false;
-  if (!reuse) {
-    const double inv_h3 = 1.0 / (g->h * g->h * g->h);
-    hipLaunchKernelGGL((k_point_sources<T>), dim3(std::min<unsigned>(DOT_BLOCKS, ceil_div(N, 256)), np), dim3(256),
-                       0, st, Q, N, (const int64_t*)d_src, (const double2*)d_amp, inv_h3);
-    worst = std::max(worst, S.solve(0, Q, U, inf.data()));
-    if (info)
-      for (int p = 0; p < np; ++p) to_info(inf[p], info + prow[p]);
-    if (u64) {  // keep the FP64 iterates as the stored fields
-      if (np == nall) {
-        hipLaunchKernelGGL((k_convert<double, double>), dim3(fb), dim3(256), 0, st, S.iterate(),
-                           (cx<double>*)u_store, N * np);
-      } else {
-        const unsigned pb = std::min<unsigned>(65536, ceil_div(N, 256));
-        for (int p = 0; p < np; ++p)
-          hipLaunchKernelGGL((k_convert<double, double>), dim3(pb), dim3(256), 0, st, S.iterate() + p * N,
-                             (cx<double>*)u_store + prow[p] * N, N);
-      }
-      ug = u_store;
-      ug_off = d_uoff_store;
-      ug64 = true;
-    } else if (u_store && !direct_u) {
-      for (int p = 0; p < np; ++p)
-        HELM_HIP_CHECK(hipMemcpyAsync((cx<T>*)u_store + prow[p] * N, U + p * N, N * sizeof(cx<T>),
-                                      hipMemcpyDeviceToDevice, st));
-    }
-    hipLaunchKernelGGL((k_sample_residual<double, T>), dim3(rblk, np), dim3(256), 0, st, S.iterate(),
-                       (const int64_t*)d_uoff_int, (const int64_t*)d_rec, nrec, (const cx<T>*)d,
-                       (const int64_t*)d_drow, d_res, d_part);
-  } else {
-    ug = u_store;
-    ug_off = d_uoff_store;
-    ug64 = u64;
-    if (u64)
-      hipLaunchKernelGGL((k_sample_residual<double, T>), dim3(rblk, np), dim3(256), 0, st,
-                         (const cx<double>*)u_store, (const int64_t*)d_uoff_store, (const int64_t*)d_rec, nrec,
-                         (const cx<T>*)d, (const int64_t*)d_drow, d_res, d_part);
-    else
-      hipLaunchKernelGGL((k_sample_residual<T, T>), dim3(rblk, np), dim3(256), 0, st, (const cx<T>*)u_store,
-                         (const int64_t*)d_uoff_store, (const int64_t*)d_rec, nrec, (const cx<T>*)d,
-                         (const int64_t*)d_drow, d_res, d_part);
-  }
-  std::vector<double> hpart((size_t)np * rblk);
-  HELM_HIP_CHECK(hipMemcpyAsync(hpart.data(), d_part, hpart.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  up(P.src, src_lin.data(), np * sizeof(int64_t));
+  up(P.drow, drow.data(), np * sizeof(int64_t));
+  up(P.uoff_int, uoff_int.data(), np * sizeof(int64_t));
+  up(P.uoff_store, uoff_store.data(), np * sizeof(int64_t));
+  up(P.ident, ident.data(), np * sizeof(int64_t));
+  up(P.amp, amp.data(), np * sizeof(double2));
+  up(P.w2, w2.data(), np * sizeof(double));
+  up(P.wg, wg.data(), np * sizeof(double));
+  up(P.rec, rec_lin.data(), nrec * sizeof(int64_t));
+  up(P.node, node_lin.data(), P.nnode * sizeof(int64_t));
+  up(P.nptr, node_ptr.data(), (P.nnode + 1) * sizeof(int));
+  up(P.nrec_ord, node_rec.data(), nrec * sizeof(int));
+  // the host vectors above go out of scope: the copies must have completed
   HELM_HIP_CHECK(hipStreamSynchronize(st));
-  double fsum = 0.0;
-  for (size_t i = 0; i < hpart.size(); ++i) fsum += hpart[i];
-  *f = 0.5 * fsum * scale;
-  if (fwd_only) return (helm_status)worst;
-  // adjoint sources b_p = -P_r^T r_p, then H^H v_p = b_p
-  hipLaunchKernelGGL((k_fill_zero<T>), dim3(fb), dim3(256), 0, st, Q, (int64_t)np * N);
-  hipLaunchKernelGGL((k_adjoint_source<T>), dim3(ceil_div(nnode, 256), np), dim3(256), 0, st, Q, N,
-                     (const int64_t*)d_node, (const int*)d_nptr, (const int*)d_nrec, nnode, (const cx<T>*)d_res,
-                     nrec);
-  worst = std::max(worst, S.solve(1, Q, V, inf.data()));
-  if (info)
-    for (int p = 0; p < np; ++p) to_info(inf[p], info + nall + prow[p]);
-  // gradient
-  const unsigned gb = std::min<unsigned>(4096, ceil_div(N, 256));
+  return P;
+}
+
+// Where kernels read per-pair fields: base pointer, per-pair element
+// offsets (device), FP64 or the dtype.
+struct FieldRef {
+  const void* p;
+  const int64_t* off;
+  bool f64;
+};
+
+// The 27-point mass weights (centre, face, edge, corner); identity for 7-point.
+inline void mass_weights(const helm_grid* g, double mw[4]) {
   const bool m27 = g->stencil == HELM_27PT;
-  const double mw[4] = {m27 ? g->w27[3] : 1.0, m27 ? g->w27[4] : 0.0, m27 ? g->w27[5] : 0.0,
-                        m27 ? g->w27[6] : 0.0};
-#define HELM_GRAD(TU, M27)                                                                                \
-  hipLaunchKernelGGL((k_gradient<TU, T, T, M27>), dim3(gb), dim3(256), 0, st, (const cx<TU>*)ug, ug_off,  \
-                     (const cx<T>*)V, np, g->n[0], g->n[1], g->n[2], (const double*)d_w, mw[0], mw[1], mw[2], \
-                     mw[3], (T*)grad, acc)
-  if (ug64) {
+  mw[0] = m27 ? g->w27[3] : 1.0;
+  mw[1] = m27 ? g->w27[4] : 0.0;
+  mw[2] = m27 ? g->w27[5] : 0.0;
+  mw[3] = m27 ? g->w27[6] : 0.0;
+}
+
+// g (+)= sum_p Re(wg_p conj(u_p) (A v_p)) over the pairs (v contiguous per pair)
+template <typename T>
+void launch_gradient(const helm_grid* g, const Pairs<T>& P, const FieldRef& u, const helm::cx<T>* v, void* grad,
+                     bool acc, hipStream_t st) {
+  using namespace helm;
+  const unsigned gb = std::min<unsigned>(4096, ceil_div(P.N, 256));
+  double mw[4];
+  mass_weights(g, mw);
+  const bool m27 = g->stencil == HELM_27PT;
+#define HELM_GRAD(TU, M27)                                                                                    \
+  hipLaunchKernelGGL((k_gradient<TU, T, T, M27>), dim3(gb), dim3(256), 0, st, (const cx<TU>*)u.p, u.off, v,   \
+                     P.np, g->n[0], g->n[1], g->n[2], (const double*)P.wg, mw[0], mw[1], mw[2], mw[3], (T*)grad, \
+                     acc)
+  if (u.f64) {
     if (m27) HELM_GRAD(double, true);
     else HELM_GRAD(double, false);
   } else {
@@ -501,6 +465,266 @@ helm_status misfit_gradient_t(helm_ctx* ctx, const helm_grid* g, const void* m, 
     else HELM_GRAD(T, false);
   }
 #undef HELM_GRAD
+  HELM_HIP_CHECK(hipGetLastError());
+}
+
+// out_p = -omega_p^2 A (x_p * dm)  (DHADJ false)  or  -omega_p^2 dm * (A x_p)  (DHADJ true)
+template <typename T, bool DHADJ>
+void launch_born_source(const helm_grid* g, const Pairs<T>& P, const FieldRef& x, const void* dm, helm::cx<T>* out,
+                        hipStream_t st) {
+  using namespace helm;
+  const dim3 grid(std::min<unsigned>(DOT_BLOCKS, ceil_div(P.N, 256)), P.np);
+  double mw[4];
+  mass_weights(g, mw);
+  const bool m27 = g->stencil == HELM_27PT;
+#define HELM_BORN(TX, M27)                                                                                     \
+  hipLaunchKernelGGL((k_born_source<TX, T, M27, DHADJ>), grid, dim3(256), 0, st, (const cx<TX>*)x.p, x.off,    \
+                     (const T*)dm, P.np, g->n[0], g->n[1], g->n[2], (const double*)P.w2, mw[0], mw[1], mw[2],   \
+                     mw[3], out)
+  if (x.f64) {
+    if (m27) HELM_BORN(double, true);
+    else HELM_BORN(double, false);
+  } else {
+    if (m27) HELM_BORN(T, true);
+    else HELM_BORN(T, false);
+  }
+#undef HELM_BORN
+  HELM_HIP_CHECK(hipGetLastError());
+}
+
+// b_p (+)= -P_r^T res[rrow_p] (b zeroed first unless add)
+template <typename T>
+void launch_adjoint_source(const Pairs<T>& P, helm::cx<T>* b, const helm::cx<T>* res, const int64_t* rrow,
+                           bool add, hipStream_t st) {
+  using namespace helm;
+  if (!add)
+    hipLaunchKernelGGL((k_fill_zero<T>), dim3(std::min<unsigned>(65536, ceil_div((int64_t)P.np * P.N, 256))),
+                       dim3(256), 0, st, b, (int64_t)P.np * P.N);
+  if (add)
+    hipLaunchKernelGGL((k_adjoint_source<T, true>), dim3(ceil_div(P.nnode, 256), P.np), dim3(256), 0, st, b, P.N,
+                       (const int64_t*)P.node, (const int*)P.nptr, (const int*)P.nrec_ord, P.nnode, res, P.nrec,
+                       rrow);
+  else
+    hipLaunchKernelGGL((k_adjoint_source<T, false>), dim3(ceil_div(P.nnode, 256), P.np), dim3(256), 0, st, b, P.N,
+                       (const int64_t*)P.node, (const int*)P.nptr, (const int*)P.nrec_ord, P.nnode, res, P.nrec,
+                       rrow);
+  HELM_HIP_CHECK(hipGetLastError());
+}
+
+// Forward fields of the selected pairs: solved from the point sources into U
+// (and copied into u_store when given; its FP64 iterates with u64), or taken
+// from u_store with reuse.  Returns where the solve's FP64 iterates
+// (fwd_fp64, valid until the next solve; null with reuse) and the stored /
+// working fields are.
+template <typename T>
+FieldRef forward_fields(const helm_grid* g, const Pairs<T>& P, helm::Solver<T>& S, helm::cx<T>* Q, helm::cx<T>* U,
+                        void* u_store, bool reuse, bool u64, std::vector<helm::SolveInfo>& inf,
+                        helm_solve_info* info, int& worst, const helm::cx<double>** fwd_fp64, hipStream_t st) {
+  using namespace helm;
+  const int64_t N = P.N;
+  *fwd_fp64 = nullptr;
+  if (reuse) return FieldRef{u_store, P.uoff_store, u64};
+  const double inv_h3 = 1.0 / (g->h * g->h * g->h);
+  hipLaunchKernelGGL((k_point_sources<T>), dim3(std::min<unsigned>(DOT_BLOCKS, ceil_div(N, 256)), P.np), dim3(256),
+                     0, st, Q, N, (const int64_t*)P.src, (const double2*)P.amp, inv_h3);
+  worst = std::max(worst, S.solve(0, Q, U, inf.data()));
+  if (info)
+    for (int p = 0; p < P.np; ++p) to_info(inf[p], info + P.prow[p]);
+  *fwd_fp64 = S.iterate();
+  if (u64) {  // keep the FP64 iterates as the stored fields
+    const unsigned pb = std::min<unsigned>(65536, ceil_div(N, 256));
+    for (int p = 0; p < P.np; ++p)
+      hipLaunchKernelGGL((k_convert<double, double>), dim3(pb), dim3(256), 0, st, S.iterate() + p * N,
+                         (cx<double>*)u_store + P.prow[p] * N, N);
+    return FieldRef{u_store, P.uoff_store, true};
+  }
+  if (u_store && (cx<T>*)u_store != U)
+    for (int p = 0; p < P.np; ++p)
+      HELM_HIP_CHECK(hipMemcpyAsync((cx<T>*)u_store + P.prow[p] * N, U + p * N, N * sizeof(cx<T>),
+                                    hipMemcpyDeviceToDevice, st));
+  return FieldRef{U, P.uoff_int, false};
+}
+
+// sum of the partial sums |r|^2 written by k_sample_residual
+template <typename T>
+double residual_norm2(const Pairs<T>& P, hipStream_t st) {
+  std::vector<double> hpart((size_t)P.np * P.rblk);
+  HELM_HIP_CHECK(hipMemcpyAsync(hpart.data(), P.part, hpart.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HELM_HIP_CHECK(hipStreamSynchronize(st));
+  double fsum = 0.0;
+  for (size_t i = 0; i < hpart.size(); ++i) fsum += hpart[i];
+  return fsum;
+}
+
+// r_p = P_r u_p - d_p from the forward solve's FP64 iterate, or from the
+// given fields (reuse)
+template <typename T>
+void launch_residual(const Pairs<T>& P, const helm::cx<double>* fwd_fp64, const FieldRef& u, const void* d,
+                     hipStream_t st) {
+  using namespace helm;
+  const dim3 grid(P.rblk, P.np);
+  if (fwd_fp64)
+    hipLaunchKernelGGL((k_sample_residual<double, T>), grid, dim3(256), 0, st, fwd_fp64, (const int64_t*)P.uoff_int,
+                       (const int64_t*)P.rec, P.nrec, (const cx<T>*)d, (const int64_t*)P.drow, P.res, P.part);
+  else if (u.f64)
+    hipLaunchKernelGGL((k_sample_residual<double, T>), grid, dim3(256), 0, st, (const cx<double>*)u.p, u.off,
+                       (const int64_t*)P.rec, P.nrec, (const cx<T>*)d, (const int64_t*)P.drow, P.res, P.part);
+  else
+    hipLaunchKernelGGL((k_sample_residual<T, T>), grid, dim3(256), 0, st, (const cx<T>*)u.p, u.off,
+                       (const int64_t*)P.rec, P.nrec, (const cx<T>*)d, (const int64_t*)P.drow, P.res, P.part);
+  HELM_HIP_CHECK(hipGetLastError());
+}
+
+// misfit + gradient over the selected (frequency, source) pairs, element type T
+template <typename T>
+helm_status misfit_gradient_t(helm_ctx* ctx, const helm_grid* g, const void* m, int nfreq, const double* omega,
+                              int nsrc, const int32_t* src_idx, const double* src_amp, const uint8_t* mask,
+                              int nrec, const int32_t* rec_idx, const void* d, double* f, void* grad,
+                              void* u_store, int flags, const helm::SolveOpts& o, helm_solve_info* info,
+                              void* caller) {
+  using namespace helm;
+  hipStream_t st = solve_stream(ctx, caller);
+  const bool fwd_only = (flags & HELM_MG_FORWARD_ONLY) != 0;
+  const bool reuse = (flags & HELM_MG_REUSE_U) != 0;
+  const bool acc = (flags & HELM_MG_ACCUMULATE) != 0;
+  const bool u64 = (flags & HELM_MG_U_FP64) != 0 && sizeof(T) == 4;
+  if (info)
+    for (int k = 0; k < 2 * nfreq * nsrc; ++k) to_info(SolveInfo(), info + k);
+  Pairs<T> P = plan_pairs<T>(ctx, g, m, nfreq, omega, nsrc, src_idx, src_amp, mask, nrec, rec_idx,
+                             (flags & HELM_MG_RENORMALISE) != 0, st);
+  const int64_t N = P.N;
+  if (P.np == 0) {
+    *f = 0.0;
+    if (!fwd_only && !acc) HELM_HIP_CHECK(hipMemsetAsync(grad, 0, (size_t)N * sizeof(T), st));
+    HELM_HIP_CHECK(hipStreamSynchronize(st));
+    return HELM_OK;
+  }
+  const int np = P.np;
+  // Device scratch: Q (sources, then adjoint sources), V, and U unless the
+  // solve writes the caller's u_store directly (every pair selected, fields
+  // stored in the dtype).
+  const size_t fbytes = (size_t)np * N * sizeof(cx<T>);
+  const bool direct_u = u_store && !u64 && np == P.nall;
+  const bool own_u = !reuse && !direct_u;
+  ctx->fwi_buf.ensure(fbytes * (own_u ? 3 : 2));
+  char* base = (char*)ctx->fwi_buf.p;
+  cx<T>* Q = (cx<T>*)base;
+  cx<T>* V = (cx<T>*)(base + fbytes);
+  cx<T>* U = direct_u ? (cx<T>*)u_store : own_u ? (cx<T>*)(base + 2 * fbytes) : nullptr;
+
+  Solver<T>& S = solver_for<T>(ctx, P.probs, o, st);
+  std::vector<SolveInfo> inf(np);
+  int worst = 0;
+  const cx<double>* fwd64 = nullptr;
+  const FieldRef uf = forward_fields<T>(g, P, S, Q, U, u_store, reuse, u64, inf, info, worst, &fwd64, st);
+  launch_residual<T>(P, fwd64, uf, d, st);
+  *f = 0.5 * residual_norm2<T>(P, st) * P.scale;
+  if (fwd_only) return (helm_status)worst;
+  // adjoint sources b_p = -P_r^T r_p, then H^H v_p = b_p
+  launch_adjoint_source<T>(P, Q, P.res, nullptr, false, st);
+  worst = std::max(worst, S.solve(1, Q, V, inf.data()));
+  if (info)
+    for (int p = 0; p < np; ++p) to_info(inf[p], info + P.nall + P.prow[p]);
+  launch_gradient<T>(g, P, uf, V, grad, acc, st);
+  HELM_HIP_CHECK(hipStreamSynchronize(st));
+  return (helm_status)worst;
+}
+
+// Linearised products over the selected (frequency, source) pairs (the
+// PDEfunc modes JACOB_FORW, JACOB_ADJ, HESS_GN, HESS), element type T.
+// Solves of pair p, in order, with their info rows (k * nall + row):
+//   forward fields u (k = 0; absent with REUSE_U), then
+//   JACOB_FORW: du = -H^{-1} T dm (1);            out = P_r du
+//   JACOB_ADJ:  v  = -H^{-H} P_r^T y (1);          out = sum Re(T^* v)
+//   HESS_GN:    du (1), w = -H^{-H} P_r^T P_r du (2); out = sum Re(T^* w)
+//   HESS:       v = -H^{-H} P_r^T r (1), du (2),
+//               dv = H^{-H}(-omega^2 dm (A v) - P_r^T P_r du) (3);
+//               out = sum Re(omega^2 conj(du) (A v)) + Re(T^* dv)
+template <typename T>
+helm_status derivative_t(helm_ctx* ctx, int mode, const helm_grid* g, const void* m, int nfreq, const double* omega,
+                         int nsrc, const int32_t* src_idx, const double* src_amp, const uint8_t* mask, int nrec,
+                         const int32_t* rec_idx, const void* in, const void* d, void* out, void* u_store, int flags,
+                         const helm::SolveOpts& o, helm_solve_info* info, void* caller) {
+  using namespace helm;
+  hipStream_t st = solve_stream(ctx, caller);
+  const bool reuse = (flags & HELM_MG_REUSE_U) != 0;
+  const bool acc = (flags & HELM_MG_ACCUMULATE) != 0;
+  const bool u64 = (flags & HELM_MG_U_FP64) != 0 && sizeof(T) == 4;
+  const int nall = nfreq * nsrc;
+  if (info)
+    for (int k = 0; k < 4 * nall; ++k) to_info(SolveInfo(), info + k);
+  Pairs<T> P = plan_pairs<T>(ctx, g, m, nfreq, omega, nsrc, src_idx, src_amp, mask, nrec, rec_idx,
+                             (flags & HELM_MG_RENORMALISE) != 0, st);
+  const int64_t N = P.N;
+  const int np = P.np;
+  if (mode == HELM_JACOB_FORW)  // rows of unselected pairs are zero
+    hipLaunchKernelGGL((k_fill_zero<T>), dim3(std::min<unsigned>(65536, ceil_div((int64_t)nall * nrec, 256))),
+                       dim3(256), 0, st, (cx<T>*)out, (int64_t)nall * nrec);
+  else if (!acc)
+    hipLaunchKernelGGL((k_fill_zero_real<T>), dim3(std::min<unsigned>(65536, ceil_div(N, 256))), dim3(256), 0, st,
+                       (T*)out, N);
+  HELM_HIP_CHECK(hipGetLastError());
+  if (np == 0) {
+    HELM_HIP_CHECK(hipStreamSynchronize(st));
+    return HELM_OK;
+  }
+  // work vectors: Q (right-hand sides), U (forward fields unless reused),
+  // B1, B2, B3 (the linearised fields)
+  const size_t fbytes = (size_t)np * N * sizeof(cx<T>);
+  const int nwork = mode == HELM_HESS ? 4 : mode == HELM_HESS_GN ? 3 : 2;
+  ctx->fwi_buf.ensure(fbytes * (nwork + (reuse ? 0 : 1)));
+  char* base = (char*)ctx->fwi_buf.p;
+  cx<T>* Q = (cx<T>*)base;
+  cx<T>* B[3] = {(cx<T>*)(base + fbytes), nwork > 2 ? (cx<T>*)(base + 2 * fbytes) : nullptr,
+                 nwork > 3 ? (cx<T>*)(base + 3 * fbytes) : nullptr};
+  cx<T>* U = reuse ? nullptr : (cx<T>*)(base + (size_t)nwork * fbytes);
+
+  Solver<T>& S = solver_for<T>(ctx, P.probs, o, st);
+  std::vector<SolveInfo> inf(np);
+  int worst = 0, k = 1;
+  auto solve = [&](int dir, cx<T>* rhs, cx<T>* x) {
+    worst = std::max(worst, S.solve(dir, rhs, x, inf.data()));
+    if (info)
+      for (int p = 0; p < np; ++p) to_info(inf[p], info + (size_t)k * nall + P.prow[p]);
+    ++k;
+  };
+  const cx<double>* fwd64 = nullptr;
+  const FieldRef uf = forward_fields<T>(g, P, S, Q, U, u_store, reuse, u64, inf, info, worst, &fwd64, st);
+  const FieldRef b0{B[0], P.uoff_int, false};
+  const dim3 sgrid(P.rblk, np);
+  if (mode == HELM_JACOB_FORW || mode == HELM_HESS_GN) {
+    launch_born_source<T, false>(g, P, uf, in, Q, st);  // -T dm
+    solve(0, Q, B[0]);                                  // du
+    if (mode == HELM_JACOB_FORW) {
+      hipLaunchKernelGGL((k_sample<double, T>), sgrid, dim3(256), 0, st, S.iterate(), (const int64_t*)P.uoff_int,
+                         (const int64_t*)P.rec, nrec, (cx<T>*)out, (const int64_t*)P.drow);
+    } else {
+      hipLaunchKernelGGL((k_sample<double, T>), sgrid, dim3(256), 0, st, S.iterate(), (const int64_t*)P.uoff_int,
+                         (const int64_t*)P.rec, nrec, P.res, (const int64_t*)P.ident);
+      HELM_HIP_CHECK(hipGetLastError());
+      launch_adjoint_source<T>(P, Q, P.res, nullptr, false, st);  // -P_r^T P_r du
+      solve(1, Q, B[1]);                                            // w
+      launch_gradient<T>(g, P, uf, B[1], out, true, st);
+    }
+  } else if (mode == HELM_JACOB_ADJ) {
+    launch_adjoint_source<T>(P, Q, (const cx<T>*)in, P.drow, false, st);  // -P_r^T y
+    solve(1, Q, B[0]);                                                    // v
+    launch_gradient<T>(g, P, uf, B[0], out, true, st);
+  } else {  // HESS
+    launch_residual<T>(P, fwd64, uf, d, st);                 // r
+    launch_adjoint_source<T>(P, Q, P.res, nullptr, false, st);
+    solve(1, Q, B[0]);                                         // v
+    launch_born_source<T, false>(g, P, uf, in, Q, st);         // -T dm
+    solve(0, Q, B[1]);                                         // du
+    hipLaunchKernelGGL((k_sample<double, T>), sgrid, dim3(256), 0, st, S.iterate(), (const int64_t*)P.uoff_int,
+                       (const int64_t*)P.rec, nrec, P.res, (const int64_t*)P.ident);
+    HELM_HIP_CHECK(hipGetLastError());
+    launch_born_source<T, true>(g, P, b0, in, Q, st);          // -omega^2 dm (A v)
+    launch_adjoint_source<T>(P, Q, P.res, nullptr, true, st);  // - P_r^T P_r du
+    solve(1, Q, B[2]);                                         // dv
+    launch_gradient<T>(g, P, FieldRef{B[1], P.uoff_int, false}, B[0], out, true, st);
+    launch_gradient<T>(g, P, uf, B[2], out, true, st);
+  }
   HELM_HIP_CHECK(hipGetLastError());
   HELM_HIP_CHECK(hipStreamSynchronize(st));
   return (helm_status)worst;
@@ -705,6 +929,43 @@ helm_status misfit_gradient(helm_ctx* ctx, const helm_grid* g, const void* m, in
                                       grad, u_store, flags, so, info, stream);
     return misfit_gradient_t<double>(ctx, g, m, nfreq, omega, nsrc, src_idx, src_amp, mask, nrec, rec_idx, d, f,
                                      grad, u_store, flags, so, info, stream);
+  });
+}
+
+helm_status pde_derivative(helm_ctx* ctx, int mode, const helm_grid* g, const void* m, int nfreq,
+                           const double* omega, int nsrc, const int32_t* src_idx, const double* src_amp,
+                           const uint8_t* mask, int nrec, const int32_t* rec_idx, const void* input, const void* d,
+                           void* output, void* u_store, int flags, const helm_solver_opts* o, helm_solve_info* info,
+                           void* stream) {
+  return guarded(ctx, [&]() -> helm_status {
+    check_grid(g);
+    HELM_REQUIRE(mode == HELM_JACOB_FORW || mode == HELM_JACOB_ADJ || mode == HELM_HESS_GN || mode == HELM_HESS,
+                 "unknown derivative mode");
+    HELM_REQUIRE(m && input && output, "null pointer argument");
+    HELM_REQUIRE(mode != HELM_HESS || d, "HELM_HESS needs the observed data d");
+    HELM_REQUIRE(nfreq >= 1 && omega, "nfreq must be >= 1 with an omega array");
+    for (int k = 0; k < nfreq; ++k)
+      HELM_REQUIRE(omega[k] > 0.0 && std::isfinite(omega[k]), "omega must be positive");
+    HELM_REQUIRE(nsrc >= 1 && nrec >= 1, "nsrc and nrec must be >= 1");
+    HELM_REQUIRE((int64_t)nfreq * nsrc <= (1 << 20), "too many (frequency, source) pairs");
+    HELM_REQUIRE(src_idx && rec_idx, "null source / receiver index array");
+    HELM_REQUIRE(!(flags & HELM_MG_REUSE_U) || u_store, "HELM_MG_REUSE_U needs u_store");
+    HELM_REQUIRE(!(flags & HELM_MG_U_FP64) || u_store, "HELM_MG_U_FP64 needs u_store");
+    HELM_REQUIRE((flags & ~(HELM_MG_REUSE_U | HELM_MG_ACCUMULATE | HELM_MG_U_FP64 | HELM_MG_RENORMALISE)) == 0,
+                 "unknown or unsupported flag bits");
+    for (int s = 0; s < nsrc; ++s)
+      for (int a = 0; a < 3; ++a)
+        HELM_REQUIRE(src_idx[3 * s + a] >= 0 && src_idx[3 * s + a] < g->n[a], "source outside the grid");
+    for (int k = 0; k < nrec; ++k)
+      for (int a = 0; a < 3; ++a)
+        HELM_REQUIRE(rec_idx[3 * k + a] >= 0 && rec_idx[3 * k + a] < g->n[a], "receiver outside the grid");
+    const helm::SolveOpts so = opts_of(o);
+    check_coarse_sizes(g, so);
+    if (g->dtype == HELM_C64)
+      return derivative_t<float>(ctx, mode, g, m, nfreq, omega, nsrc, src_idx, src_amp, mask, nrec, rec_idx, input,
+                                 d, output, u_store, flags, so, info, stream);
+    return derivative_t<double>(ctx, mode, g, m, nfreq, omega, nsrc, src_idx, src_amp, mask, nrec, rec_idx, input,
+                                d, output, u_store, flags, so, info, stream);
   });
 }
 

@@ -35,3 +35,25 @@ def test_traffic_is_tied_to_the_stencil_sources():
     text = open(bench.TRAFFIC_FILE).read()
     recorded = re.search(r'"stencil_source_sha256": "([0-9a-f]{64})"', text).group(1)
     assert (t is not None) == (recorded == digest)
+
+
+def test_host_pool_helpers():
+    """The host-side pools: worker count within one GPU's share of the host,
+    the uneven-draw members built in spawned workers equal the ones built
+    here, and one oracle step on a small grid runs in a worker."""
+    import numpy as np
+    import bench
+    import workloads
+    assert 1 <= bench._pool_workers() <= 16
+    assert isinstance(bench.cpu_model(), str) and bench.cpu_model()
+    params = [dict(n=(20, 22, 18), freq=5.0, h=37.5, npml=3, seed=11),
+              dict(n=(17, 19, 21), freq=6.0, h=31.25, npml=3, seed=12)]
+    got = bench.c4_members(params)
+    for p, (n, h, npml, vref, omega, src, m32) in zip(params, got):
+        w = workloads.c4_problem(p)
+        assert n == tuple(w.n) and h == w.h and npml == w.npml and omega == w.omega
+        assert src == tuple(int(v) for v in w.src[0])
+        assert np.array_equal(m32, w.m.astype(np.float32))
+    w = workloads.c4_problem(params[0])
+    dt, setup = bench._oracle_step((tuple(w.n), w.h, w.npml, w.omega, w.v_ref, w.m, tuple(w.src[0])))
+    assert dt > 0 and setup > 0
