@@ -47,6 +47,12 @@ W27_DEFAULT = (
     1.4904158307892655e-12,
 )
 
+# Off-grid source / receiver interpolation: Kaiser-windowed sinc of half-width
+# 4 nodes with window shape b, as printed by ``python -m oracle.fit_kaiser``
+# (spectral error below 0.9 % up to three points per wavelength).
+SINC_RADIUS = 4
+SINC_KAISER_B = 4.058383564340161
+
 
 @dataclass
 class Workload:
