@@ -279,6 +279,33 @@ helm_status misfit_gradient(helm_ctx* ctx, const helm_grid* g, const void* m,
                             const helm_solver_opts* o, helm_solve_info* info,
                             void* stream);
 
+/* misfit_gradient with sources and receivers anywhere inside the grid (the
+ * paper's Kaiser-windowed sinc interpolation operators Ps and Pr: Software
+ * Design section and the PDEfunc listing).  Same arguments and results as
+ * misfit_gradient, except:
+ *   src_pos  host double [nsrc][3], rec_pos host double [nrec][3]: positions
+ *            in node units (node (i, j, k) sits at (i, j, k)), each inside
+ *            [0, n_a - 1]
+ *   radius   half-width r of the windowed sinc in nodes (1..8)
+ *   kaiser_b shape b of the Kaiser window (>= 0)
+ * A point at x contributes, per axis, w(i) = sinc(i - x) I0(b sqrt(1 - ((i -
+ * x)/r)^2)) / I0(b) to the 2r nodes floor(x) - r + 1 .. floor(x) + r that lie
+ * inside the grid; the 3D weights are the product of the axes.  The source
+ * is q = amp sum_n w_n e_n / h^3, the receiver value (P_r u)_k = sum_n w_{k,n}
+ * u_n; an on-node position reduces to misfit_gradient's point source and
+ * sampling.  Out-of-range positions, radius or b return HELM_E_INVAL. */
+helm_status misfit_gradient_offgrid(helm_ctx* ctx, const helm_grid* g,
+                                    const void* m, int nfreq,
+                                    const double* omega, int nsrc,
+                                    const double* src_pos,
+                                    const double* src_amp,
+                                    const uint8_t* mask, int nrec,
+                                    const double* rec_pos, int radius,
+                                    double kaiser_b, const void* d, double* f,
+                                    void* grad, void* u_store, int flags,
+                                    const helm_solver_opts* o,
+                                    helm_solve_info* info, void* stream);
+
 /* pde_derivative modes (the paper's PDEfunc cases of the same names) */
 #define HELM_JACOB_FORW 1 /* output = J dm                       */
 #define HELM_JACOB_ADJ 2  /* output = J^* y                      */
@@ -331,6 +358,21 @@ helm_status pde_derivative(helm_ctx* ctx, int mode, const helm_grid* g,
                            const void* d, void* output, void* u_store,
                            int flags, const helm_solver_opts* o,
                            helm_solve_info* info, void* stream);
+
+/* pde_derivative with off-grid sources and receivers: the arguments of
+ * pde_derivative with src_idx / rec_idx replaced by src_pos / rec_pos,
+ * radius and kaiser_b as in misfit_gradient_offgrid. */
+helm_status pde_derivative_offgrid(helm_ctx* ctx, int mode,
+                                   const helm_grid* g, const void* m,
+                                   int nfreq, const double* omega, int nsrc,
+                                   const double* src_pos,
+                                   const double* src_amp, const uint8_t* mask,
+                                   int nrec, const double* rec_pos,
+                                   int radius, double kaiser_b,
+                                   const void* input, const void* d,
+                                   void* output, void* u_store, int flags,
+                                   const helm_solver_opts* o,
+                                   helm_solve_info* info, void* stream);
 
 #ifdef __cplusplus
 }

@@ -48,7 +48,7 @@ STATUS_NAMES = {
 EXPORTS = ("helm_create", "helm_destroy", "helm_last_error", "helm_version",
            "helm_default_opts", "helm_workspace_bytes", "helm_apply",
            "helm_apply_noalloc", "helm_solve", "helm_solve_batched", "misfit_gradient",
-           "pde_derivative")
+           "misfit_gradient_offgrid", "pde_derivative", "pde_derivative_offgrid")
 
 
 class helm_grid(C.Structure):
@@ -113,8 +113,14 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                                    C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                    C.POINTER(C.c_uint8), i32, C.POINTER(C.c_int32), vp, vp,
                                    vp, vp, i32, O, I, vp]
+    D = C.POINTER(C.c_double)
+    lib.misfit_gradient_offgrid.argtypes = [vp, G, vp, i32, D, i32, D, D, C.POINTER(C.c_uint8), i32, D,
+                                            i32, dbl, vp, D, vp, vp, i32, O, I, vp]
+    lib.pde_derivative_offgrid.argtypes = [vp, i32, G, vp, i32, D, i32, D, D, C.POINTER(C.c_uint8), i32, D,
+                                           i32, dbl, vp, vp, vp, vp, i32, O, I, vp]
     for name in ("helm_create", "helm_destroy", "helm_apply", "helm_apply_noalloc", "helm_solve",
-                 "helm_solve_batched", "misfit_gradient", "pde_derivative"):
+                 "helm_solve_batched", "misfit_gradient", "misfit_gradient_offgrid", "pde_derivative",
+                 "pde_derivative_offgrid"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib

@@ -239,8 +239,21 @@ def _idx_array(pos):
     return np.ascontiguousarray(np.asarray(pos, dtype=np.int32).reshape(-1, 3))
 
 
+def _points(src, rec, sinc):
+    """Host arrays of the source and receiver geometry: on-node int32 indices
+    (sinc None), or float64 positions in node units for the windowed-sinc
+    entry points (sinc = (radius, kaiser_b))."""
+    if sinc is None:
+        for name, a in (("src", src), ("rec", rec)):
+            if not np.issubdtype(np.asarray(a).dtype, np.integer):
+                raise ValueError(f"{name}: off-grid positions need sinc=(radius, kaiser_b)")
+        return _idx_array(src), _idx_array(rec), C.POINTER(C.c_int32)
+    conv = lambda a: np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(-1, 3))
+    return conv(src), conv(rec), C.POINTER(C.c_double)
+
+
 def misfit_gradient(grid: Grid, m: torch.Tensor, omega, src, rec, d: torch.Tensor,
-                    src_amp=None, mask=None, grad: Optional[torch.Tensor] = None,
+                    src_amp=None, mask=None, grad: Optional[torch.Tensor] = None, sinc=None,
                     u_store: Optional[torch.Tensor] = None, forward_only: bool = False,
                     reuse_u: bool = False, accumulate: bool = False, u_fp64: bool = False,
                     renormalise: bool = False, opts: Optional[SolverOpts] = None,
@@ -257,14 +270,16 @@ def misfit_gradient(grid: Grid, m: torch.Tensor, omega, src, rec, d: torch.Tenso
     with u_fp64 it is complex128 (the FP64 outer iterates).  renormalise
     divides f and g by the number of selected pairs.  Returns (f, grad,
     infos): infos per pair, forward solves then adjoint solves (only those
-    that ran), [frequency][source] order, zero entries for unselected pairs."""
+    that ran), [frequency][source] order, zero entries for unselected pairs.
+    sinc=(radius, kaiser_b): src / rec are positions in node units anywhere
+    inside the grid, interpolated by Kaiser-windowed sincs
+    (misfit_gradient_offgrid)."""
     if (u_fp64 or reuse_u) and u_store is None:
         raise ValueError("u_fp64 and reuse_u need u_store")
     dev = m.device.index or 0
     om = np.ascontiguousarray(np.atleast_1d(np.asarray(omega, dtype=np.float64)).ravel())
     nfreq = len(om)
-    src_a = _idx_array(src)
-    rec_a = _idx_array(rec)
+    src_a, rec_a, PT = _points(src, rec, sinc)
     nsrc, nrec = len(src_a), len(rec_a)
     amp_p = None
     if src_amp is not None:
@@ -288,11 +303,13 @@ def misfit_gradient(grid: Grid, m: torch.Tensor, omega, src, rec, d: torch.Tenso
     f = C.c_double(0.0)
     ctx = _context(dev)
     g, o = grid.c_struct(), opts.c_struct()
-    st = L.load().misfit_gradient(
+    geo = (nrec, rec_a.ctypes.data_as(PT)) if sinc is None else \
+        (nrec, rec_a.ctypes.data_as(PT), int(sinc[0]), float(sinc[1]))
+    fn = L.load().misfit_gradient if sinc is None else L.load().misfit_gradient_offgrid
+    st = fn(
         ctx, C.byref(g), _dev_tensor(m, grid.real_dtype, grid.N, "m"), nfreq,
         om.ctypes.data_as(C.POINTER(C.c_double)), nsrc,
-        src_a.ctypes.data_as(C.POINTER(C.c_int32)), amp_p, mask_p, nrec,
-        rec_a.ctypes.data_as(C.POINTER(C.c_int32)),
+        src_a.ctypes.data_as(PT), amp_p, mask_p, *geo,
         _dev_tensor(d, grid.complex_dtype, npair * nrec, "d"), C.byref(f),
         None if grad is None else _dev_tensor(grad, grid.real_dtype, grid.N, "grad"),
         None if u_store is None else _dev_tensor(u_store, u_dtype, npair * grid.N, "u_store"),
@@ -315,7 +332,7 @@ def pde_derivative(mode: str, grid: Grid, m: torch.Tensor, omega, src, rec, inpu
                    out: Optional[torch.Tensor] = None, u_store: Optional[torch.Tensor] = None,
                    reuse_u: bool = False, u_fp64: bool = False, accumulate: bool = False,
                    renormalise: bool = False, opts: Optional[SolverOpts] = None,
-                   raise_on_failure: bool = True):
+                   raise_on_failure: bool = True, sinc=None):
     """Linearised products over the selected (frequency, source) pairs.
 
     mode: "jacobian" (J dm -> [nfreq][nsrc][nrec] complex), "jacobian_adjoint"
@@ -334,8 +351,7 @@ def pde_derivative(mode: str, grid: Grid, m: torch.Tensor, omega, src, rec, inpu
     dev = m.device.index or 0
     om = np.ascontiguousarray(np.atleast_1d(np.asarray(omega, dtype=np.float64)).ravel())
     nfreq = len(om)
-    src_a = _idx_array(src)
-    rec_a = _idx_array(rec)
+    src_a, rec_a, PT = _points(src, rec, sinc)
     nsrc, nrec = len(src_a), len(rec_a)
     npair = nfreq * nsrc
     amp_p = None
@@ -365,11 +381,13 @@ def pde_derivative(mode: str, grid: Grid, m: torch.Tensor, omega, src, rec, inpu
     infos = (L.helm_solve_info * (4 * npair))()
     ctx = _context(dev)
     g, o = grid.c_struct(), opts.c_struct()
-    st = L.load().pde_derivative(
+    geo = (nrec, rec_a.ctypes.data_as(PT)) if sinc is None else \
+        (nrec, rec_a.ctypes.data_as(PT), int(sinc[0]), float(sinc[1]))
+    fn = L.load().pde_derivative if sinc is None else L.load().pde_derivative_offgrid
+    st = fn(
         ctx, md, C.byref(g), _dev_tensor(m, grid.real_dtype, grid.N, "m"), nfreq,
         om.ctypes.data_as(C.POINTER(C.c_double)), nsrc,
-        src_a.ctypes.data_as(C.POINTER(C.c_int32)), amp_p, mask_p, nrec,
-        rec_a.ctypes.data_as(C.POINTER(C.c_int32)), in_p,
+        src_a.ctypes.data_as(PT), amp_p, mask_p, *geo, in_p,
         None if d is None else _dev_tensor(d, grid.complex_dtype, npair * nrec, "d"), out_p,
         None if u_store is None else _dev_tensor(u_store, u_dtype, npair * grid.N, "u_store"),
         flags, C.byref(o), infos, _stream(dev))

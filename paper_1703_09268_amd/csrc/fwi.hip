@@ -2,7 +2,8 @@
 // PDEfunc cases OBJ, JACOB_FORW, JACOB_ADJ, HESS_GN, HESS; Table derivstuff;
 // Appendix A eqs. dH, dHadj, DTadj), over a list of (frequency, source)
 // pairs solved together:
-//   q_p = amp_p e_{src_p} / h^3                   (on-node point source)
+//   q_p = amp_p P_s^T 1 / h^3                     (point source: on a node, or
+//                                                   the windowed sinc around it)
 //   r_p = P_r u_p - d_p,  f = 1/2 sum_p ||r_p||^2  (FP64 accumulation)
 //   b_p = -P_r^T r_p                               (adjoint source)
 //   g   = sum_p Re(w_p conj(u_p) (A^H v_p))        (gradient w.r.t. real m,
@@ -18,21 +19,29 @@
 
 namespace helm {
 
-// q[s][p] = 0 except q[s][src_s] = amp_s / h^3  (s: pair)
+// Sources and receivers are weighted node lists (CSR): entry e of point k is
+// node lin[e] with weight w[e], e in [ptr[k], ptr[k+1]).  An on-node point is
+// one entry of weight 1; an off-grid point the windowed-sinc stencil around
+// it (nodes inside the grid only).
+
+// q[s] += amp_s w_e / h^3 at the nodes of pair s's source (q zeroed before;
+// the nodes of one source are distinct).  Grid: (entry blocks, pairs).
 template <typename T>
 __global__ __launch_bounds__(256) void k_point_sources(cx<T>* __restrict__ q, int64_t N,
-                                                       const int64_t* __restrict__ src_lin,
+                                                       const int* __restrict__ src_of_pair,
+                                                       const int* __restrict__ ptr, const int64_t* __restrict__ lin,
+                                                       const double* __restrict__ w,
                                                        const double2* __restrict__ amp, double inv_h3) {
   const int s = blockIdx.y;
-  const int64_t stride = (int64_t)gridDim.x * 256;
-  const int64_t ps = src_lin[s];
+  const int k = src_of_pair[s];
   const double2 a = amp[s];
-  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < N; p += stride) {
-    q[s * N + p] = (p == ps) ? mk<T>((T)(a.x * inv_h3), (T)(a.y * inv_h3)) : czero<T>();
+  for (int e = ptr[k] + blockIdx.x * 256 + threadIdx.x; e < ptr[k + 1]; e += gridDim.x * 256) {
+    const double c = w[e] * inv_h3;
+    q[s * N + lin[e]] = mk<T>((T)(a.x * c), (T)(a.y * c));
   }
 }
 
-// r[s][k] = u[uoff_s + rec_k] - d[drow_s][k] (s: pair); per-workgroup
+// r[s][k] = (P_r u_s)_k - d[drow_s][k] (s: pair); per-workgroup
 // partial sum of |r|^2 in part[s * gridDim.x + blk] (FP64).  u may be the
 // FP64 outer iterate of the solve (TU = double): the residual is a small
 // difference of two fields, so it is formed before the fields are rounded to
@@ -40,7 +49,9 @@ __global__ __launch_bounds__(256) void k_point_sources(cx<T>* __restrict__ q, in
 template <typename TU, typename T>
 __global__ __launch_bounds__(256) void k_sample_residual(const cx<TU>* __restrict__ u,
                                                          const int64_t* __restrict__ uoff,
-                                                         const int64_t* __restrict__ rec_lin, int nrec,
+                                                         const int* __restrict__ rptr,
+                                                         const int64_t* __restrict__ rlin,
+                                                         const double* __restrict__ rw, int nrec,
                                                          const cx<T>* __restrict__ d,
                                                          const int64_t* __restrict__ drow,
                                                          cx<T>* __restrict__ res, double* __restrict__ part) {
@@ -49,9 +60,11 @@ __global__ __launch_bounds__(256) void k_sample_residual(const cx<TU>* __restric
   const int k = blockIdx.x * 256 + threadIdx.x;
   double acc = 0.0;
   if (k < nrec) {
-    const cx<TU> uv = u[uoff[s] + rec_lin[k]];
+    cx<double> uv = czero<double>();
+    const cx<TU>* us = u + uoff[s];
+    for (int e = rptr[k]; e < rptr[k + 1]; ++e) uv = uv + rw[e] * cast<double>(us[rlin[e]]);
     const cx<T> dv = d[drow[s] * nrec + k];
-    const cx<double> rr = mk<double>((double)uv.re - (double)dv.re, (double)uv.im - (double)dv.im);
+    const cx<double> rr = mk<double>(uv.re - (double)dv.re, uv.im - (double)dv.im);
     res[(int64_t)s * nrec + k] = cast<T>(rr);
     acc = rr.re * rr.re + rr.im * rr.im;
   }
@@ -59,15 +72,16 @@ __global__ __launch_bounds__(256) void k_sample_residual(const cx<TU>* __restric
   if (threadIdx.x == 0) part[(int64_t)s * gridDim.x + blockIdx.x] = t;
 }
 
-// b[s] (+)= -P_r^T r[rrow_s]: one lane per distinct receiver node, summing
-// that node's receivers (node_ptr/node_rec: CSR over distinct nodes,
-// ascending).  rrow (row of pair s in r; null: row s).  Without ADD, b must
+// b[s] (+)= -P_r^T r[rrow_s]: one lane per distinct node any receiver
+// touches, summing that node's (receiver, weight) entries in a fixed order
+// (node_ptr / node_rec / node_w: CSR over distinct nodes, ascending).  rrow (row of pair s in r; null: row s).  Without ADD, b must
 // be zero beforehand.
 template <typename T, bool ADD = false>
 __global__ __launch_bounds__(256) void k_adjoint_source(cx<T>* __restrict__ b, int64_t N,
                                                         const int64_t* __restrict__ node_lin,
                                                         const int* __restrict__ node_ptr,
-                                                        const int* __restrict__ node_rec, int nnode,
+                                                        const int* __restrict__ node_rec,
+                                                        const double* __restrict__ node_w, int nnode,
                                                         const cx<T>* __restrict__ res, int nrec,
                                                         const int64_t* __restrict__ rrow = nullptr) {
   const int s = blockIdx.y;
@@ -76,21 +90,26 @@ __global__ __launch_bounds__(256) void k_adjoint_source(cx<T>* __restrict__ b, i
   const int64_t row = rrow ? rrow[s] : s;
   cx<double> acc = czero<double>();
   for (int e = node_ptr[q]; e < node_ptr[q + 1]; ++e)
-    acc = acc + cast<double>(res[row * nrec + node_rec[e]]);
+    acc = acc + node_w[e] * cast<double>(res[row * nrec + node_rec[e]]);
   cx<T>* dst = b + s * N + node_lin[q];
   if (ADD) acc = mk<double>(acc.re - (double)dst->re, acc.im - (double)dst->im);
   *dst = cast<T>(mk<double>(-acc.re, -acc.im));
 }
 
-// out[orow_s][k] = u[uoff_s + rec_k]: receiver sampling P_r of pair s's field
-// (u may be an FP64 outer iterate).
+// out[orow_s][k] = (P_r u_s)_k: receiver sampling of pair s's field (u may be
+// an FP64 outer iterate).
 template <typename TU, typename T>
 __global__ __launch_bounds__(256) void k_sample(const cx<TU>* __restrict__ u, const int64_t* __restrict__ uoff,
-                                                const int64_t* __restrict__ rec_lin, int nrec,
+                                                const int* __restrict__ rptr, const int64_t* __restrict__ rlin,
+                                                const double* __restrict__ rw, int nrec,
                                                 cx<T>* __restrict__ out, const int64_t* __restrict__ orow) {
   const int s = blockIdx.y;
   const int k = blockIdx.x * 256 + threadIdx.x;
-  if (k < nrec) out[orow[s] * nrec + k] = cast<T>(u[uoff[s] + rec_lin[k]]);
+  if (k >= nrec) return;
+  cx<double> uv = czero<double>();
+  const cx<TU>* us = u + uoff[s];
+  for (int e = rptr[k]; e < rptr[k + 1]; ++e) uv = uv + rw[e] * cast<double>(us[rlin[e]]);
+  out[orow[s] * nrec + k] = cast<T>(uv);
 }
 
 // Right-hand sides of the linearised problems (Appendix A, eqs. dH and the

@@ -303,6 +303,88 @@ helm_status solve_batched_t(helm_ctx* ctx, int nprob, const helm_problem* probs,
   return (helm_status)worst;
 }
 
+// Sources or receivers as weighted node lists (CSR over the points): point k
+// is sum_e w[e] e_{lin[e]}, e in [ptr[k], ptr[k+1]).
+struct PointSet {
+  std::vector<int> ptr{0};
+  std::vector<int64_t> lin;
+  std::vector<double> w;
+  int n() const { return (int)ptr.size() - 1; }
+};
+
+PointSet on_node_points(const helm_grid* g, int n, const int32_t* idx) {
+  PointSet P;
+  const int64_t plane = (int64_t)g->n[1] * g->n[2];
+  for (int k = 0; k < n; ++k) {
+    P.lin.push_back((int64_t)idx[3 * k] * plane + (int64_t)idx[3 * k + 1] * g->n[2] + idx[3 * k + 2]);
+    P.w.push_back(1.0);
+    P.ptr.push_back((int)P.lin.size());
+  }
+  return P;
+}
+
+// Modified Bessel function I0 by its power series sum_k ((x/2)^k / k!)^2.
+double bessel_i0(double x) {
+  const double q = 0.25 * x * x;
+  double sum = 1.0, term = 1.0;
+  for (int k = 1; k < 1000; ++k) {
+    term *= q / ((double)k * (double)k);
+    sum += term;
+    if (term <= 1e-17 * sum) break;
+  }
+  return sum;
+}
+
+// sin(pi t) / (pi t), exactly zero at nonzero integers: sin(pi t) is taken
+// as (-1)^n sin(pi (t - n)) with n the nearest integer.
+double sinc_pi(double t) {
+  if (t == 0.0) return 1.0;
+  const double n = std::nearbyint(t);
+  double sn = std::sin(M_PI * (t - n));
+  if (std::fmod(n, 2.0) != 0.0) sn = -sn;
+  return sn / (M_PI * t);
+}
+
+// Kaiser-windowed sinc interpolation (the paper's source and receiver
+// operators, Software Design section): per axis, for position x in node
+// units, w(i) = sinc(i - x) I0(b sqrt(1 - ((i - x)/r)^2)) / I0(b) over the 2r
+// nodes floor(x) - r + 1 .. floor(x) + r inside the grid; the 3D weights
+// are the tensor product.  Zero weights (all but one node of an on-node
+// position) are left out.
+PointSet sinc_points(const helm_grid* g, int n, const double* pos, int radius, double kb) {
+  PointSet P;
+  const double i0b = bessel_i0(kb);
+  std::vector<int64_t> node[3];
+  std::vector<double> wt[3];
+  for (int k = 0; k < n; ++k) {
+    for (int a = 0; a < 3; ++a) {
+      node[a].clear();
+      wt[a].clear();
+      const double x = pos[3 * k + a];
+      const int64_t base = (int64_t)std::floor(x);
+      for (int64_t i = base - radius + 1; i <= base + radius; ++i) {
+        if (i < 0 || i >= g->n[a]) continue;
+        const double t = (double)i - x;
+        const double u = t / radius;
+        const double win = std::fabs(t) <= radius ? bessel_i0(kb * std::sqrt(std::max(0.0, 1.0 - u * u))) / i0b : 0.0;
+        const double v = sinc_pi(t) * win;
+        if (v != 0.0) {
+          node[a].push_back(i);
+          wt[a].push_back(v);
+        }
+      }
+    }
+    for (size_t ix = 0; ix < node[0].size(); ++ix)
+      for (size_t iy = 0; iy < node[1].size(); ++iy)
+        for (size_t iz = 0; iz < node[2].size(); ++iz) {
+          P.lin.push_back((node[0][ix] * g->n[1] + node[1][iy]) * g->n[2] + node[2][iz]);
+          P.w.push_back(wt[0][ix] * wt[1][iy] * wt[2][iz]);
+        }
+    P.ptr.push_back((int)P.lin.size());
+  }
+  return P;
+}
+
 // The selected (frequency, source) pairs of a misfit or derivative call:
 // host tables, their device copies (in the context's small scratch) and the
 // receiver node lists.  Pair p is row prow[p] = f * nsrc + s of the caller's
@@ -315,9 +397,13 @@ struct Pairs {
   double scale = 1.0;  // 1 / #pairs with HELM_MG_RENORMALISE, else 1
   std::vector<int> prow;
   std::vector<helm::ProblemSpec> probs;
+  int sblk = 1;  // entry blocks of the largest source
   // device tables
-  int64_t *src = nullptr, *drow = nullptr, *uoff_int = nullptr, *uoff_store = nullptr, *rec = nullptr,
-          *node = nullptr, *ident = nullptr;  // ident[p] = p
+  int64_t *drow = nullptr, *uoff_int = nullptr, *uoff_store = nullptr, *node = nullptr,
+          *ident = nullptr;  // ident[p] = p
+  int *src_of_pair = nullptr, *sptr = nullptr, *rptr = nullptr;
+  int64_t *slin = nullptr, *rlin = nullptr;
+  double *sw = nullptr, *rw = nullptr, *node_w = nullptr;
   double2* amp = nullptr;
   double *w2 = nullptr, *wg = nullptr;  // omega^2; omega^2 * scale (model-space sums)
   helm::cx<T>* res = nullptr;           // [np][nrec] receiver values
@@ -326,29 +412,29 @@ struct Pairs {
 };
 
 template <typename T>
-Pairs<T> plan_pairs(helm_ctx* ctx, const helm_grid* g, const void* m, int nfreq, const double* omega, int nsrc,
-                    const int32_t* src_idx, const double* src_amp, const uint8_t* mask, int nrec,
-                    const int32_t* rec_idx, bool renormalise, hipStream_t st) {
+Pairs<T> plan_pairs(helm_ctx* ctx, const helm_grid* g, const void* m, int nfreq, const double* omega,
+                    const PointSet& S, const double* src_amp, const uint8_t* mask, const PointSet& Rc,
+                    bool renormalise, hipStream_t st) {
   using namespace helm;
   Pairs<T> P;
+  const int nsrc = S.n(), nrec = Rc.n();
   P.N = (int64_t)g->n[0] * g->n[1] * g->n[2];
   P.nsrc = nsrc;
   P.nrec = nrec;
   P.nall = nfreq * nsrc;
-  const int64_t plane = (int64_t)g->n[1] * g->n[2];
-  auto lin = [&](const int32_t* q) { return (int64_t)q[0] * plane + (int64_t)q[1] * g->n[2] + q[2]; };
   for (int k = 0; k < P.nall; ++k)
     if (!mask || mask[k]) P.prow.push_back(k);
   P.np = (int)P.prow.size();
   if (P.np == 0) return P;
   const int np = P.np;
   P.scale = renormalise ? 1.0 / np : 1.0;
-  std::vector<int64_t> src_lin(np), drow(np), uoff_int(np), uoff_store(np), ident(np);
+  std::vector<int64_t> drow(np), uoff_int(np), uoff_store(np), ident(np);
+  std::vector<int> src_of_pair(np);
   std::vector<double2> amp(np);
   std::vector<double> w2(np), wg(np);
   for (int p = 0; p < np; ++p) {
     const int fi = P.prow[p] / nsrc, s = P.prow[p] % nsrc;
-    src_lin[p] = lin(src_idx + 3 * s);
+    src_of_pair[p] = s;
     const double* a = src_amp ? src_amp + 2 * (size_t)P.prow[p] : nullptr;
     amp[p] = a ? make_double2(a[0], a[1]) : make_double2(1.0, 0.0);
     drow[p] = P.prow[p];
@@ -359,31 +445,41 @@ Pairs<T> plan_pairs(helm_ctx* ctx, const helm_grid* g, const void* m, int nfreq,
     wg[p] = w2[p] * P.scale;
     P.probs.push_back(shared_problems(g, m, omega[fi], 0, 1)[0]);
   }
-  std::vector<int64_t> rec_lin(nrec);
-  for (int k = 0; k < nrec; ++k) rec_lin[k] = lin(rec_idx + 3 * k);
-  // distinct receiver nodes, ascending, each with its receivers in order
-  std::vector<int> order(nrec);
-  for (int k = 0; k < nrec; ++k) order[k] = k;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return rec_lin[a] < rec_lin[b]; });
+  int smax = 1;
+  for (int k = 0; k < nsrc; ++k) smax = std::max(smax, S.ptr[k + 1] - S.ptr[k]);
+  P.sblk = (int)ceil_div(smax, 256);
+  // the nodes the receivers touch, ascending, each with its (receiver,
+  // weight) entries in receiver order (a fixed summation order)
+  const int nent = (int)Rc.lin.size();
+  std::vector<int> ent(nent), ent_rec(nent);
+  for (int k = 0; k < nrec; ++k)
+    for (int e = Rc.ptr[k]; e < Rc.ptr[k + 1]; ++e) ent_rec[e] = k;
+  for (int e = 0; e < nent; ++e) ent[e] = e;
+  std::stable_sort(ent.begin(), ent.end(), [&](int x, int y) { return Rc.lin[x] < Rc.lin[y]; });
   std::vector<int64_t> node_lin;
-  std::vector<int> node_ptr, node_rec(nrec);
-  for (int e = 0; e < nrec; ++e) {
-    const int k = order[e];
-    if (node_lin.empty() || node_lin.back() != rec_lin[k]) {
-      node_lin.push_back(rec_lin[k]);
-      node_ptr.push_back(e);
+  std::vector<int> node_ptr, node_rec(nent);
+  std::vector<double> node_w(nent);
+  for (int i = 0; i < nent; ++i) {
+    const int e = ent[i];
+    if (node_lin.empty() || node_lin.back() != Rc.lin[e]) {
+      node_lin.push_back(Rc.lin[e]);
+      node_ptr.push_back(i);
     }
-    node_rec[e] = k;
+    node_rec[i] = ent_rec[e];
+    node_w[i] = Rc.w[e];
   }
-  node_ptr.push_back(nrec);
+  node_ptr.push_back(nent);
   P.nnode = (int)node_lin.size();
   P.rblk = (int)ceil_div(nrec, 256);
+  const int nsent = (int)S.lin.size();
   auto r256 = [](size_t b) { return (b + 255) / 256 * 256; };
-  const size_t small = 5 * r256(np * sizeof(int64_t)) + r256(np * sizeof(double2)) +
-                       2 * r256(np * sizeof(double)) + r256(nrec * sizeof(int64_t)) +
+  const size_t small = 4 * r256(np * sizeof(int64_t)) + r256(np * sizeof(int)) + r256(np * sizeof(double2)) +
+                       2 * r256(np * sizeof(double)) + r256((nsrc + 1) * sizeof(int)) +
+                       r256(nsent * sizeof(int64_t)) + r256(nsent * sizeof(double)) +
+                       r256((nrec + 1) * sizeof(int)) + r256(nent * sizeof(int64_t)) + r256(nent * sizeof(double)) +
                        r256((size_t)np * nrec * sizeof(cx<T>)) + r256((size_t)np * P.rblk * sizeof(double)) +
                        r256(P.nnode * sizeof(int64_t)) + r256((P.nnode + 1) * sizeof(int)) +
-                       r256(nrec * sizeof(int));
+                       r256(nent * sizeof(int)) + r256(nent * sizeof(double));
   ctx->fwi_small.ensure(small);
   char* sp = (char*)ctx->fwi_small.p;
   char* const sp_end = sp + small;
@@ -393,35 +489,47 @@ Pairs<T> plan_pairs(helm_ctx* ctx, const helm_grid* g, const void* m, int nfreq,
     if (sp > sp_end) throw Error{-3, "internal: misfit scratch layout overflow"};
     return (void*)q;
   };
-  P.src = (int64_t*)carve(np * sizeof(int64_t));
   P.drow = (int64_t*)carve(np * sizeof(int64_t));
   P.uoff_int = (int64_t*)carve(np * sizeof(int64_t));
   P.uoff_store = (int64_t*)carve(np * sizeof(int64_t));
   P.ident = (int64_t*)carve(np * sizeof(int64_t));
+  P.src_of_pair = (int*)carve(np * sizeof(int));
   P.amp = (double2*)carve(np * sizeof(double2));
   P.w2 = (double*)carve(np * sizeof(double));
   P.wg = (double*)carve(np * sizeof(double));
-  P.rec = (int64_t*)carve(nrec * sizeof(int64_t));
+  P.sptr = (int*)carve((nsrc + 1) * sizeof(int));
+  P.slin = (int64_t*)carve(nsent * sizeof(int64_t));
+  P.sw = (double*)carve(nsent * sizeof(double));
+  P.rptr = (int*)carve((nrec + 1) * sizeof(int));
+  P.rlin = (int64_t*)carve(nent * sizeof(int64_t));
+  P.rw = (double*)carve(nent * sizeof(double));
   P.res = (cx<T>*)carve((size_t)np * nrec * sizeof(cx<T>));
   P.part = (double*)carve((size_t)np * P.rblk * sizeof(double));
   P.node = (int64_t*)carve(P.nnode * sizeof(int64_t));
   P.nptr = (int*)carve((P.nnode + 1) * sizeof(int));
-  P.nrec_ord = (int*)carve(nrec * sizeof(int));
+  P.nrec_ord = (int*)carve(nent * sizeof(int));
+  P.node_w = (double*)carve(nent * sizeof(double));
   auto up = [&](void* dst, const void* src, size_t b) {
-    HELM_HIP_CHECK(hipMemcpyAsync(dst, src, b, hipMemcpyHostToDevice, st));
+    if (b) HELM_HIP_CHECK(hipMemcpyAsync(dst, src, b, hipMemcpyHostToDevice, st));
   };
-  up(P.src, src_lin.data(), np * sizeof(int64_t));
   up(P.drow, drow.data(), np * sizeof(int64_t));
   up(P.uoff_int, uoff_int.data(), np * sizeof(int64_t));
   up(P.uoff_store, uoff_store.data(), np * sizeof(int64_t));
   up(P.ident, ident.data(), np * sizeof(int64_t));
+  up(P.src_of_pair, src_of_pair.data(), np * sizeof(int));
   up(P.amp, amp.data(), np * sizeof(double2));
   up(P.w2, w2.data(), np * sizeof(double));
   up(P.wg, wg.data(), np * sizeof(double));
-  up(P.rec, rec_lin.data(), nrec * sizeof(int64_t));
+  up(P.sptr, S.ptr.data(), (nsrc + 1) * sizeof(int));
+  up(P.slin, S.lin.data(), nsent * sizeof(int64_t));
+  up(P.sw, S.w.data(), nsent * sizeof(double));
+  up(P.rptr, Rc.ptr.data(), (nrec + 1) * sizeof(int));
+  up(P.rlin, Rc.lin.data(), nent * sizeof(int64_t));
+  up(P.rw, Rc.w.data(), nent * sizeof(double));
   up(P.node, node_lin.data(), P.nnode * sizeof(int64_t));
   up(P.nptr, node_ptr.data(), (P.nnode + 1) * sizeof(int));
-  up(P.nrec_ord, node_rec.data(), nrec * sizeof(int));
+  up(P.nrec_ord, node_rec.data(), nent * sizeof(int));
+  up(P.node_w, node_w.data(), nent * sizeof(double));
   // the host vectors above go out of scope: the copies must have completed
   HELM_HIP_CHECK(hipStreamSynchronize(st));
   return P;
@@ -502,12 +610,12 @@ void launch_adjoint_source(const Pairs<T>& P, helm::cx<T>* b, const helm::cx<T>*
                        dim3(256), 0, st, b, (int64_t)P.np * P.N);
   if (add)
     hipLaunchKernelGGL((k_adjoint_source<T, true>), dim3(ceil_div(P.nnode, 256), P.np), dim3(256), 0, st, b, P.N,
-                       (const int64_t*)P.node, (const int*)P.nptr, (const int*)P.nrec_ord, P.nnode, res, P.nrec,
-                       rrow);
+                       (const int64_t*)P.node, (const int*)P.nptr, (const int*)P.nrec_ord, (const double*)P.node_w,
+                       P.nnode, res, P.nrec, rrow);
   else
     hipLaunchKernelGGL((k_adjoint_source<T, false>), dim3(ceil_div(P.nnode, 256), P.np), dim3(256), 0, st, b, P.N,
-                       (const int64_t*)P.node, (const int*)P.nptr, (const int*)P.nrec_ord, P.nnode, res, P.nrec,
-                       rrow);
+                       (const int64_t*)P.node, (const int*)P.nptr, (const int*)P.nrec_ord, (const double*)P.node_w,
+                       P.nnode, res, P.nrec, rrow);
   HELM_HIP_CHECK(hipGetLastError());
 }
 
@@ -525,8 +633,10 @@ FieldRef forward_fields(const helm_grid* g, const Pairs<T>& P, helm::Solver<T>& 
   *fwd_fp64 = nullptr;
   if (reuse) return FieldRef{u_store, P.uoff_store, u64};
   const double inv_h3 = 1.0 / (g->h * g->h * g->h);
-  hipLaunchKernelGGL((k_point_sources<T>), dim3(std::min<unsigned>(DOT_BLOCKS, ceil_div(N, 256)), P.np), dim3(256),
-                     0, st, Q, N, (const int64_t*)P.src, (const double2*)P.amp, inv_h3);
+  hipLaunchKernelGGL((k_fill_zero<T>), dim3(std::min<unsigned>(65536, ceil_div((int64_t)P.np * N, 256))), dim3(256), 0,
+                     st, Q, (int64_t)P.np * N);
+  hipLaunchKernelGGL((k_point_sources<T>), dim3(P.sblk, P.np), dim3(256), 0, st, Q, N, (const int*)P.src_of_pair,
+                     (const int*)P.sptr, (const int64_t*)P.slin, (const double*)P.sw, (const double2*)P.amp, inv_h3);
   worst = std::max(worst, S.solve(0, Q, U, inf.data()));
   if (info)
     for (int p = 0; p < P.np; ++p) to_info(inf[p], info + P.prow[p]);
@@ -565,21 +675,24 @@ void launch_residual(const Pairs<T>& P, const helm::cx<double>* fwd_fp64, const 
   const dim3 grid(P.rblk, P.np);
   if (fwd_fp64)
     hipLaunchKernelGGL((k_sample_residual<double, T>), grid, dim3(256), 0, st, fwd_fp64, (const int64_t*)P.uoff_int,
-                       (const int64_t*)P.rec, P.nrec, (const cx<T>*)d, (const int64_t*)P.drow, P.res, P.part);
+                       (const int*)P.rptr, (const int64_t*)P.rlin, (const double*)P.rw, P.nrec, (const cx<T>*)d,
+                       (const int64_t*)P.drow, P.res, P.part);
   else if (u.f64)
     hipLaunchKernelGGL((k_sample_residual<double, T>), grid, dim3(256), 0, st, (const cx<double>*)u.p, u.off,
-                       (const int64_t*)P.rec, P.nrec, (const cx<T>*)d, (const int64_t*)P.drow, P.res, P.part);
+                       (const int*)P.rptr, (const int64_t*)P.rlin, (const double*)P.rw, P.nrec, (const cx<T>*)d,
+                       (const int64_t*)P.drow, P.res, P.part);
   else
     hipLaunchKernelGGL((k_sample_residual<T, T>), grid, dim3(256), 0, st, (const cx<T>*)u.p, u.off,
-                       (const int64_t*)P.rec, P.nrec, (const cx<T>*)d, (const int64_t*)P.drow, P.res, P.part);
+                       (const int*)P.rptr, (const int64_t*)P.rlin, (const double*)P.rw, P.nrec, (const cx<T>*)d,
+                       (const int64_t*)P.drow, P.res, P.part);
   HELM_HIP_CHECK(hipGetLastError());
 }
 
 // misfit + gradient over the selected (frequency, source) pairs, element type T
 template <typename T>
 helm_status misfit_gradient_t(helm_ctx* ctx, const helm_grid* g, const void* m, int nfreq, const double* omega,
-                              int nsrc, const int32_t* src_idx, const double* src_amp, const uint8_t* mask,
-                              int nrec, const int32_t* rec_idx, const void* d, double* f, void* grad,
+                              const PointSet& src, const double* src_amp, const uint8_t* mask, const PointSet& rec,
+                              const void* d, double* f, void* grad,
                               void* u_store, int flags, const helm::SolveOpts& o, helm_solve_info* info,
                               void* caller) {
   using namespace helm;
@@ -589,9 +702,9 @@ helm_status misfit_gradient_t(helm_ctx* ctx, const helm_grid* g, const void* m, 
   const bool acc = (flags & HELM_MG_ACCUMULATE) != 0;
   const bool u64 = (flags & HELM_MG_U_FP64) != 0 && sizeof(T) == 4;
   if (info)
-    for (int k = 0; k < 2 * nfreq * nsrc; ++k) to_info(SolveInfo(), info + k);
-  Pairs<T> P = plan_pairs<T>(ctx, g, m, nfreq, omega, nsrc, src_idx, src_amp, mask, nrec, rec_idx,
-                             (flags & HELM_MG_RENORMALISE) != 0, st);
+    for (int k = 0; k < 2 * nfreq * src.n(); ++k) to_info(SolveInfo(), info + k);
+  Pairs<T> P = plan_pairs<T>(ctx, g, m, nfreq, omega, src, src_amp, mask, rec, (flags & HELM_MG_RENORMALISE) != 0,
+                             st);
   const int64_t N = P.N;
   if (P.np == 0) {
     *f = 0.0;
@@ -642,19 +755,19 @@ helm_status misfit_gradient_t(helm_ctx* ctx, const helm_grid* g, const void* m, 
 //               out = sum Re(omega^2 conj(du) (A v)) + Re(T^* dv)
 template <typename T>
 helm_status derivative_t(helm_ctx* ctx, int mode, const helm_grid* g, const void* m, int nfreq, const double* omega,
-                         int nsrc, const int32_t* src_idx, const double* src_amp, const uint8_t* mask, int nrec,
-                         const int32_t* rec_idx, const void* in, const void* d, void* out, void* u_store, int flags,
-                         const helm::SolveOpts& o, helm_solve_info* info, void* caller) {
+                         const PointSet& src, const double* src_amp, const uint8_t* mask, const PointSet& rec,
+                         const void* in, const void* d, void* out, void* u_store, int flags, const helm::SolveOpts& o,
+                         helm_solve_info* info, void* caller) {
   using namespace helm;
   hipStream_t st = solve_stream(ctx, caller);
   const bool reuse = (flags & HELM_MG_REUSE_U) != 0;
   const bool acc = (flags & HELM_MG_ACCUMULATE) != 0;
   const bool u64 = (flags & HELM_MG_U_FP64) != 0 && sizeof(T) == 4;
-  const int nall = nfreq * nsrc;
+  const int nall = nfreq * src.n(), nrec = rec.n();
   if (info)
     for (int k = 0; k < 4 * nall; ++k) to_info(SolveInfo(), info + k);
-  Pairs<T> P = plan_pairs<T>(ctx, g, m, nfreq, omega, nsrc, src_idx, src_amp, mask, nrec, rec_idx,
-                             (flags & HELM_MG_RENORMALISE) != 0, st);
+  Pairs<T> P = plan_pairs<T>(ctx, g, m, nfreq, omega, src, src_amp, mask, rec, (flags & HELM_MG_RENORMALISE) != 0,
+                             st);
   const int64_t N = P.N;
   const int np = P.np;
   if (mode == HELM_JACOB_FORW)  // rows of unselected pairs are zero
@@ -697,10 +810,12 @@ helm_status derivative_t(helm_ctx* ctx, int mode, const helm_grid* g, const void
     solve(0, Q, B[0]);                                  // du
     if (mode == HELM_JACOB_FORW) {
       hipLaunchKernelGGL((k_sample<double, T>), sgrid, dim3(256), 0, st, S.iterate(), (const int64_t*)P.uoff_int,
-                         (const int64_t*)P.rec, nrec, (cx<T>*)out, (const int64_t*)P.drow);
+                         (const int*)P.rptr, (const int64_t*)P.rlin, (const double*)P.rw, nrec, (cx<T>*)out,
+                         (const int64_t*)P.drow);
     } else {
       hipLaunchKernelGGL((k_sample<double, T>), sgrid, dim3(256), 0, st, S.iterate(), (const int64_t*)P.uoff_int,
-                         (const int64_t*)P.rec, nrec, P.res, (const int64_t*)P.ident);
+                         (const int*)P.rptr, (const int64_t*)P.rlin, (const double*)P.rw, nrec, P.res,
+                         (const int64_t*)P.ident);
       HELM_HIP_CHECK(hipGetLastError());
       launch_adjoint_source<T>(P, Q, P.res, nullptr, false, st);  // -P_r^T P_r du
       solve(1, Q, B[1]);                                            // w
@@ -717,7 +832,8 @@ helm_status derivative_t(helm_ctx* ctx, int mode, const helm_grid* g, const void
     launch_born_source<T, false>(g, P, uf, in, Q, st);         // -T dm
     solve(0, Q, B[1]);                                         // du
     hipLaunchKernelGGL((k_sample<double, T>), sgrid, dim3(256), 0, st, S.iterate(), (const int64_t*)P.uoff_int,
-                       (const int64_t*)P.rec, nrec, P.res, (const int64_t*)P.ident);
+                       (const int*)P.rptr, (const int64_t*)P.rlin, (const double*)P.rw, nrec, P.res,
+                         (const int64_t*)P.ident);
     HELM_HIP_CHECK(hipGetLastError());
     launch_born_source<T, true>(g, P, b0, in, Q, st);          // -omega^2 dm (A v)
     launch_adjoint_source<T>(P, Q, P.res, nullptr, true, st);  // - P_r^T P_r du
@@ -728,6 +844,78 @@ helm_status derivative_t(helm_ctx* ctx, int mode, const helm_grid* g, const void
   HELM_HIP_CHECK(hipGetLastError());
   HELM_HIP_CHECK(hipStreamSynchronize(st));
   return (helm_status)worst;
+}
+
+// Argument checks shared by the misfit and derivative entry points.
+void check_pair_args(const helm_grid* g, const void* m, int nfreq, const double* omega, int nsrc, int nrec) {
+  check_grid(g);
+  HELM_REQUIRE(m, "null model pointer");
+  HELM_REQUIRE(nfreq >= 1 && omega, "nfreq must be >= 1 with an omega array");
+  for (int k = 0; k < nfreq; ++k) HELM_REQUIRE(omega[k] > 0.0 && std::isfinite(omega[k]), "omega must be positive");
+  HELM_REQUIRE(nsrc >= 1 && nrec >= 1, "nsrc and nrec must be >= 1");
+  HELM_REQUIRE((int64_t)nfreq * nsrc <= (1 << 20), "too many (frequency, source) pairs");
+}
+
+void check_nodes(const helm_grid* g, int n, const int32_t* idx, const char* what) {
+  for (int k = 0; k < n; ++k)
+    for (int a = 0; a < 3; ++a) HELM_REQUIRE(idx[3 * k + a] >= 0 && idx[3 * k + a] < g->n[a], what);
+}
+
+void check_sinc(const helm_grid* g, int nsrc, const double* src_pos, int nrec, const double* rec_pos, int radius,
+                double kb) {
+  HELM_REQUIRE(radius >= 1 && radius <= 8, "sinc radius must be in 1..8");
+  HELM_REQUIRE(kb >= 0.0 && kb <= 100.0, "Kaiser window shape must be in [0, 100]");
+  for (int k = 0; k < nsrc; ++k)
+    for (int a = 0; a < 3; ++a)
+      HELM_REQUIRE(std::isfinite(src_pos[3 * k + a]) && src_pos[3 * k + a] >= 0.0 &&
+                       src_pos[3 * k + a] <= g->n[a] - 1,
+                   "source outside the grid");
+  for (int k = 0; k < nrec; ++k)
+    for (int a = 0; a < 3; ++a)
+      HELM_REQUIRE(std::isfinite(rec_pos[3 * k + a]) && rec_pos[3 * k + a] >= 0.0 &&
+                       rec_pos[3 * k + a] <= g->n[a] - 1,
+                   "receiver outside the grid");
+  HELM_REQUIRE((int64_t)nrec * (2 * radius) * (2 * radius) * (2 * radius) < ((int64_t)1 << 31),
+               "too many receiver interpolation entries");
+}
+
+helm_status misfit_common(helm_ctx* ctx, const helm_grid* g, const void* m, int nfreq, const double* omega,
+                          const PointSet& src, const double* src_amp, const uint8_t* mask, const PointSet& rec,
+                          const void* d, double* f, void* grad, void* u_store, int flags, const helm_solver_opts* o,
+                          helm_solve_info* info, void* stream) {
+  HELM_REQUIRE(d && f, "null pointer argument");
+  HELM_REQUIRE((flags & HELM_MG_FORWARD_ONLY) || grad, "null gradient");
+  HELM_REQUIRE(!(flags & HELM_MG_REUSE_U) || u_store, "HELM_MG_REUSE_U needs u_store");
+  HELM_REQUIRE(!(flags & HELM_MG_U_FP64) || u_store, "HELM_MG_U_FP64 needs u_store");
+  HELM_REQUIRE((flags & ~31) == 0, "unknown flag bits");
+  const helm::SolveOpts so = opts_of(o);
+  check_coarse_sizes(g, so);
+  if (g->dtype == HELM_C64)
+    return misfit_gradient_t<float>(ctx, g, m, nfreq, omega, src, src_amp, mask, rec, d, f, grad, u_store, flags, so,
+                                    info, stream);
+  return misfit_gradient_t<double>(ctx, g, m, nfreq, omega, src, src_amp, mask, rec, d, f, grad, u_store, flags, so,
+                                   info, stream);
+}
+
+helm_status derivative_common(helm_ctx* ctx, int mode, const helm_grid* g, const void* m, int nfreq,
+                              const double* omega, const PointSet& src, const double* src_amp, const uint8_t* mask,
+                              const PointSet& rec, const void* input, const void* d, void* output, void* u_store,
+                              int flags, const helm_solver_opts* o, helm_solve_info* info, void* stream) {
+  HELM_REQUIRE(mode == HELM_JACOB_FORW || mode == HELM_JACOB_ADJ || mode == HELM_HESS_GN || mode == HELM_HESS,
+               "unknown derivative mode");
+  HELM_REQUIRE(input && output, "null pointer argument");
+  HELM_REQUIRE(mode != HELM_HESS || d, "HELM_HESS needs the observed data d");
+  HELM_REQUIRE(!(flags & HELM_MG_REUSE_U) || u_store, "HELM_MG_REUSE_U needs u_store");
+  HELM_REQUIRE(!(flags & HELM_MG_U_FP64) || u_store, "HELM_MG_U_FP64 needs u_store");
+  HELM_REQUIRE((flags & ~(HELM_MG_REUSE_U | HELM_MG_ACCUMULATE | HELM_MG_U_FP64 | HELM_MG_RENORMALISE)) == 0,
+               "unknown or unsupported flag bits");
+  const helm::SolveOpts so = opts_of(o);
+  check_coarse_sizes(g, so);
+  if (g->dtype == HELM_C64)
+    return derivative_t<float>(ctx, mode, g, m, nfreq, omega, src, src_amp, mask, rec, input, d, output, u_store,
+                               flags, so, info, stream);
+  return derivative_t<double>(ctx, mode, g, m, nfreq, omega, src, src_amp, mask, rec, input, d, output, u_store, flags,
+                              so, info, stream);
 }
 
 }  // namespace
@@ -904,31 +1092,27 @@ helm_status misfit_gradient(helm_ctx* ctx, const helm_grid* g, const void* m, in
                             const int32_t* rec_idx, const void* d, double* f, void* grad, void* u_store, int flags,
                             const helm_solver_opts* o, helm_solve_info* info, void* stream) {
   return guarded(ctx, [&]() -> helm_status {
-    check_grid(g);
-    HELM_REQUIRE(m && d && f, "null pointer argument");
-    HELM_REQUIRE(nfreq >= 1 && omega, "nfreq must be >= 1 with an omega array");
-    for (int k = 0; k < nfreq; ++k)
-      HELM_REQUIRE(omega[k] > 0.0 && std::isfinite(omega[k]), "omega must be positive");
-    HELM_REQUIRE(nsrc >= 1 && nrec >= 1, "nsrc and nrec must be >= 1");
-    HELM_REQUIRE((int64_t)nfreq * nsrc <= (1 << 20), "too many (frequency, source) pairs");
+    check_pair_args(g, m, nfreq, omega, nsrc, nrec);
     HELM_REQUIRE(src_idx && rec_idx, "null source / receiver index array");
-    HELM_REQUIRE((flags & HELM_MG_FORWARD_ONLY) || grad, "null gradient");
-    HELM_REQUIRE(!(flags & HELM_MG_REUSE_U) || u_store, "HELM_MG_REUSE_U needs u_store");
-    HELM_REQUIRE(!(flags & HELM_MG_U_FP64) || u_store, "HELM_MG_U_FP64 needs u_store");
-    HELM_REQUIRE((flags & ~31) == 0, "unknown flag bits");
-    for (int s = 0; s < nsrc; ++s)
-      for (int a = 0; a < 3; ++a)
-        HELM_REQUIRE(src_idx[3 * s + a] >= 0 && src_idx[3 * s + a] < g->n[a], "source outside the grid");
-    for (int k = 0; k < nrec; ++k)
-      for (int a = 0; a < 3; ++a)
-        HELM_REQUIRE(rec_idx[3 * k + a] >= 0 && rec_idx[3 * k + a] < g->n[a], "receiver outside the grid");
-    const helm::SolveOpts so = opts_of(o);
-    check_coarse_sizes(g, so);
-    if (g->dtype == HELM_C64)
-      return misfit_gradient_t<float>(ctx, g, m, nfreq, omega, nsrc, src_idx, src_amp, mask, nrec, rec_idx, d, f,
-                                      grad, u_store, flags, so, info, stream);
-    return misfit_gradient_t<double>(ctx, g, m, nfreq, omega, nsrc, src_idx, src_amp, mask, nrec, rec_idx, d, f,
-                                     grad, u_store, flags, so, info, stream);
+    check_nodes(g, nsrc, src_idx, "source outside the grid");
+    check_nodes(g, nrec, rec_idx, "receiver outside the grid");
+    return misfit_common(ctx, g, m, nfreq, omega, on_node_points(g, nsrc, src_idx), src_amp, mask,
+                         on_node_points(g, nrec, rec_idx), d, f, grad, u_store, flags, o, info, stream);
+  });
+}
+
+helm_status misfit_gradient_offgrid(helm_ctx* ctx, const helm_grid* g, const void* m, int nfreq,
+                                    const double* omega, int nsrc, const double* src_pos, const double* src_amp,
+                                    const uint8_t* mask, int nrec, const double* rec_pos, int radius,
+                                    double kaiser_b, const void* d, double* f, void* grad, void* u_store, int flags,
+                                    const helm_solver_opts* o, helm_solve_info* info, void* stream) {
+  return guarded(ctx, [&]() -> helm_status {
+    check_pair_args(g, m, nfreq, omega, nsrc, nrec);
+    HELM_REQUIRE(src_pos && rec_pos, "null source / receiver position array");
+    check_sinc(g, nsrc, src_pos, nrec, rec_pos, radius, kaiser_b);
+    return misfit_common(ctx, g, m, nfreq, omega, sinc_points(g, nsrc, src_pos, radius, kaiser_b), src_amp, mask,
+                         sinc_points(g, nrec, rec_pos, radius, kaiser_b), d, f, grad, u_store, flags, o, info,
+                         stream);
   });
 }
 
@@ -938,34 +1122,27 @@ helm_status pde_derivative(helm_ctx* ctx, int mode, const helm_grid* g, const vo
                            void* output, void* u_store, int flags, const helm_solver_opts* o, helm_solve_info* info,
                            void* stream) {
   return guarded(ctx, [&]() -> helm_status {
-    check_grid(g);
-    HELM_REQUIRE(mode == HELM_JACOB_FORW || mode == HELM_JACOB_ADJ || mode == HELM_HESS_GN || mode == HELM_HESS,
-                 "unknown derivative mode");
-    HELM_REQUIRE(m && input && output, "null pointer argument");
-    HELM_REQUIRE(mode != HELM_HESS || d, "HELM_HESS needs the observed data d");
-    HELM_REQUIRE(nfreq >= 1 && omega, "nfreq must be >= 1 with an omega array");
-    for (int k = 0; k < nfreq; ++k)
-      HELM_REQUIRE(omega[k] > 0.0 && std::isfinite(omega[k]), "omega must be positive");
-    HELM_REQUIRE(nsrc >= 1 && nrec >= 1, "nsrc and nrec must be >= 1");
-    HELM_REQUIRE((int64_t)nfreq * nsrc <= (1 << 20), "too many (frequency, source) pairs");
+    check_pair_args(g, m, nfreq, omega, nsrc, nrec);
     HELM_REQUIRE(src_idx && rec_idx, "null source / receiver index array");
-    HELM_REQUIRE(!(flags & HELM_MG_REUSE_U) || u_store, "HELM_MG_REUSE_U needs u_store");
-    HELM_REQUIRE(!(flags & HELM_MG_U_FP64) || u_store, "HELM_MG_U_FP64 needs u_store");
-    HELM_REQUIRE((flags & ~(HELM_MG_REUSE_U | HELM_MG_ACCUMULATE | HELM_MG_U_FP64 | HELM_MG_RENORMALISE)) == 0,
-                 "unknown or unsupported flag bits");
-    for (int s = 0; s < nsrc; ++s)
-      for (int a = 0; a < 3; ++a)
-        HELM_REQUIRE(src_idx[3 * s + a] >= 0 && src_idx[3 * s + a] < g->n[a], "source outside the grid");
-    for (int k = 0; k < nrec; ++k)
-      for (int a = 0; a < 3; ++a)
-        HELM_REQUIRE(rec_idx[3 * k + a] >= 0 && rec_idx[3 * k + a] < g->n[a], "receiver outside the grid");
-    const helm::SolveOpts so = opts_of(o);
-    check_coarse_sizes(g, so);
-    if (g->dtype == HELM_C64)
-      return derivative_t<float>(ctx, mode, g, m, nfreq, omega, nsrc, src_idx, src_amp, mask, nrec, rec_idx, input,
-                                 d, output, u_store, flags, so, info, stream);
-    return derivative_t<double>(ctx, mode, g, m, nfreq, omega, nsrc, src_idx, src_amp, mask, nrec, rec_idx, input,
-                                d, output, u_store, flags, so, info, stream);
+    check_nodes(g, nsrc, src_idx, "source outside the grid");
+    check_nodes(g, nrec, rec_idx, "receiver outside the grid");
+    return derivative_common(ctx, mode, g, m, nfreq, omega, on_node_points(g, nsrc, src_idx), src_amp, mask,
+                             on_node_points(g, nrec, rec_idx), input, d, output, u_store, flags, o, info, stream);
+  });
+}
+
+helm_status pde_derivative_offgrid(helm_ctx* ctx, int mode, const helm_grid* g, const void* m, int nfreq,
+                                   const double* omega, int nsrc, const double* src_pos, const double* src_amp,
+                                   const uint8_t* mask, int nrec, const double* rec_pos, int radius, double kaiser_b,
+                                   const void* input, const void* d, void* output, void* u_store, int flags,
+                                   const helm_solver_opts* o, helm_solve_info* info, void* stream) {
+  return guarded(ctx, [&]() -> helm_status {
+    check_pair_args(g, m, nfreq, omega, nsrc, nrec);
+    HELM_REQUIRE(src_pos && rec_pos, "null source / receiver position array");
+    check_sinc(g, nsrc, src_pos, nrec, rec_pos, radius, kaiser_b);
+    return derivative_common(ctx, mode, g, m, nfreq, omega, sinc_points(g, nsrc, src_pos, radius, kaiser_b),
+                             src_amp, mask, sinc_points(g, nrec, rec_pos, radius, kaiser_b), input, d, output,
+                             u_store, flags, o, info, stream);
   });
 }
 
