@@ -374,6 +374,127 @@ helm_status pde_derivative_offgrid(helm_ctx* ctx, int mode,
                                    const helm_solver_opts* o,
                                    helm_solve_info* info, void* stream);
 
+/* Parameters of the inversion driver (fwi_invert). */
+typedef struct {
+  int32_t band_size;      /* frequencies per band (>= 1)                      */
+  int32_t band_overlap;   /* frequencies shared by consecutive bands,
+                             0 <= band_overlap < band_size                    */
+  int32_t r_sub;          /* iterations per draw: r_sub * ceil(nsrc / p)      */
+  int32_t memory;         /* stored L-BFGS pairs (0..16)                      */
+  int32_t batch;          /* initial subset size p; <= 0 or >= nsrc: every
+                             source (no random draw)                          */
+  int32_t subproblems;    /* draws per band (T, >= 1)                         */
+  int32_t batch_increase; /* growth of p after a failed line search (>= 0)    */
+  int32_t max_ls;         /* line-search trials per iteration (1..60)         */
+  uint64_t seed;          /* SplitMix64 seed of the source draws              */
+  double c1;              /* sufficient-decrease constant, (0, 1)             */
+  double gtol;            /* stop a draw when max|g_F| <= gtol * its value at
+                             the draw's start (>= 0)                          */
+  double step0;           /* max-norm length of a steepest-descent trial
+                             step, > 0 (model units)                          */
+  double lo, hi;          /* scalar bounds, used where lo / hi arrays are
+                             NULL                                             */
+} helm_fwi_params;
+
+/* Summary of one draw (subproblem) of fwi_invert. */
+typedef struct {
+  int32_t band, draw;     /* band index, draw index within the band           */
+  int32_t nsel;           /* sources in the draw                              */
+  int32_t max_iters;      /* r_sub * ceil(nsrc / p)                           */
+  int32_t iters;          /* iterations performed (a failed one included)     */
+  int32_t failed;         /* 1: ended by a failed line search                 */
+  int32_t evals;          /* objective + gradient evaluations                 */
+  int32_t status;         /* worst helm_status of the draw's solves           */
+  double f_start, f_end;  /* subset objective at the draw's first and last
+                             iterate                                          */
+} helm_fwi_draw;
+
+/* One L-BFGS iteration of fwi_invert. */
+typedef struct {
+  int32_t band, draw, iter, nsel;
+  int32_t trials;         /* line-search trials                               */
+  int32_t accepted;       /* 1: a trial met the sufficient decrease           */
+  int32_t status;         /* worst helm_status of the draw's solves so far    */
+  int32_t pad_;
+  double f;               /* subset objective at the iterate                  */
+  double f_new;           /* at the accepted (or last) trial                  */
+  double step;            /* accepted t (or half the last one tried)          */
+  double pgmax;           /* max |g_F| at the iterate                         */
+} helm_fwi_record;
+
+/* Number of draws fwi_invert performs: bands * subproblems, bands =
+ * 1 + ceil(max(0, nfreq - band_size) / (band_size - band_overlap)); -1 for
+ * invalid arguments. */
+int helm_fwi_draw_count(int nfreq, const helm_fwi_params* p);
+
+/* Full-waveform inversion by frequency continuation, stochastic source
+ * subsets and a box-constrained L-BFGS (paper: the 2D inversion example --
+ * bands of band_size frequencies overlapping by band_overlap, a fixed number
+ * of bound-constrained L-BFGS iterations per band, warm-started band to band,
+ * the source/frequency mask selecting the band -- and the stochastic
+ * inversion section -- min over m_LB <= m <= m_UB of the average of f_i over
+ * a uniformly drawn subset I_k of p sources, r_sub ceil(nsrc / p)
+ * iterations per draw, the result warm-starting the next draw, p grown by
+ * batch_increase after a failed line search).  Per band, per draw: the
+ * objective is misfit_gradient over the band's frequencies and the drawn
+ * sources with HELM_MG_RENORMALISE; the projected L-BFGS is
+ *   F   = points not held at a bound by the gradient (x <= lo with g > 0,
+ *         x >= hi with g < 0 are held);
+ *   d   = -H g on F by the two-loop recursion over the stored pairs restricted
+ *         to F (initial scaling s.y / y.y of the newest), 0 off F; d =
+ *         -g_F step0 / max|g_F| with no pair or when g.d >= 0;
+ *   stop the draw when max|g_F| <= gtol * its value at the draw's start;
+ *   x_t = clamp(x + t d, lo, hi), t = 1, 1/2, ... (max_ls trials) until
+ *         f(x_t) <= f(x) + c1 g.(x_t - x); a failed search ends the draw;
+ *   keep (x_t - x, g_t - g) when s.y > 1e-10 |s| |y| (memory pairs, oldest
+ *         dropped); every draw starts with an empty memory.
+ * Subsets: a partial Fisher-Yates shuffle of 0..nsrc-1 whose step-i swap
+ * partner is i + (u mod (nsrc - i)), u the next output of SplitMix64 (Steele,
+ * Lea and Flood 2014) seeded with p->seed, one counter for the whole run
+ * (drawing every source consumes none); sorted ascending.  The L-BFGS
+ * vectors are FP64 on the device (4 + 2 (memory + 1) vectors of N doubles
+ * in the context's workspace); the solves read the trial model in the
+ * grid's real type.
+ * Arguments (the pair arguments as in misfit_gradient):
+ *   m        dev, N reals of g->dtype: the starting model, overwritten by
+ *            the result (clamped into the bounds first)
+ *   lo, hi   dev, N doubles each, or NULL for p->lo / p->hi: the bounds
+ *            (lo = hi clamps a point, e.g. a water layer)
+ *   d        dev [nfreq][nsrc][nrec] complex of g->dtype: observed data
+ *   p        host: the driver parameters
+ *   draws    host, helm_fwi_draw_count() entries or NULL
+ *   sources  host, [draws][nsrc] int32 or NULL: each draw's sources
+ *            ascending, padded with -1
+ *   recs     host, rec_cap entries or NULL: the iterations in order (the
+ *            first rec_cap of them); *nrecs (host, may be NULL) receives the
+ *            total number of iterations
+ * Invalid arguments return HELM_E_INVAL before any device work, except bounds
+ * with lo > hi (or NaN) somewhere in the arrays, which return HELM_E_INVAL
+ * after one checking kernel, m unchanged.  Returns the worst status of all
+ * solves. */
+helm_status fwi_invert(helm_ctx* ctx, const helm_grid* g, void* m,
+                       const double* lo, const double* hi, int nfreq,
+                       const double* omega, int nsrc, const int32_t* src_idx,
+                       const double* src_amp, int nrec,
+                       const int32_t* rec_idx, const void* d,
+                       const helm_fwi_params* p, const helm_solver_opts* o,
+                       helm_fwi_draw* draws, int32_t* sources,
+                       helm_fwi_record* recs, int rec_cap, int* nrecs,
+                       void* stream);
+
+/* fwi_invert with off-grid sources and receivers: src_idx / rec_idx replaced
+ * by src_pos / rec_pos, radius and kaiser_b as in misfit_gradient_offgrid. */
+helm_status fwi_invert_offgrid(helm_ctx* ctx, const helm_grid* g, void* m,
+                               const double* lo, const double* hi, int nfreq,
+                               const double* omega, int nsrc,
+                               const double* src_pos, const double* src_amp,
+                               int nrec, const double* rec_pos, int radius,
+                               double kaiser_b, const void* d,
+                               const helm_fwi_params* p,
+                               const helm_solver_opts* o, helm_fwi_draw* draws,
+                               int32_t* sources, helm_fwi_record* recs,
+                               int rec_cap, int* nrecs, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -140,7 +140,7 @@ def projected_lbfgs(fg, x, lo, hi, iters, memory, step0, c1=1e-4, max_ls=10, gto
                 break
             t *= 0.5
         if log is not None:
-            log.append(dict(iter=it, f=f, f_new=ft, trials=trial, accepted=accepted, step=t))
+            log.append(dict(iter=it, f=f, f_new=ft, trials=trial, accepted=accepted, step=t, pgmax=gmax))
         if not accepted:
             return x, True
         s, y = xt - x, gt - g
@@ -160,8 +160,9 @@ def iterations(r_sub, nsrc, p):
 
 
 def default_step0(lo, hi):
-    """First steepest-descent trial: 5 % of the widest bound interval."""
-    return 0.05 * float(np.max(np.asarray(hi) - np.asarray(lo)))
+    """Max-norm length of a steepest-descent trial: 5 % of the range the
+    bounds span, max(hi) - min(lo)."""
+    return 0.05 * (float(np.max(hi)) - float(np.min(lo)))
 
 
 def fwi_invert(g: ops.Grid, m0, lo, hi, omegas, src, rec, d, amp=None, band_size=4, band_overlap=2,

@@ -6,11 +6,11 @@ C ABI of ``include/helm.h``); this package only marshals torch tensors into
 those entry points.  Importing it does not load the library; the first call
 does, and raises if the library has not been built.
 """
-from .api import (Grid, SolverOpts, SolveInfo, HelmError, helm_apply, helm_apply_noalloc, helm_solve,
+from .api import (Grid, SolverOpts, SolveInfo, HelmError, fwi_invert, helm_apply, helm_apply_noalloc, helm_solve,
                   helm_solve_batched, misfit_gradient, pde_derivative, version, workspace_bytes)
 from .autograd import HelmholtzMisfit, helmholtz_misfit
 
 __all__ = ["Grid", "SolverOpts", "SolveInfo", "HelmError", "helm_apply", "helm_apply_noalloc", "helm_solve",
            "helm_solve_batched",
-           "misfit_gradient", "pde_derivative", "version", "workspace_bytes", "HelmholtzMisfit",
+           "misfit_gradient", "pde_derivative", "fwi_invert", "version", "workspace_bytes", "HelmholtzMisfit",
            "helmholtz_misfit"]

@@ -48,7 +48,8 @@ STATUS_NAMES = {
 EXPORTS = ("helm_create", "helm_destroy", "helm_last_error", "helm_version",
            "helm_default_opts", "helm_workspace_bytes", "helm_apply",
            "helm_apply_noalloc", "helm_solve", "helm_solve_batched", "misfit_gradient",
-           "misfit_gradient_offgrid", "pde_derivative", "pde_derivative_offgrid")
+           "misfit_gradient_offgrid", "pde_derivative", "pde_derivative_offgrid",
+           "helm_fwi_draw_count", "fwi_invert", "fwi_invert_offgrid")
 
 
 class helm_grid(C.Structure):
@@ -75,6 +76,28 @@ class helm_solve_info(C.Structure):
     _fields_ = [("status", C.c_int32), ("cycles", C.c_int32),
                 ("inner_its", C.c_int32), ("pad_", C.c_int32),
                 ("matvecs", C.c_int64), ("relres_fp64", C.c_double)]
+
+
+class helm_fwi_params(C.Structure):
+    _fields_ = [("band_size", C.c_int32), ("band_overlap", C.c_int32), ("r_sub", C.c_int32),
+                ("memory", C.c_int32), ("batch", C.c_int32), ("subproblems", C.c_int32),
+                ("batch_increase", C.c_int32), ("max_ls", C.c_int32), ("seed", C.c_uint64),
+                ("c1", C.c_double), ("gtol", C.c_double), ("step0", C.c_double),
+                ("lo", C.c_double), ("hi", C.c_double)]
+
+
+class helm_fwi_draw(C.Structure):
+    _fields_ = [("band", C.c_int32), ("draw", C.c_int32), ("nsel", C.c_int32),
+                ("max_iters", C.c_int32), ("iters", C.c_int32), ("failed", C.c_int32),
+                ("evals", C.c_int32), ("status", C.c_int32), ("f_start", C.c_double),
+                ("f_end", C.c_double)]
+
+
+class helm_fwi_record(C.Structure):
+    _fields_ = [("band", C.c_int32), ("draw", C.c_int32), ("iter", C.c_int32), ("nsel", C.c_int32),
+                ("trials", C.c_int32), ("accepted", C.c_int32), ("status", C.c_int32),
+                ("pad_", C.c_int32), ("f", C.c_double), ("f_new", C.c_double), ("step", C.c_double),
+                ("pgmax", C.c_double)]
 
 
 _lib = None
@@ -118,9 +141,18 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                                             i32, dbl, vp, D, vp, vp, i32, O, I, vp]
     lib.pde_derivative_offgrid.argtypes = [vp, i32, G, vp, i32, D, i32, D, D, C.POINTER(C.c_uint8), i32, D,
                                            i32, dbl, vp, vp, vp, vp, i32, O, I, vp]
+    P = C.POINTER(helm_fwi_params)
+    lib.helm_fwi_draw_count.argtypes = [i32, P]
+    lib.helm_fwi_draw_count.restype = C.c_int
+    FW = [C.POINTER(helm_fwi_draw), C.POINTER(C.c_int32), C.POINTER(helm_fwi_record), i32,
+          C.POINTER(C.c_int), vp]
+    lib.fwi_invert.argtypes = [vp, G, vp, vp, vp, i32, D, i32, C.POINTER(C.c_int32), D, i32,
+                               C.POINTER(C.c_int32), vp, P, O] + FW
+    lib.fwi_invert_offgrid.argtypes = [vp, G, vp, vp, vp, i32, D, i32, D, D, i32, D, i32, dbl, vp, P,
+                                       O] + FW
     for name in ("helm_create", "helm_destroy", "helm_apply", "helm_apply_noalloc", "helm_solve",
                  "helm_solve_batched", "misfit_gradient", "misfit_gradient_offgrid", "pde_derivative",
-                 "pde_derivative_offgrid"):
+                 "pde_derivative_offgrid", "fwi_invert", "fwi_invert_offgrid"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib

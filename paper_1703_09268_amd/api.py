@@ -399,6 +399,70 @@ def pde_derivative(mode: str, grid: Grid, m: torch.Tensor, omega, src, rec, inpu
     return out, inf
 
 
+def fwi_invert(grid: Grid, m: torch.Tensor, omega, src, rec, d: torch.Tensor, lo, hi,
+               src_amp=None, band_size: int = 4, band_overlap: int = 2, r_sub: int = 20,
+               memory: int = 5, batch: int = 0, subproblems: int = 1, batch_increase: int = 1,
+               seed: int = 0, c1: float = 1e-4, max_ls: int = 10, gtol: float = 1e-6,
+               step0: Optional[float] = None, sinc=None, opts: Optional[SolverOpts] = None,
+               max_records: int = 100000, raise_on_failure: bool = False):
+    """Inversion by frequency continuation, stochastic source subsets and a
+    box-constrained L-BFGS (fwi_invert / fwi_invert_offgrid); m (device,
+    the grid's real dtype) is overwritten by the result.
+
+    lo, hi: floats, or float64 device tensors of N values (lo = hi clamps a
+    point).  step0 defaults to 5 % of the range the bounds span,
+    max(hi) - min(lo).  The other
+    arguments are those of misfit_gradient and of ``helm_fwi_params``.
+    Returns (draws, records, sources): one dict per draw, one dict per
+    L-BFGS iteration (the first max_records), and the sources of every draw
+    ([draws][nsrc], -1 padded)."""
+    dev = m.device.index or 0
+    om = np.ascontiguousarray(np.atleast_1d(np.asarray(omega, dtype=np.float64)).ravel())
+    nfreq = len(om)
+    src_a, rec_a, PT = _points(src, rec, sinc)
+    nsrc, nrec = len(src_a), len(rec_a)
+    amp_p = None
+    if src_amp is not None:
+        amp = np.broadcast_to(np.asarray(src_amp, np.complex128), (nfreq, nsrc))
+        amp_d = np.ascontiguousarray(np.stack([amp.real, amp.imag], axis=-1).ravel())
+        amp_p = amp_d.ctypes.data_as(C.POINTER(C.c_double))
+    bounds = []
+    for b in (lo, hi):
+        if isinstance(b, torch.Tensor):
+            bounds.append((_dev_tensor(b, torch.float64, grid.N, "bound"), 0.0))
+        else:
+            bounds.append((None, float(b)))
+    if step0 is None:
+        width = [float((b.max() if i else -b.min()).item()) if isinstance(b, torch.Tensor) else
+                 (float(b) if i else -float(b)) for i, b in enumerate((lo, hi))]
+        step0 = 0.05 * (width[0] + width[1])
+    p = L.helm_fwi_params(band_size, band_overlap, r_sub, memory, batch, subproblems, batch_increase,
+                          max_ls, seed & ((1 << 64) - 1), c1, gtol, float(step0), bounds[0][1], bounds[1][1])
+    lib = L.load()
+    ndraw = lib.helm_fwi_draw_count(nfreq, C.byref(p))
+    if ndraw < 0:
+        raise HelmError(L.HELM_E_INVAL, "invalid inversion parameters")
+    draws = (L.helm_fwi_draw * ndraw)()
+    sources = np.full(ndraw * nsrc, -1, np.int32)
+    recs = (L.helm_fwi_record * max(1, max_records))()
+    nrecs = C.c_int(0)
+    opts = opts or SolverOpts()
+    ctx = _context(dev)
+    g, o = grid.c_struct(), opts.c_struct()
+    geo = (nrec, rec_a.ctypes.data_as(PT)) if sinc is None else \
+        (nrec, rec_a.ctypes.data_as(PT), int(sinc[0]), float(sinc[1]))
+    fn = lib.fwi_invert if sinc is None else lib.fwi_invert_offgrid
+    st = fn(ctx, C.byref(g), _dev_tensor(m, grid.real_dtype, grid.N, "m"), bounds[0][0], bounds[1][0], nfreq,
+            om.ctypes.data_as(C.POINTER(C.c_double)), nsrc, src_a.ctypes.data_as(PT), amp_p, *geo,
+            _dev_tensor(d, grid.complex_dtype, nfreq * nsrc * nrec, "d"), C.byref(p), C.byref(o), draws,
+            sources.ctypes.data_as(C.POINTER(C.c_int32)), recs, max_records, C.byref(nrecs), _stream(dev))
+    allow = (L.HELM_OK,) if raise_on_failure else (L.HELM_OK, L.HELM_NOT_CONVERGED, L.HELM_BREAKDOWN)
+    _check(ctx, st, allow)
+    fields = lambda s: {k: getattr(s, k) for k, _ in s._fields_ if k != "pad_"}
+    return ([fields(x) for x in draws], [fields(x) for x in list(recs)[:min(nrecs.value, max_records)]],
+            sources.reshape(ndraw, nsrc))
+
+
 def version() -> str:
     return L.load().helm_version().decode()
 

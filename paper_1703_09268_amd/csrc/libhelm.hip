@@ -13,6 +13,7 @@
 
 #include "common.h"
 #include "fwi.hip"
+#include "lbfgs.hip"
 #include "noalloc.hip"
 #include "solver.hip"
 
@@ -38,6 +39,7 @@ struct helm_ctx {
   helm::DevBuf fwi_buf;          // sources / fields scratch of misfit_gradient
   helm::DevBuf fwi_small;
   helm::DevBuf batch_buf;        // concatenated q / u of a batched solve
+  helm::DevBuf drv_buf;          // L-BFGS vectors of the inversion driver
   CachedSolver solver;
   std::unique_ptr<helm::Hierarchy> apply_h;  // operator of the last helm_apply
   std::string apply_key;
@@ -918,6 +920,8 @@ helm_status derivative_common(helm_ctx* ctx, int mode, const helm_grid* g, const
                               so, info, stream);
 }
 
+#include "driver.hip"
+
 }  // namespace
 
 extern "C" {
@@ -1143,6 +1147,47 @@ helm_status pde_derivative_offgrid(helm_ctx* ctx, int mode, const helm_grid* g, 
     return derivative_common(ctx, mode, g, m, nfreq, omega, sinc_points(g, nsrc, src_pos, radius, kaiser_b),
                              src_amp, mask, sinc_points(g, nrec, rec_pos, radius, kaiser_b), input, d, output,
                              u_store, flags, o, info, stream);
+  });
+}
+
+int helm_fwi_draw_count(int nfreq, const helm_fwi_params* p) {
+  try {
+    HELM_REQUIRE(nfreq >= 1, "nfreq must be >= 1");
+    check_fwi_params(p);
+    return fwi_band_count(nfreq, p->band_size, p->band_overlap) * p->subproblems;
+  } catch (...) {
+    return -1;
+  }
+}
+
+helm_status fwi_invert(helm_ctx* ctx, const helm_grid* g, void* m, const double* lo, const double* hi, int nfreq,
+                       const double* omega, int nsrc, const int32_t* src_idx, const double* src_amp, int nrec,
+                       const int32_t* rec_idx, const void* d, const helm_fwi_params* p, const helm_solver_opts* o,
+                       helm_fwi_draw* draws, int32_t* sources, helm_fwi_record* recs, int rec_cap, int* nrecs,
+                       void* stream) {
+  return guarded(ctx, [&]() -> helm_status {
+    check_pair_args(g, m, nfreq, omega, nsrc, nrec);
+    HELM_REQUIRE(src_idx && rec_idx, "null source / receiver index array");
+    check_nodes(g, nsrc, src_idx, "source outside the grid");
+    check_nodes(g, nrec, rec_idx, "receiver outside the grid");
+    return fwi_common(ctx, g, m, lo, hi, nfreq, omega, on_node_points(g, nsrc, src_idx), src_amp,
+                      on_node_points(g, nrec, rec_idx), d, p, o, draws, sources, recs, rec_cap, nrecs, stream);
+  });
+}
+
+helm_status fwi_invert_offgrid(helm_ctx* ctx, const helm_grid* g, void* m, const double* lo, const double* hi,
+                               int nfreq, const double* omega, int nsrc, const double* src_pos,
+                               const double* src_amp, int nrec, const double* rec_pos, int radius, double kaiser_b,
+                               const void* d, const helm_fwi_params* p, const helm_solver_opts* o,
+                               helm_fwi_draw* draws, int32_t* sources, helm_fwi_record* recs, int rec_cap,
+                               int* nrecs, void* stream) {
+  return guarded(ctx, [&]() -> helm_status {
+    check_pair_args(g, m, nfreq, omega, nsrc, nrec);
+    HELM_REQUIRE(src_pos && rec_pos, "null source / receiver position array");
+    check_sinc(g, nsrc, src_pos, nrec, rec_pos, radius, kaiser_b);
+    return fwi_common(ctx, g, m, lo, hi, nfreq, omega, sinc_points(g, nsrc, src_pos, radius, kaiser_b), src_amp,
+                      sinc_points(g, nrec, rec_pos, radius, kaiser_b), d, p, o, draws, sources, recs, rec_cap, nrecs,
+                      stream);
   });
 }
 

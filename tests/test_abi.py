@@ -16,7 +16,7 @@ HEADER = os.path.join(ROOT, "include", "helm.h")
 def _declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"\b(?:helm_status|size_t|void|const char\*)\s+(\w+)\s*\(", text)
+    names = re.findall(r"\b(?:helm_status|size_t|void|int|const char\*)\s+(\w+)\s*\(", text)
     return sorted(set(names))
 
 
@@ -76,3 +76,51 @@ def test_null_context_is_rejected(lib):
     st = lib.helm_apply(None, C.byref(g), None, 1.0, 0, 1, None, None, None)
     assert st == L.HELM_E_INVAL
     assert b"context" in lib.helm_last_error(None)
+
+
+def _fwi_params(**kw):
+    p = L.helm_fwi_params(4, 2, 20, 5, 0, 1, 1, 10, 0, 1e-4, 1e-6, 1e-8, 0.0, 1.0)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def test_fwi_draw_count(lib):
+    """bands x draws: 10 frequencies in bands of 4 overlapping by 2 give 4
+    bands (the 2D example's layout); 11 give 5; invalid parameters -1."""
+    cnt = lambda nf, **kw: lib.helm_fwi_draw_count(nf, C.byref(_fwi_params(**kw)))
+    assert cnt(10) == 4 and cnt(11) == 5 and cnt(3) == 1
+    assert cnt(10, subproblems=3) == 12
+    assert cnt(5, band_size=1, band_overlap=0) == 5
+    assert cnt(10, band_overlap=4) == -1 and cnt(10, memory=17) == -1 and cnt(0) == -1
+    assert cnt(10, step0=0.0) == -1 and cnt(10, c1=1.0) == -1
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """sizeof / offsetof of every struct of include/helm.h, compiled by the
+    host C compiler, equal the ctypes mirrors."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"helm_grid": L.helm_grid, "helm_solver_opts": L.helm_solver_opts,
+               "helm_solve_info": L.helm_solve_info, "helm_problem": L.helm_problem,
+               "helm_fwi_params": L.helm_fwi_params, "helm_fwi_draw": L.helm_fwi_draw,
+               "helm_fwi_record": L.helm_fwi_record}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "helm.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                       text=True).stdout.splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == C.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert int(got[f"{name}.{f}"]) == getattr(cls, f).offset, f"{name}.{f}"
