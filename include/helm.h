@@ -374,6 +374,46 @@ helm_status pde_derivative_offgrid(helm_ctx* ctx, int mode,
                                    const helm_solver_opts* o,
                                    helm_solve_info* info, void* stream);
 
+/* Wavefield Reconstruction Inversion (the paper's penalty method: Penalty
+ * Method subsection, eqs. wri and wrifieldeq; Appendix B, derivative
+ * expressions for WRI), summed over the selected (frequency, source) pairs.
+ * Per pair, with q, P_r, the amplitudes, mask and c as in misfit_gradient:
+ *   u_fs = argmin_u 1/2 ||P_r u - d_fs||^2 + lambda^2/2 ||H_f u - q_fs||^2,
+ *          i.e. (P_r^T P_r + lambda^2 H^H H) u = P_r^T d + lambda^2 H^H q
+ *   f    = c sum (1/2 ||P_r u_fs - d_fs||^2 + lambda^2/2 ||H_f u_fs - q_fs||^2)
+ *   g    = c sum lambda^2 Re(omega_f^2 conj(u_fs) * (A^H (H_f u_fs - q_fs)))
+ * The field is computed as u = H^{-1}(q + H^{-H} P_r^T y) with y from
+ * conjugate gradients on the receiver-space system
+ * (P_r H^{-1} H^{-H} P_r^T + lambda^2 I) y = d - P_r H^{-1} q, started at
+ * y = 0 and stopped when its residual falls to cg_tol times the initial one
+ * (or after cg_max steps); every step costs one adjoint and one forward
+ * ML-GMRES solve per active pair, all pairs batched.  The field is
+ * accumulated in FP64 and H u - q formed in FP64.
+ * Arguments as misfit_gradient, plus:
+ *   lambda   penalty weight (> 0)
+ *   cg_tol   relative residual target of the receiver-space CG, [0, 1)
+ *   cg_max   CG step limit (>= 0; 0 returns the reduced field H^{-1} q)
+ *   u_store  dev or NULL: receives the WRI fields of the selected pairs
+ *            ([nfreq][nsrc][N], complex128 with HELM_MG_U_FP64)
+ *   flags    HELM_MG_FORWARD_ONLY (f only), HELM_MG_ACCUMULATE,
+ *            HELM_MG_U_FP64, HELM_MG_RENORMALISE
+ *   info     host, nfreq*nsrc entries or NULL: the CG of pair (f, s) at
+ *            f*nsrc + s: status (0 converged, 1 step limit, 2 breakdown),
+ *            cycles = CG steps, matvecs = ML-GMRES solves (1 + 2 steps),
+ *            relres_fp64 = final CG relative residual
+ * Invalid arguments return HELM_E_INVAL before any device work.  Returns
+ * the worst of the solves' and the CGs' statuses. */
+helm_status wri_misfit_gradient(helm_ctx* ctx, const helm_grid* g,
+                                const void* m, int nfreq, const double* omega,
+                                int nsrc, const int32_t* src_idx,
+                                const double* src_amp, const uint8_t* mask,
+                                int nrec, const int32_t* rec_idx,
+                                const void* d, double lambda, double cg_tol,
+                                int cg_max, double* f, void* grad,
+                                void* u_store, int flags,
+                                const helm_solver_opts* o,
+                                helm_solve_info* info, void* stream);
+
 /* Parameters of the inversion driver (fwi_invert). */
 typedef struct {
   int32_t band_size;      /* frequencies per band (>= 1)                      */

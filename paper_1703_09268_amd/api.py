@@ -399,6 +399,60 @@ def pde_derivative(mode: str, grid: Grid, m: torch.Tensor, omega, src, rec, inpu
     return out, inf
 
 
+def wri_misfit_gradient(grid: Grid, m: torch.Tensor, omega, src, rec, d: torch.Tensor, lam: float,
+                        src_amp=None, mask=None, grad: Optional[torch.Tensor] = None,
+                        u_store: Optional[torch.Tensor] = None, forward_only: bool = False,
+                        accumulate: bool = False, u_fp64: bool = False, renormalise: bool = False,
+                        cg_tol: float = 1e-6, cg_max: int = 200, opts: Optional[SolverOpts] = None,
+                        raise_on_failure: bool = True):
+    """WRI (penalty method) objective and gradient over the selected
+    (frequency, source) pairs (wri_misfit_gradient): the arguments of
+    misfit_gradient (on-node geometry) plus the penalty weight lam and the
+    receiver-space CG's tolerance and step limit.  Returns (f, grad, infos)
+    with one SolveInfo per pair ([frequency][source] order) describing its
+    CG: status, cycles = CG steps, matvecs = ML-GMRES solves, relres = the
+    CG's final relative residual."""
+    if u_fp64 and u_store is None:
+        raise ValueError("u_fp64 needs u_store")
+    dev = m.device.index or 0
+    om = np.ascontiguousarray(np.atleast_1d(np.asarray(omega, dtype=np.float64)).ravel())
+    nfreq = len(om)
+    src_a, rec_a, PT = _points(src, rec, None)
+    nsrc, nrec = len(src_a), len(rec_a)
+    amp_p = None
+    if src_amp is not None:
+        amp = np.broadcast_to(np.asarray(src_amp, np.complex128), (nfreq, nsrc))
+        amp_d = np.ascontiguousarray(np.stack([amp.real, amp.imag], axis=-1).ravel())
+        amp_p = amp_d.ctypes.data_as(C.POINTER(C.c_double))
+    mask_p = None
+    if mask is not None:
+        mask_a = np.ascontiguousarray(np.broadcast_to(np.asarray(mask, bool), (nfreq, nsrc)).astype(np.uint8))
+        mask_p = mask_a.ctypes.data_as(C.POINTER(C.c_uint8))
+    flags = (L.HELM_MG_FORWARD_ONLY if forward_only else 0) | (L.HELM_MG_ACCUMULATE if accumulate else 0) | \
+        (L.HELM_MG_U_FP64 if u_fp64 else 0) | (L.HELM_MG_RENORMALISE if renormalise else 0)
+    if grad is None and not forward_only:
+        grad = torch.empty(tuple(grid.n), dtype=grid.real_dtype, device=m.device)
+    opts = opts or SolverOpts()
+    npair = nfreq * nsrc
+    infos = (L.helm_solve_info * npair)()
+    f = C.c_double(0.0)
+    ctx = _context(dev)
+    g, o = grid.c_struct(), opts.c_struct()
+    u_dtype = torch.complex128 if u_fp64 else grid.complex_dtype
+    st = L.load().wri_misfit_gradient(
+        ctx, C.byref(g), _dev_tensor(m, grid.real_dtype, grid.N, "m"), nfreq,
+        om.ctypes.data_as(C.POINTER(C.c_double)), nsrc, src_a.ctypes.data_as(PT), amp_p, mask_p, nrec,
+        rec_a.ctypes.data_as(PT), _dev_tensor(d, grid.complex_dtype, npair * nrec, "d"), float(lam),
+        float(cg_tol), int(cg_max), C.byref(f),
+        None if grad is None else _dev_tensor(grad, grid.real_dtype, grid.N, "grad"),
+        None if u_store is None else _dev_tensor(u_store, u_dtype, npair * grid.N, "u_store"),
+        flags, C.byref(o), infos, _stream(dev))
+    allow = (L.HELM_OK,) if raise_on_failure else (L.HELM_OK, L.HELM_NOT_CONVERGED, L.HELM_BREAKDOWN)
+    _check(ctx, st, allow)
+    inf = [SolveInfo(i.status, i.cycles, i.inner_its, i.matvecs, i.relres_fp64) for i in infos]
+    return f.value, grad, inf
+
+
 def fwi_invert(grid: Grid, m: torch.Tensor, omega, src, rec, d: torch.Tensor, lo, hi,
                src_amp=None, band_size: int = 4, band_overlap: int = 2, r_sub: int = 20,
                memory: int = 5, batch: int = 0, subproblems: int = 1, batch_increase: int = 1,

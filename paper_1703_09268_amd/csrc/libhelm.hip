@@ -14,6 +14,7 @@
 #include "common.h"
 #include "fwi.hip"
 #include "lbfgs.hip"
+#include "wri.hip"
 #include "noalloc.hip"
 #include "solver.hip"
 
@@ -849,6 +850,186 @@ helm_status derivative_t(helm_ctx* ctx, int mode, const helm_grid* g, const void
 }
 
 // Argument checks shared by the misfit and derivative entry points.
+// WRI objective and gradient over the selected (frequency, source) pairs
+// (Penalty Method subsection, eqs. wri and wrifieldeq; Appendix B):
+//   u  = argmin 1/2 ||P_r u - d||^2 + lambda^2/2 ||H u - q||^2
+//      = u0 + H^{-1} H^{-H} P_r^T y,  u0 = H^{-1} q,
+//        (P_r H^{-1} H^{-H} P_r^T + lambda^2 I) y = d - P_r u0   (CG, per pair)
+//   f  = c sum (1/2 ||P_r u - d||^2 + lambda^2/2 ||H u - q||^2)
+//   g  = c sum lambda^2 Re(omega^2 conj(u) (A^H (H u - q)))
+// Per CG step every active pair costs one adjoint and one forward solve,
+// batched over the pairs; converged pairs get a zero right-hand side (their
+// solves drop out at once).  The field is accumulated in FP64 from the
+// solves' FP64 outer iterates, and H u - q is formed in FP64.
+template <typename T>
+helm_status wri_t(helm_ctx* ctx, const helm_grid* g, const void* m, int nfreq, const double* omega,
+                  const PointSet& src, const double* src_amp, const uint8_t* mask, const PointSet& rec,
+                  const void* d, double lam, double cg_tol, int cg_max, double* f, void* grad, void* u_store,
+                  int flags, const helm::SolveOpts& o, helm_solve_info* info, void* caller) {
+  using namespace helm;
+  hipStream_t st = solve_stream(ctx, caller);
+  const bool fwd_only = (flags & HELM_MG_FORWARD_ONLY) != 0;
+  const bool acc = (flags & HELM_MG_ACCUMULATE) != 0;
+  const bool u64 = (flags & HELM_MG_U_FP64) != 0;
+  const int nall = nfreq * src.n();
+  if (info)
+    for (int k = 0; k < nall; ++k) to_info(SolveInfo(), info + k);
+  Pairs<T> P = plan_pairs<T>(ctx, g, m, nfreq, omega, src, src_amp, mask, rec, (flags & HELM_MG_RENORMALISE) != 0,
+                             st);
+  const int64_t N = P.N;
+  if (P.np == 0) {
+    *f = 0.0;
+    if (!fwd_only && !acc) HELM_HIP_CHECK(hipMemsetAsync(grad, 0, (size_t)N * sizeof(T), st));
+    HELM_HIP_CHECK(hipStreamSynchronize(st));
+    return HELM_OK;
+  }
+  const int np = P.np, nrec = P.nrec, rblk = P.rblk;
+  const double lam2 = lam * lam;
+  auto r256 = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t fb = r256((size_t)np * N * sizeof(cx<T>)), ub = r256((size_t)np * N * sizeof(cx<double>));
+  const size_t rb = r256((size_t)np * nrec * sizeof(cx<double>)), pb = r256((size_t)np * rblk * sizeof(double));
+  const size_t sb = r256((size_t)np * sizeof(double));
+  ctx->fwi_buf.ensure(3 * fb + ub + 3 * rb + pb + 2 * sb);
+  char* base = (char*)ctx->fwi_buf.p;
+  cx<T>* Q = (cx<T>*)base;
+  cx<T>* B = (cx<T>*)(base + fb);
+  cx<T>* W = (cx<T>*)(base + 2 * fb);
+  cx<double>* U = (cx<double>*)(base + 3 * fb);
+  char* rbase = base + 3 * fb + ub;
+  cx<double>* rho = (cx<double>*)rbase;
+  cx<double>* pv = (cx<double>*)(rbase + rb);
+  cx<double>* ap = (cx<double>*)(rbase + 2 * rb);
+  double* part = (double*)(rbase + 3 * rb);
+  double* alpha_d = (double*)(rbase + 3 * rb + pb);
+  double* beta_d = (double*)(rbase + 3 * rb + pb + sb);
+
+  Solver<T>& S = solver_for<T>(ctx, P.probs, o, st);
+  std::vector<SolveInfo> inf(np);
+  int worst = 0;
+  const cx<double>* fwd64 = nullptr;
+  forward_fields<T>(g, P, S, Q, W, nullptr, false, false, inf, nullptr, worst, &fwd64, st);
+  HELM_HIP_CHECK(hipMemcpyAsync(U, fwd64, (size_t)np * N * sizeof(cx<double>), hipMemcpyDeviceToDevice, st));
+  // Q still holds the sources (forward_fields solved into W)
+  std::vector<double> hp((size_t)np * rblk);
+  auto pair_sums = [&]() {
+    HELM_HIP_CHECK(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HELM_HIP_CHECK(hipStreamSynchronize(st));
+    std::vector<double> out(np, 0.0);
+    for (int p = 0; p < np; ++p)
+      for (int b = 0; b < rblk; ++b) out[p] += hp[(size_t)p * rblk + b];
+    return out;
+  };
+  const dim3 rgrid(rblk, np);
+  hipLaunchKernelGGL((k_wri_start<T>), rgrid, dim3(256), 0, st, (const cx<double>*)U, (const int64_t*)P.uoff_int,
+                     (const int*)P.rptr, (const int64_t*)P.rlin, (const double*)P.rw, nrec, (const cx<T>*)d,
+                     (const int64_t*)P.drow, rho, pv, part);
+  HELM_HIP_CHECK(hipGetLastError());
+  const std::vector<double> rr0 = pair_sums();
+  std::vector<double> rr = rr0, alpha(np), beta(np), rel(np, 0.0);
+  std::vector<int> active(np), iters(np, 0), solves(np, 1), cg_status(np, 0);
+  for (int p = 0; p < np; ++p) {
+    active[p] = rr0[p] > 0.0 && std::isfinite(rr0[p]);
+    if (!std::isfinite(rr0[p])) cg_status[p] = 2;
+  }
+  const unsigned fblk = std::min<unsigned>(1024, ceil_div(N, 256));
+  for (int it = 0; it < cg_max; ++it) {
+    int n_active = 0;
+    for (int p = 0; p < np; ++p) n_active += active[p];
+    if (n_active == 0) break;
+    // z = H^{-1} H^{-H} P_r^T p
+    hipLaunchKernelGGL((k_fill_zero<T>), dim3(std::min<unsigned>(65536, ceil_div((int64_t)np * N, 256))), dim3(256),
+                       0, st, B, (int64_t)np * N);
+    hipLaunchKernelGGL((k_wri_spread<T>), dim3(ceil_div(P.nnode, 256), np), dim3(256), 0, st, B, N,
+                       (const int64_t*)P.node, (const int*)P.nptr, (const int*)P.nrec_ord, (const double*)P.node_w,
+                       P.nnode, (const cx<double>*)pv, nrec);
+    HELM_HIP_CHECK(hipGetLastError());
+    worst = std::max(worst, S.solve(1, B, W, inf.data()));
+    worst = std::max(worst, S.solve(0, W, B, inf.data()));
+    const cx<double>* z = S.iterate();
+    hipLaunchKernelGGL(k_wri_apply, rgrid, dim3(256), 0, st, z, N, (const int*)P.rptr, (const int64_t*)P.rlin,
+                       (const double*)P.rw, nrec, lam2, (const cx<double>*)pv, ap, part);
+    HELM_HIP_CHECK(hipGetLastError());
+    const std::vector<double> pap = pair_sums();
+    for (int p = 0; p < np; ++p) {
+      alpha[p] = 0.0;
+      if (!active[p]) continue;
+      if (!(pap[p] > 0.0) || !std::isfinite(pap[p])) {  // breakdown: keep the field so far
+        active[p] = 0;
+        cg_status[p] = 2;
+        continue;
+      }
+      alpha[p] = rr[p] / pap[p];
+    }
+    HELM_HIP_CHECK(hipMemcpyAsync(alpha_d, alpha.data(), np * sizeof(double), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_wri_field, dim3(fblk, np), dim3(256), 0, st, U, z, (const double*)alpha_d, N);
+    hipLaunchKernelGGL(k_wri_residual, rgrid, dim3(256), 0, st, rho, (const cx<double>*)ap, (const double*)alpha_d,
+                       nrec, part);
+    HELM_HIP_CHECK(hipGetLastError());
+    const std::vector<double> rrn = pair_sums();
+    for (int p = 0; p < np; ++p) {
+      beta[p] = -1.0;
+      if (!active[p]) continue;
+      iters[p] += 1;
+      solves[p] += 2;
+      rel[p] = std::sqrt(rrn[p] / rr0[p]);
+      if (rel[p] <= cg_tol) {
+        active[p] = 0;
+      } else {
+        beta[p] = rrn[p] / rr[p];
+        rr[p] = rrn[p];
+      }
+    }
+    HELM_HIP_CHECK(hipMemcpyAsync(beta_d, beta.data(), np * sizeof(double), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_wri_direction, rgrid, dim3(256), 0, st, pv, (const cx<double>*)rho, (const double*)beta_d,
+                       nrec);
+    HELM_HIP_CHECK(hipGetLastError());
+  }
+  for (int p = 0; p < np; ++p)
+    if (active[p]) cg_status[p] = std::max(cg_status[p], 1);  // iteration limit reached
+  // objective: data term from the FP64 field, penalty term ||q - H u|| in FP64
+  launch_residual<T>(P, U, FieldRef{U, P.uoff_int, true}, d, st);
+  const double f_data = 0.5 * residual_norm2<T>(P, st);
+  const std::vector<double> en = S.residual(0, U, Q, W);  // W = q - H u (rounded)
+  double f_pen = 0.0;
+  for (int p = 0; p < np; ++p) f_pen += en[p] * en[p];
+  *f = (f_data + 0.5 * lam2 * f_pen) * P.scale;
+  if (u_store) {
+    const unsigned pbk = std::min<unsigned>(65536, ceil_div(N, 256));
+    for (int p = 0; p < np; ++p) {
+      if (u64)
+        HELM_HIP_CHECK(hipMemcpyAsync((cx<double>*)u_store + P.prow[p] * N, U + (int64_t)p * N,
+                                      N * sizeof(cx<double>), hipMemcpyDeviceToDevice, st));
+      else
+        hipLaunchKernelGGL((k_convert<T, double>), dim3(pbk), dim3(256), 0, st, (const cx<double>*)(U + p * N),
+                           (cx<T>*)u_store + P.prow[p] * N, N);
+    }
+  }
+  if (!fwd_only) {
+    // g = c lambda^2 sum Re(omega^2 conj(u) A (H u - q)) = -c lambda^2 sum Re(omega^2 conj(u) A W)
+    std::vector<double> wg(np);
+    for (int p = 0; p < np; ++p) {
+      const double om = omega[P.prow[p] / P.nsrc];
+      wg[p] = -lam2 * om * om * P.scale;
+    }
+    HELM_HIP_CHECK(hipMemcpyAsync(P.wg, wg.data(), np * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_gradient<T>(g, P, FieldRef{U, P.uoff_int, true}, W, grad, acc, st);
+  }
+  HELM_HIP_CHECK(hipStreamSynchronize(st));
+  for (int p = 0; p < np; ++p) {
+    worst = std::max(worst, cg_status[p]);
+    if (info) {
+      helm_solve_info& r = info[P.prow[p]];
+      r.status = cg_status[p];
+      r.cycles = iters[p];
+      r.inner_its = 0;
+      r.pad_ = 0;
+      r.matvecs = solves[p];
+      r.relres_fp64 = rel[p];
+    }
+  }
+  return (helm_status)worst;
+}
+
 void check_pair_args(const helm_grid* g, const void* m, int nfreq, const double* omega, int nsrc, int nrec) {
   check_grid(g);
   HELM_REQUIRE(m, "null model pointer");
@@ -1188,6 +1369,35 @@ helm_status fwi_invert_offgrid(helm_ctx* ctx, const helm_grid* g, void* m, const
     return fwi_common(ctx, g, m, lo, hi, nfreq, omega, sinc_points(g, nsrc, src_pos, radius, kaiser_b), src_amp,
                       sinc_points(g, nrec, rec_pos, radius, kaiser_b), d, p, o, draws, sources, recs, rec_cap, nrecs,
                       stream);
+  });
+}
+
+helm_status wri_misfit_gradient(helm_ctx* ctx, const helm_grid* g, const void* m, int nfreq,
+                                const double* omega, int nsrc, const int32_t* src_idx, const double* src_amp,
+                                const uint8_t* mask, int nrec, const int32_t* rec_idx, const void* d, double lambda,
+                                double cg_tol, int cg_max, double* f, void* grad, void* u_store, int flags,
+                                const helm_solver_opts* o, helm_solve_info* info, void* stream) {
+  return guarded(ctx, [&]() -> helm_status {
+    check_pair_args(g, m, nfreq, omega, nsrc, nrec);
+    HELM_REQUIRE(src_idx && rec_idx, "null source / receiver index array");
+    check_nodes(g, nsrc, src_idx, "source outside the grid");
+    check_nodes(g, nrec, rec_idx, "receiver outside the grid");
+    HELM_REQUIRE(d && f, "null pointer argument");
+    HELM_REQUIRE((flags & HELM_MG_FORWARD_ONLY) || grad, "null gradient");
+    HELM_REQUIRE(!(flags & HELM_MG_U_FP64) || u_store, "HELM_MG_U_FP64 needs u_store");
+    HELM_REQUIRE((flags & ~(HELM_MG_FORWARD_ONLY | HELM_MG_ACCUMULATE | HELM_MG_U_FP64 | HELM_MG_RENORMALISE)) == 0,
+                 "unknown or unsupported flag bits");
+    HELM_REQUIRE(lambda > 0.0 && std::isfinite(lambda), "lambda must be positive");
+    HELM_REQUIRE(cg_tol >= 0.0 && cg_tol < 1.0, "cg_tol must be in [0, 1)");
+    HELM_REQUIRE(cg_max >= 0, "cg_max must be >= 0");
+    const helm::SolveOpts so = opts_of(o);
+    check_coarse_sizes(g, so);
+    const PointSet S = on_node_points(g, nsrc, src_idx), R = on_node_points(g, nrec, rec_idx);
+    if (g->dtype == HELM_C64)
+      return wri_t<float>(ctx, g, m, nfreq, omega, S, src_amp, mask, R, d, lambda, cg_tol, cg_max, f, grad, u_store,
+                          flags, so, info, stream);
+    return wri_t<double>(ctx, g, m, nfreq, omega, S, src_amp, mask, R, d, lambda, cg_tol, cg_max, f, grad, u_store,
+                         flags, so, info, stream);
   });
 }
 

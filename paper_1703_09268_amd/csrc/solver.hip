@@ -189,6 +189,24 @@ class Solver {
     return worst;
   }
 
+  // r = q - H x (dir 0) or q - H^H x (dir 1) for every segment, formed in
+  // FP64 from an FP64 x (level-0 layout) and rounded to T; returns the FP64
+  // norms ||r|| per segment.
+  std::vector<double> residual(int dir, const cx<double>* x, const cx<T>* q, cx<T>* r) {
+    HELM_REQUIRE(dir == 0 || dir == 1, "direction must be 0 (H) or 1 (H^H)");
+    dir_ = dir;
+    H_->set_dir(dir);
+    const LevelSet& L = H_->level(0);
+    const int rng = launch_h<double, double, T, T, T, true, true>(L, x, nullptr, q, nullptr, r, part_,
+                                                                  (const int*)nullptr, st_);
+    hipLaunchKernelGGL(k_seg_norm, dim3(nseg_), dim3(256), 0, st_, L.d(), (const double*)part_, rng, beta_dev_);
+    HELM_HIP_CHECK(hipGetLastError());
+    std::vector<double> out(nseg_);
+    HELM_HIP_CHECK(hipMemcpyAsync(out.data(), beta_dev_, nseg_ * sizeof(double), hipMemcpyDeviceToHost, st_));
+    HELM_HIP_CHECK(hipStreamSynchronize(st_));
+    return out;
+  }
+
   static size_t workspace_bytes(const std::vector<int64_t>& Nlev, const SolveOpts& o) {
     // Nlev[l] = total points of all segments on level l
     size_t total = 0;
