@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <sys/stat.h>
 #include <map>
 #include <mutex>
 #include <memory>
@@ -238,6 +239,7 @@ struct LevelSet {
   int nsblk = 0, nvblk = 0, ntblk = 0;
   int sblk_bound = 1;  // stencil workgroups at the smallest x chunk
   int xchunk = 0;      // current x chunk of the stencil tiles
+  int interleave = 0;  // 1: the segments of a tile get consecutive workgroups (segment fastest)
   bool pair = false;   // every segment uses pair stencil tiles
   int stage27 = 0;     // LDS bytes per workgroup of the staged 27-point pass (0: register path)
   int64_t total = 0;  // vector length (sum of N)
@@ -458,13 +460,28 @@ class Hierarchy {
     }
   }
 
+  // Whether level l's stencil tiles may interleave the segments: several
+  // segments of one grid and one model, on a tiled stencil path.
+  bool can_interleave(int l) const {
+    const LevelSet& L = *lev_[l];
+    const int ns = (int)L.host.size();
+    bool ok = (stencil_ == 0 || L.pair) && ns > 1;
+    for (int s = 1; s < ns && ok; ++s)
+      ok = L.host[s].m == L.host[0].m && L.host[s].n[0] == L.host[0].n[0] &&
+           L.host[s].n[1] == L.host[0].n[1] && L.host[s].n[2] == L.host[0].n[2];
+    return ok;
+  }
+
   // Stencil workgroup layout of level l for x chunk `xchunk`: segment ranges,
   // workgroup -> (segment, tile) maps, uploaded.  When every segment of a
   // small level has the same geometry and model (the sources of one
   // frequency), the segments of one tile get consecutive workgroup ids
   // (segment fastest), so they run together on one XCD and read that tile of
   // the model once into its L2.
-  void layout_stencil(int l, int xchunk) {
+  // interleave: -1 chooses (the size rule below, or HELM_INTERLEAVE), 0 / 1
+  // forces segment-major / segment-fastest order where the segments share
+  // grid and model (segment-major otherwise).
+  void layout_stencil(int l, int xchunk, int interleave = -1) {
     LevelSet& L = *lev_[l];
     const int ns = (int)L.host.size();
     xchunk = std::max(xchunk, kMinXchunk);
@@ -485,11 +502,10 @@ class Hierarchy {
     // tile's distinct data; on 128^3 and larger, keeping one right-hand
     // side's neighbouring tiles on one XCD is worth more)
     const char* il = std::getenv("HELM_INTERLEAVE");  // 1 / 0: force on / off (tile experiments)
-    bool shared = (stencil_ == 0 || L.pair) && ns > 1 &&
-                  (il ? il[0] == '1' : L.host[0].N <= ((int64_t)1 << 20));
-    for (int s = 1; s < ns && shared; ++s)
-      shared = L.host[s].m == L.host[0].m && L.host[s].n[0] == L.host[0].n[0] &&
-               L.host[s].n[1] == L.host[0].n[1] && L.host[s].n[2] == L.host[0].n[2];
+    const bool want = interleave >= 0 ? interleave == 1
+                                      : (il ? il[0] == '1' : L.host[0].N <= ((int64_t)1 << 20));
+    const bool shared = want && can_interleave(l);
+    L.interleave = shared ? 1 : 0;
     for (int s = 0; s < ns; ++s) {
       const Seg& S = L.host[s];
       for (int b = 0; b < S.snblk; ++b) {
@@ -659,31 +675,103 @@ int launch_h(const LevelSet& L, const cx<TX>* x, const double* xs, const cx<TB>*
   return launch_h<TC, TX, TM, TB, TO, RESID, NORM>(L.view(), x, xs, b, bs, out, part, active, st);
 }
 
-// Tile tuner (7-point levels): time a stencil launch for a few x chunks and
-// keep the fastest.  The choice is cached per tile key for the process,
-// so one problem set, in any order, always gets the same tiles and hence the
-// same results.  Fixed tiles with HELM_XCHUNK / HELM_STENCIL_WG; off with
-// HELM_AUTOTUNE=0 (heuristic tiles).
-// `run(L)` launches the kernel to time on level L (what the caller runs most
-// there); `kind` names it in the cache key.
+// Tile choice of one level: x chunk of the stencil march and segment order.
+struct TileChoice {
+  int xchunk = 0;
+  int interleave = 0;
+};
+
+// On-disk record of tile choices, so that a problem set gets the same tiles
+// (hence bitwise the same results) in every process on the same kind of GPU:
+// one line "key<TAB>xchunk<TAB>interleave" per choice, in the file named by
+// HELM_TUNE_CACHE (set but empty: no file), else
+// $XDG_CACHE_HOME/helm/tiles.tsv or $HOME/.cache/helm/tiles.tsv.  Keys carry
+// the record format and the device (architecture, compute units).  A file
+// that cannot be read or written is ignored: choices then live for the
+// process only.
+inline std::string tune_cache_path() {
+  if (const char* e = std::getenv("HELM_TUNE_CACHE")) return std::string(e);
+  std::string dir;
+  if (const char* x = std::getenv("XDG_CACHE_HOME")) dir = x;
+  else if (const char* h = std::getenv("HOME")) dir = std::string(h) + "/.cache";
+  if (dir.empty()) return std::string();
+  return dir + "/helm/tiles.tsv";
+}
+
+inline void tune_cache_load(const std::string& path, std::map<std::string, TileChoice>& cache) {
+  if (path.empty()) return;
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return;
+  char line[4096];
+  while (std::fgets(line, sizeof(line), f)) {
+    char* t1 = std::strchr(line, '\t');
+    if (!t1) continue;
+    *t1 = '\0';
+    TileChoice c;
+    if (std::sscanf(t1 + 1, "%d\t%d", &c.xchunk, &c.interleave) == 2 && c.xchunk >= kMinXchunk &&
+        (c.interleave == 0 || c.interleave == 1))
+      cache[line] = c;
+  }
+  std::fclose(f);
+}
+
+inline void tune_cache_store(const std::string& path, const std::string& key, const TileChoice& c) {
+  if (path.empty()) return;
+  const size_t slash = path.rfind('/');
+  if (slash != std::string::npos && slash > 0) {  // the directory and its parent, best effort
+    const std::string dir = path.substr(0, slash);
+    const size_t up = dir.rfind('/');
+    if (up != std::string::npos && up > 0) (void)mkdir(dir.substr(0, up).c_str(), 0755);
+    (void)mkdir(dir.c_str(), 0755);
+  }
+  FILE* f = std::fopen(path.c_str(), "a");
+  if (!f) return;
+  std::fprintf(f, "%s\t%d\t%d\n", key.c_str(), c.xchunk, c.interleave);
+  std::fclose(f);
+}
+
+inline std::string device_tag() {
+  int dev = 0;
+  HELM_HIP_CHECK(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HELM_HIP_CHECK(hipGetDeviceProperties(&prop, dev));
+  return std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount);
+}
+
+// Tile tuner: time a stencil launch for a few x chunks, each with the
+// segment-major and, where the segments share grid and model, the
+// segment-fastest order, and keep the fastest.  The choice is cached per tile
+// key for the process and on disk (see above), so one problem set, in any
+// order, always gets the same tiles and hence the same results.  Fixed tiles
+// with HELM_XCHUNK / HELM_STENCIL_WG; off with HELM_AUTOTUNE=0 (heuristic
+// tiles).  `run(L)` launches the kernel to time on level L (what the caller
+// runs most there); `kind` names it in the cache key.
 template <typename Run>
 void tune_tiles(Hierarchy& H, const std::string& kind, Run run, hipStream_t st) {
   static std::mutex mu;
-  static std::map<std::string, int> cache;
+  static std::map<std::string, TileChoice> cache;
+  static std::string loaded_from = "\x01";  // path the cache was last read from
   if (std::getenv("HELM_XCHUNK") || std::getenv("HELM_STENCIL_WG")) return;
   if (const char* e = std::getenv("HELM_AUTOTUNE"))
     if (e[0] == '0') return;
   std::lock_guard<std::mutex> guard(mu);
+  const std::string path = tune_cache_path();
+  if (path != loaded_from) {
+    tune_cache_load(path, cache);
+    loaded_from = path;
+  }
+  const std::string prefix = "tiles2|" + device_tag() + "|" + kind + "|";
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HELM_HIP_CHECK(hipEventCreate(&e0));
   HELM_HIP_CHECK(hipEventCreate(&e1));
   try {
     for (int l = 0; l < H.nlev(); ++l) {
       if (H.stencil() != 0 && !H.level(l).pair) continue;  // point-wise 27-point kernel: no tiles
-      const std::string key = kind + "|" + H.tile_key(l);
+      const std::string key = prefix + H.tile_key(l);
       auto it = cache.find(key);
       if (it != cache.end()) {
-        if (it->second != H.level(l).xchunk) H.layout_stencil(l, it->second);
+        if (it->second.xchunk != H.level(l).xchunk || it->second.interleave != H.level(l).interleave)
+          H.layout_stencil(l, it->second.xchunk, it->second.interleave);
         continue;
       }
       int nxm = 0;
@@ -692,31 +780,38 @@ void tune_tiles(Hierarchy& H, const std::string& kind, Run run, hipStream_t st) 
       std::vector<int> cand = {H.level(l).xchunk, nxm, (nxm + 1) / 2, (nxm + 3) / 4, 32, 16, 8, kMinXchunk};
       std::sort(cand.begin(), cand.end());
       cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
-      int best = H.level(l).xchunk;
+      std::vector<int> orders = {H.level(l).interleave};
+      if (H.can_interleave(l)) orders.push_back(1 - H.level(l).interleave);
+      TileChoice best{H.level(l).xchunk, H.level(l).interleave};
       float best_ms = 1e30f;
       const bool verbose = std::getenv("HELM_VERBOSE") != nullptr;
       std::string trace;
-      for (int c : cand) {
-        if (c < kMinXchunk || c > std::max(nxm, kMinXchunk)) continue;
-        H.layout_stencil(l, c);
-        const LevelSet& L = H.level(l);
-        run(L);  // warm
-        HELM_HIP_CHECK(hipEventRecord(e0, st));
-        for (int r = 0; r < reps; ++r) run(L);
-        HELM_HIP_CHECK(hipEventRecord(e1, st));
-        HELM_HIP_CHECK(hipEventSynchronize(e1));
-        float ms = 0.f;
-        HELM_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
-        if (verbose) trace += " " + std::to_string(c) + ":" + std::to_string(ms / reps * 1e3f) + "us";
-        if (ms < best_ms) {
-          best_ms = ms;
-          best = c;
+      for (int order : orders) {
+        for (int c : cand) {
+          if (c < kMinXchunk || c > std::max(nxm, kMinXchunk)) continue;
+          H.layout_stencil(l, c, order);
+          const LevelSet& L = H.level(l);
+          run(L);  // warm
+          HELM_HIP_CHECK(hipEventRecord(e0, st));
+          for (int r = 0; r < reps; ++r) run(L);
+          HELM_HIP_CHECK(hipEventRecord(e1, st));
+          HELM_HIP_CHECK(hipEventSynchronize(e1));
+          float ms = 0.f;
+          HELM_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+          if (verbose)
+            trace += " " + std::to_string(c) + (order ? "i" : "") + ":" + std::to_string(ms / reps * 1e3f) + "us";
+          if (ms < best_ms) {
+            best_ms = ms;
+            best = TileChoice{c, L.interleave};
+          }
         }
       }
       if (verbose)
-        fprintf(stderr, "helm tiles %s level %d -> x chunk %d (%s)\n", kind.c_str(), l, best, trace.c_str());
-      H.layout_stencil(l, best);
+        fprintf(stderr, "helm tiles %s level %d -> x chunk %d%s (%s)\n", kind.c_str(), l, best.xchunk,
+                best.interleave ? " interleaved" : "", trace.c_str());
+      H.layout_stencil(l, best.xchunk, best.interleave);
       cache[key] = best;
+      tune_cache_store(path, key, best);
     }
   } catch (...) {
     (void)hipEventDestroy(e0);

@@ -137,3 +137,31 @@ def test_apply_rejects_bad_arguments():
     grid = hx.Grid(n=n, h=10.0, npml=2, v_ref=2000.0)
     with pytest.raises(hx.HelmError):
         hx.helm_apply(grid, m_t, -1.0, x_t)
+
+
+def test_tile_choice_recorded_on_disk(tmp_path, monkeypatch):
+    """The tile tuner writes its choice (x chunk, segment order) to the cache
+    file named by HELM_TUNE_CACHE, keyed by the device and the segment
+    shapes; the operator's values do not depend on the tiles (no reductions),
+    so the tuned launch equals a launch with fixed heuristic tiles bit for bit."""
+    path = tmp_path / "tiles.tsv"
+    n = (41, 29, 34)  # a shape no other test uses
+    rng, m, vref, omega, h = _case(n, 4, seed=77)
+    grid = hx.Grid(n=n, h=h, npml=4, v_ref=vref, dtype="c64")
+    m_t = _to_dev(m, torch.float32)
+    x_t = _to_dev(workloads.random_complex(rng, (3,) + n), torch.complex64)
+    monkeypatch.setenv("HELM_TUNE_CACHE", str(path))
+    y1 = hx.helm_apply(grid, m_t, omega, x_t)
+    torch.cuda.synchronize()
+    lines = [ln.split("\t") for ln in path.read_text().splitlines()]
+    mine = [ln for ln in lines if "41x29x34" in ln[0]]
+    assert len(mine) == 1 and mine[0][0].startswith("tiles2|gfx") and "|apply|" in mine[0][0]
+    assert int(mine[0][1]) >= 4 and mine[0][2] in ("0", "1")
+    monkeypatch.setenv("HELM_AUTOTUNE", "0")
+    # another operator in between, so that the next call rebuilds this one
+    # (now with the heuristic tiles) instead of reusing the tuned one
+    y2 = hx.helm_apply(grid, m_t, omega * (1 + 1e-15), x_t)
+    y3 = hx.helm_apply(grid, m_t, omega, x_t)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y3)
+    assert y2.shape == y1.shape
