@@ -19,6 +19,8 @@ Also measured in the same run:
   right-hand sides), the same way;
 * batched vs plain solves of uneven problems (helm_solve_batched vs
   helm_solve one at a time);
+* on the 96^3 FWI workload: the linearised products (J, J^*, H_GN, full
+  Hessian), off-grid sources and receivers, WRI and the inversion driver;
 * the FP64 CPU oracle on a bounded sample of the same workload (rank 0).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -69,6 +71,9 @@ def parse():
                    help="only the 27-point operator timing on the 320x320x160 workload (and a plain "
                         "copy of the same size, the calibration of hardware-counter runs)")
     p.add_argument("--batch-only", action="store_true", help="only batched vs plain")
+    p.add_argument("--no-extras", action="store_true",
+                   help="skip the derivative / off-grid / WRI / driver timings on the 96^3 workload")
+    p.add_argument("--extras-only", action="store_true")
     return p.parse_args()
 
 
@@ -155,6 +160,95 @@ def sweep(hx, torch, reps, dev):
         print(json.dumps({"grid": list(n), "rhs": S, "stencil": sten, "us_per_launch": round(ms * 1e3, 1),
                           "GB_s": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}), flush=True)
         torch.cuda.empty_cache()
+
+
+def extras(hx, torch, workloads, dev):
+    """The paths beside the headline step, on the 96^3 FWI workload (h = 30 m,
+    layer 10, 5 Hz, 64 sources, 48 x 48 receivers, complex64, ML-GMRES to
+    1e-6), each timed warm (its first call builds the solver):
+    * the linearised products of pde_derivative over 16 sources (J dm, J^* y,
+      H_GN dm, full Hessian dm: 2 / 2 / 3 / 4 solves per source);
+    * misfit + gradient with off-grid (windowed-sinc) sources and receivers
+      beside the on-node call, all 64 sources;
+    * WRI objective + gradient over 16 sources (receiver-space CG capped at 4
+      steps: 1 + 2 x 4 solves per source);
+    * the inversion driver (fwi_invert): 2 frequencies in one band, 2 draws
+      of 16 of the 64 sources, r_sub = 1 (4 L-BFGS iterations per draw)."""
+    w = workloads.c3_fwi()
+    grid = hx.Grid(n=w.n, h=w.h, npml=w.npml, v_ref=w.v_ref, dtype="c64")
+    opts = hx.SolverOpts(tol=1e-6, max_cycles=30)
+    nsrc, nrec = len(w.src), len(w.rec)
+    omegas = [2 * np.pi * 4.0, 2 * np.pi * 5.0]
+    mt = torch.tensor(w.m_true, dtype=torch.float32, device=dev)
+    m_t = torch.tensor(w.m, dtype=torch.float32, device=dev)
+    u = torch.empty((2, nsrc) + w.n, dtype=torch.complex64, device=dev)
+    hx.misfit_gradient(grid, mt, omegas, w.src, w.rec,
+                       torch.zeros((2, nsrc, nrec), dtype=torch.complex64, device=dev),
+                       u_store=u, forward_only=True, opts=opts)
+    ridx = torch.tensor(w.rec.astype(np.int64), device=dev)
+    d2 = u[:, :, ridx[:, 0], ridx[:, 1], ridx[:, 2]].contiguous()
+    del u, mt
+    torch.cuda.empty_cache()
+    d1 = d2[1:2].contiguous()  # 5 Hz
+    out = {"workload": "96^3 FWI model (layers + low-velocity sphere), h=30 m, layer 10, complex64, "
+                       "ML-GMRES to rel.res 1e-6; data from the true model"}
+
+    def timed(fn):
+        fn()  # warm: builds the solver of this problem set
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, r
+
+    rng = np.random.default_rng(workloads.SEED_BASE + 3)
+    dm = torch.tensor(workloads.gaussian_random_field(rng, w.n, 4.0) * w.m * 0.02, dtype=torch.float32,
+                      device=dev)
+    mask16 = np.zeros((1, nsrc), bool)
+    mask16[0, ::4] = True
+    y = torch.randn((1, nsrc, nrec), dtype=torch.complex64, device=dev) * float(d1.abs().mean())
+    progress("extras: pde_derivative products")
+    for name, mode, inp, nsol in (("jacobian", "jacobian", dm, 2), ("jacobian_adjoint", "jacobian_adjoint", y, 2),
+                                  ("hessian_gn", "hessian_gn", dm, 3), ("hessian", "hessian", dm, 4)):
+        dt, _ = timed(lambda: hx.pde_derivative(mode, grid, m_t, w.omega, w.src, w.rec, inp, d=d1, mask=mask16,
+                                                opts=opts, raise_on_failure=False))
+        out["pde_derivative_" + name] = {"sources": 16, "solves": 16 * nsol, "s": round(dt, 3),
+                                         "solves_per_s": round(16 * nsol / dt, 3)}
+    progress("extras: off-grid vs on-node misfit + gradient")
+    jit = np.random.default_rng(workloads.SEED_BASE + 5)
+    src_pos = w.src + np.column_stack([jit.uniform(-0.4, 0.4, (nsrc, 2)), np.zeros(nsrc)])
+    rec_pos = w.rec + np.column_stack([jit.uniform(-0.4, 0.4, (nrec, 2)), np.zeros(nrec)])
+    sinc = (workloads.SINC_RADIUS, workloads.SINC_KAISER_B)
+    dt_on, _ = timed(lambda: hx.misfit_gradient(grid, m_t, w.omega, w.src, w.rec, d1, opts=opts))
+    dt_off, _ = timed(lambda: hx.misfit_gradient(grid, m_t, w.omega, src_pos, rec_pos, d1, sinc=sinc, opts=opts))
+    out["offgrid_misfit_gradient"] = {"sources": nsrc, "solves": 2 * nsrc, "s": round(dt_off, 3),
+                                      "solves_per_s": round(2 * nsrc / dt_off, 3), "on_node_s": round(dt_on, 3),
+                                      "sinc": [int(sinc[0]), float(sinc[1])]}
+    progress("extras: WRI")
+    lam = 3.0 / (12.0 / w.h ** 2 + w.omega ** 2 * float(w.m.max()))  # 3 / (an estimate of ||H||)
+    dt, (f, _, infos) = timed(lambda: hx.wri_misfit_gradient(grid, m_t, w.omega, w.src, w.rec, d1, lam,
+                                                             mask=mask16, cg_tol=1e-3, cg_max=4, opts=opts,
+                                                             raise_on_failure=False))
+    sel = [i for k, i in enumerate(infos) if mask16.ravel()[k]]
+    nsol = sum(i.matvecs for i in sel)
+    out["wri_misfit_gradient"] = {"sources": 16, "lambda": lam, "cg_steps_max": max(i.cycles for i in sel),
+                                  "cg_relres_max": max(i.relres_fp64 for i in sel), "solves": int(nsol),
+                                  "s": round(dt, 3), "solves_per_s": round(nsol / dt, 3)}
+    progress("extras: inversion driver")
+    lo, hi = 1.0 / 4500.0 ** 2, 1.0 / 1500.0 ** 2
+    m_run = m_t.clone()
+
+    def run_driver():
+        m_run.copy_(m_t)
+        return hx.fwi_invert(grid, m_run, omegas, w.src, w.rec, d2, lo, hi, band_size=2, band_overlap=0,
+                             r_sub=1, batch=16, subproblems=2, seed=3, opts=opts)
+    dt, (draws, recs, _) = timed(run_driver)
+    evals = sum(d["evals"] for d in draws)
+    out["fwi_invert"] = {"draws": len(draws), "iterations": len(recs), "evaluations": evals,
+                         "solves": evals * 2 * 2 * 16, "s": round(dt, 3),
+                         "solves_per_s": round(evals * 2 * 2 * 16 / dt, 3),
+                         "f_first": draws[0]["f_start"], "f_last": draws[-1]["f_end"]}
+    return out
 
 
 def _c4_member(p):
@@ -415,6 +509,9 @@ def main():
     if args.batch_only:
         print(json.dumps(batched_vs_plain(hx, torch, workloads, args.batch_count, dev)), flush=True)
         return
+    if args.extras_only:
+        print(json.dumps(extras(hx, torch, workloads, dev)), flush=True)
+        return
     w = workloads.c2_layered()
     if args.stencil_only:
         grid = hx.Grid(n=w.n, h=w.h, npml=w.npml, v_ref=w.v_ref, dtype="c64")
@@ -476,6 +573,9 @@ def main():
     if not args.no_batch:
         progress("uneven batch: building problems")
     batch = None if args.no_batch else batched_vs_plain(hx, torch, workloads, args.batch_count, dev)
+    if not args.no_extras:
+        progress("96^3 derivative products, off-grid geometry, WRI, inversion driver")
+    ext = None if args.no_extras else extras(hx, torch, workloads, dev)
 
     out = {
         "metric": METRIC,
@@ -513,6 +613,7 @@ def main():
         },
         "stencil27": st27,
         "c5_27pt_gradient": c5,
+        "extras_96cube": ext,
         "roofline": {
             "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
