@@ -73,7 +73,8 @@ typedef enum { HELM_GMRES = 0, HELM_FGMRES_ML = 1 } helm_method;
 
 /* Grid, layer and discretisation of one Helmholtz operator. */
 typedef struct {
-  int32_t n[3];    /* nodes per axis, layer included (each >= 3)          */
+  int32_t n[3];    /* nodes per axis, layer included (each >= 3; n[0] = 1:
+                      the 2D operator of the (n[1], n[2]) plane, 7-point) */
   double h;        /* grid spacing [m]                                     */
   int32_t npml;    /* layer width in nodes on each face (0 = no layer)     */
   double pml_R;    /* nominal reflection coefficient of the layer, (0, 1)  */
@@ -411,6 +412,55 @@ helm_status wri_misfit_gradient(helm_ctx* ctx, const helm_grid* g,
                                 const void* d, double lambda, double cg_tol,
                                 int cg_max, double* f, void* grad,
                                 void* u_store, int flags,
+                                const helm_solver_opts* o,
+                                helm_solve_info* info, void* stream);
+
+/* 2.5D modelling, misfit and gradient (paper: the 2.5D subsection) for a 3D
+ * model invariant along one axis ("y"), on a 2D grid: g->n[0] = 1, the
+ * plane (n[1], n[2]) carrying the paper's (x, z), 7-point operator.  (A grid
+ * with n[0] = 1 is the 2D operator in every entry point: the first axis has
+ * no coupling and no layer, the layers act on the plane's two axes, the
+ * point source is amp e_s / h^2, and the multigrid levels keep n[0] = 1.)
+ * Per frequency f: K_f = min(p_kc omega_f / v_min, pi / h); Gauss-Legendre
+ * nodes k_i and weights w_i (i < nky) of [0, K_f]; per selected (f, s) and i
+ * the 2D field u~_{f,s,i} solves
+ *   (L + omega_f^2 (m - k_i^2 / omega_f^2)) u~ = amp_fs e_{src_s} / h^2
+ * (all of them in one batched solve), and
+ *   d_pred[f][s][r] = sum_i (w_i / pi) cos(k_i (rec_y[r] - src_y[s])) u~(rec_r)
+ *   f = c 1/2 sum_{(f,s) selected} ||d_pred - d||^2   (d = 0 when NULL)
+ *   g = c sum Re(omega_f^2 conj(u~_{f,s,i}) * v_{f,s,i}),
+ *       v = -H_i^{-H} P_r^T (c_{f,s,i} * (d_pred - d)_{f,s})
+ * with c = 1 (1/#selected pairs with HELM_MG_RENORMALISE); the quadrature is
+ * fixed by (nky, p_kc, v_min), so g is the exact gradient of f.
+ * Arguments:
+ *   m        dev, N reals of g->dtype (the model on the plane)
+ *   nky      quadrature nodes (1..4096); p_kc (> 0): the cut at p_kc times
+ *            the critical wavenumber omega / v_min (v_min > 0, m/s)
+ *   src_idx  host int32 [nsrc][2]: plane node (j, k); src_y host double
+ *            [nsrc]: coordinate along the invariant axis (m)
+ *   rec_idx  host int32 [nrec][2], rec_y host double [nrec]: the same for
+ *            the receivers
+ *   src_amp, mask as in misfit_gradient
+ *   d        dev [nfreq][nsrc][nrec] complex of g->dtype, observed data, or
+ *            NULL with HELM_MG_FORWARD_ONLY
+ *   f        host, the misfit;  grad  dev, N reals (NULL with FORWARD_ONLY)
+ *   d_pred   dev [nfreq][nsrc][nrec] complex or NULL: receives the
+ *            modelled data of the selected pairs
+ *   flags    HELM_MG_FORWARD_ONLY, HELM_MG_ACCUMULATE, HELM_MG_RENORMALISE
+ *   info     host, 2*nfreq*nsrc*nky entries or NULL: the forward solve of
+ *            (f, s, i) at (f*nsrc + s)*nky + i, the adjoint solve after all
+ *            forward entries
+ * Invalid arguments (a 3D grid, nky, p_kc, v_min, nodes outside the plane,
+ * non-finite coordinates, flags) return HELM_E_INVAL before any device
+ * work.  Returns the worst status of the solves. */
+helm_status misfit_gradient_25d(helm_ctx* ctx, const helm_grid* g,
+                                const void* m, int nfreq, const double* omega,
+                                int nky, double p_kc, double v_min, int nsrc,
+                                const int32_t* src_idx, const double* src_y,
+                                const double* src_amp, const uint8_t* mask,
+                                int nrec, const int32_t* rec_idx,
+                                const double* rec_y, const void* d, double* f,
+                                void* grad, void* d_pred, int flags,
                                 const helm_solver_opts* o,
                                 helm_solve_info* info, void* stream);
 

@@ -7,11 +7,11 @@ those entry points.  Importing it does not load the library; the first call
 does, and raises if the library has not been built.
 """
 from .api import (Grid, SolverOpts, SolveInfo, HelmError, fwi_invert, helm_apply, helm_apply_noalloc, helm_solve,
-                  helm_solve_batched, misfit_gradient, pde_derivative, version, workspace_bytes,
-                  wri_misfit_gradient)
+                  helm_solve_batched, misfit_gradient, misfit_gradient_25d, pde_derivative, version,
+                  workspace_bytes, wri_misfit_gradient)
 from .autograd import HelmholtzMisfit, helmholtz_misfit
 
 __all__ = ["Grid", "SolverOpts", "SolveInfo", "HelmError", "helm_apply", "helm_apply_noalloc", "helm_solve",
            "helm_solve_batched",
-           "misfit_gradient", "pde_derivative", "fwi_invert", "wri_misfit_gradient", "version", "workspace_bytes", "HelmholtzMisfit",
+           "misfit_gradient", "pde_derivative", "fwi_invert", "wri_misfit_gradient", "misfit_gradient_25d", "version", "workspace_bytes", "HelmholtzMisfit",
            "helmholtz_misfit"]

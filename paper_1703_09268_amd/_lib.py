@@ -49,7 +49,8 @@ EXPORTS = ("helm_create", "helm_destroy", "helm_last_error", "helm_version",
            "helm_default_opts", "helm_workspace_bytes", "helm_apply",
            "helm_apply_noalloc", "helm_solve", "helm_solve_batched", "misfit_gradient",
            "misfit_gradient_offgrid", "pde_derivative", "pde_derivative_offgrid",
-           "helm_fwi_draw_count", "fwi_invert", "fwi_invert_offgrid", "wri_misfit_gradient")
+           "helm_fwi_draw_count", "fwi_invert", "fwi_invert_offgrid", "wri_misfit_gradient",
+           "misfit_gradient_25d")
 
 
 class helm_grid(C.Structure):
@@ -144,6 +145,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.wri_misfit_gradient.argtypes = [vp, G, vp, i32, D, i32, C.POINTER(C.c_int32), D,
                                         C.POINTER(C.c_uint8), i32, C.POINTER(C.c_int32), vp, dbl, dbl, i32,
                                         D, vp, vp, i32, O, I, vp]
+    lib.misfit_gradient_25d.argtypes = [vp, G, vp, i32, D, i32, dbl, dbl, i32, C.POINTER(C.c_int32), D, D,
+                                        C.POINTER(C.c_uint8), i32, C.POINTER(C.c_int32), D, vp, D, vp, vp, i32,
+                                        O, I, vp]
     P = C.POINTER(helm_fwi_params)
     lib.helm_fwi_draw_count.argtypes = [i32, P]
     lib.helm_fwi_draw_count.restype = C.c_int
@@ -155,7 +159,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                                        O] + FW
     for name in ("helm_create", "helm_destroy", "helm_apply", "helm_apply_noalloc", "helm_solve",
                  "helm_solve_batched", "misfit_gradient", "misfit_gradient_offgrid", "pde_derivative",
-                 "pde_derivative_offgrid", "fwi_invert", "fwi_invert_offgrid", "wri_misfit_gradient"):
+                 "pde_derivative_offgrid", "fwi_invert", "fwi_invert_offgrid", "wri_misfit_gradient",
+           "misfit_gradient_25d"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib

@@ -453,6 +453,63 @@ def wri_misfit_gradient(grid: Grid, m: torch.Tensor, omega, src, rec, d: torch.T
     return f.value, grad, inf
 
 
+def misfit_gradient_25d(grid: Grid, m: torch.Tensor, omega, src, src_y, rec, rec_y,
+                        d: Optional[torch.Tensor] = None, nky: int = 40, p_kc: float = 1.0,
+                        v_min: float = 1500.0, src_amp=None, mask=None, grad: Optional[torch.Tensor] = None,
+                        want_data: bool = True, forward_only: bool = False, accumulate: bool = False,
+                        renormalise: bool = False, opts: Optional[SolverOpts] = None,
+                        raise_on_failure: bool = True):
+    """2.5D modelling, misfit and gradient (misfit_gradient_25d) on a 2D grid
+    (grid.n[0] == 1).  src, rec: (n, 2) plane nodes; src_y, rec_y: their
+    coordinates along the invariant axis (m); d: observed data
+    [nfreq][nsrc][nrec] (None: modelling only).  Returns (f, grad, d_pred,
+    infos): d_pred [nfreq][nsrc][nrec] (None unless want_data), infos per
+    2D solve, forward then adjoint, [frequency][source][k_y] order."""
+    dev = m.device.index or 0
+    om = np.ascontiguousarray(np.atleast_1d(np.asarray(omega, dtype=np.float64)).ravel())
+    nfreq = len(om)
+    src_a = np.ascontiguousarray(np.asarray(src, dtype=np.int32).reshape(-1, 2))
+    rec_a = np.ascontiguousarray(np.asarray(rec, dtype=np.int32).reshape(-1, 2))
+    nsrc, nrec = len(src_a), len(rec_a)
+    sy = np.ascontiguousarray(np.asarray(src_y, dtype=np.float64).reshape(nsrc))
+    ry = np.ascontiguousarray(np.asarray(rec_y, dtype=np.float64).reshape(nrec))
+    amp_p = None
+    if src_amp is not None:
+        amp = np.broadcast_to(np.asarray(src_amp, np.complex128), (nfreq, nsrc))
+        amp_d = np.ascontiguousarray(np.stack([amp.real, amp.imag], axis=-1).ravel())
+        amp_p = amp_d.ctypes.data_as(C.POINTER(C.c_double))
+    mask_p = None
+    if mask is not None:
+        mask_a = np.ascontiguousarray(np.broadcast_to(np.asarray(mask, bool), (nfreq, nsrc)).astype(np.uint8))
+        mask_p = mask_a.ctypes.data_as(C.POINTER(C.c_uint8))
+    if d is None:
+        forward_only = True
+    flags = (L.HELM_MG_FORWARD_ONLY if forward_only else 0) | (L.HELM_MG_ACCUMULATE if accumulate else 0) | \
+        (L.HELM_MG_RENORMALISE if renormalise else 0)
+    if grad is None and not forward_only:
+        grad = torch.empty(tuple(grid.n), dtype=grid.real_dtype, device=m.device)
+    d_pred = torch.zeros((nfreq, nsrc, nrec), dtype=grid.complex_dtype, device=m.device) if want_data else None
+    opts = opts or SolverOpts()
+    infos = (L.helm_solve_info * (2 * nfreq * nsrc * int(nky)))()
+    f = C.c_double(0.0)
+    ctx = _context(dev)
+    g, o = grid.c_struct(), opts.c_struct()
+    PI = C.POINTER(C.c_int32)
+    PD = C.POINTER(C.c_double)
+    st = L.load().misfit_gradient_25d(
+        ctx, C.byref(g), _dev_tensor(m, grid.real_dtype, grid.N, "m"), nfreq, om.ctypes.data_as(PD), int(nky),
+        float(p_kc), float(v_min), nsrc, src_a.ctypes.data_as(PI), sy.ctypes.data_as(PD), amp_p, mask_p, nrec,
+        rec_a.ctypes.data_as(PI), ry.ctypes.data_as(PD),
+        None if d is None else _dev_tensor(d, grid.complex_dtype, nfreq * nsrc * nrec, "d"), C.byref(f),
+        None if grad is None else _dev_tensor(grad, grid.real_dtype, grid.N, "grad"),
+        None if d_pred is None else _dev_tensor(d_pred, grid.complex_dtype, nfreq * nsrc * nrec, "d_pred"),
+        flags, C.byref(o), infos, _stream(dev))
+    allow = (L.HELM_OK,) if raise_on_failure else (L.HELM_OK, L.HELM_NOT_CONVERGED, L.HELM_BREAKDOWN)
+    _check(ctx, st, allow)
+    inf = [SolveInfo(i.status, i.cycles, i.inner_its, i.matvecs, i.relres_fp64) for i in infos]
+    return f.value, grad, d_pred, inf
+
+
 def fwi_invert(grid: Grid, m: torch.Tensor, omega, src, rec, d: torch.Tensor, lo, hi,
                src_amp=None, band_size: int = 4, band_overlap: int = 2, r_sub: int = 20,
                memory: int = 5, batch: int = 0, subproblems: int = 1, batch_increase: int = 1,

@@ -15,6 +15,7 @@
 #include "fwi.hip"
 #include "lbfgs.hip"
 #include "wri.hip"
+#include "model25d.hip"
 #include "noalloc.hip"
 #include "solver.hip"
 
@@ -76,11 +77,14 @@ helm_status guarded(helm_ctx* ctx, F&& f) {
 
 void check_grid(const helm_grid* g) {
   HELM_REQUIRE(g != nullptr, "null grid");
-  for (int a = 0; a < 3; ++a) HELM_REQUIRE(g->n[a] >= 3, "grid sizes must be >= 3");
+  // n[0] == 1: the two-dimensional operator on the (n[1], n[2]) plane
+  HELM_REQUIRE(g->n[0] == 1 || g->n[0] >= 3, "grid sizes must be >= 3 (or n[0] = 1 for a 2D grid)");
+  for (int a = 1; a < 3; ++a) HELM_REQUIRE(g->n[a] >= 3, "grid sizes must be >= 3");
   HELM_REQUIRE((int64_t)g->n[0] * g->n[1] * g->n[2] < ((int64_t)1 << 40), "grid too large");
   HELM_REQUIRE(g->h > 0.0 && std::isfinite(g->h), "grid spacing must be positive");
   HELM_REQUIRE(g->npml >= 0, "npml must be >= 0");
-  for (int a = 0; a < 3; ++a) HELM_REQUIRE(2 * g->npml < g->n[a], "npml must be < n/2 on every axis");
+  for (int a = 0; a < 3; ++a)
+    HELM_REQUIRE(g->n[a] == 1 || 2 * g->npml < g->n[a], "npml must be < n/2 on every axis");
   if (g->npml > 0) {
     HELM_REQUIRE(g->pml_R > 0.0 && g->pml_R < 1.0, "pml_R must be in (0, 1)");
     HELM_REQUIRE(g->v_ref > 0.0 && std::isfinite(g->v_ref), "v_ref must be positive");
@@ -89,6 +93,7 @@ void check_grid(const helm_grid* g) {
   HELM_REQUIRE(g->dtype == HELM_C64 || g->dtype == HELM_C128, "unknown dtype");
   if (g->stencil == HELM_27PT)
     for (int c = 0; c < 7; ++c) HELM_REQUIRE(std::isfinite(g->w27[c]), "27-point weights must be finite");
+  HELM_REQUIRE(g->n[0] > 1 || g->stencil == HELM_7PT, "2D grids (n[0] = 1) use the 7-point stencil");
 }
 
 helm::GridSpec spec_of(const helm_grid* g) {
@@ -139,6 +144,7 @@ void check_coarse_sizes(const helm_grid* g, const helm::SolveOpts& o) {
   int n[3] = {g->n[0], g->n[1], g->n[2]};
   for (int l = 1; l < o.levels; ++l)
     for (int a = 0; a < 3; ++a) {
+      if (n[a] == 1) continue;  // the absent axis of a 2D grid
       n[a] = n[a] / 2 + 1;
       HELM_REQUIRE(n[a] >= 3, "grid too small for the requested number of levels");
     }
@@ -635,7 +641,8 @@ FieldRef forward_fields(const helm_grid* g, const Pairs<T>& P, helm::Solver<T>& 
   const int64_t N = P.N;
   *fwd_fp64 = nullptr;
   if (reuse) return FieldRef{u_store, P.uoff_store, u64};
-  const double inv_h3 = 1.0 / (g->h * g->h * g->h);
+  // the discrete delta: 1/h^3, or 1/h^2 on a 2D grid (n[0] = 1)
+  const double inv_h3 = g->n[0] == 1 ? 1.0 / (g->h * g->h) : 1.0 / (g->h * g->h * g->h);
   hipLaunchKernelGGL((k_fill_zero<T>), dim3(std::min<unsigned>(65536, ceil_div((int64_t)P.np * N, 256))), dim3(256), 0,
                      st, Q, (int64_t)P.np * N);
   hipLaunchKernelGGL((k_point_sources<T>), dim3(P.sblk, P.np), dim3(256), 0, st, Q, N, (const int*)P.src_of_pair,
@@ -1030,6 +1037,242 @@ helm_status wri_t(helm_ctx* ctx, const helm_grid* g, const void* m, int nfreq, c
   return (helm_status)worst;
 }
 
+// Gauss-Legendre nodes (ascending) and weights on [0, K]: Newton's method on
+// the Legendre polynomial of degree n, evaluated by its three-term
+// recurrence, from the starting guesses cos(pi (i + 3/4) / (n + 1/2)).
+void gauss_legendre(int n, double K, double* x, double* w) {
+  for (int i = 0; i < n; ++i) {
+    double t = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = t;  // P_{k-1}, P_k
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) p0 = 1.0;
+      dp = n * (t * p1 - p0) / (t * t - 1.0);  // P_n'(t)
+      const double dt = p1 / dp;
+      t -= dt;
+      if (std::fabs(dt) <= 1e-16) break;
+    }
+    double p0 = 1.0, p1 = t;
+    for (int k = 2; k <= n; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    if (n == 1) p0 = 1.0;
+    dp = n * (t * p1 - p0) / (t * t - 1.0);
+    x[n - 1 - i] = 0.5 * K * (t + 1.0);
+    w[n - 1 - i] = K / ((1.0 - t * t) * dp * dp);
+  }
+}
+
+// 2.5D modelling, misfit and gradient (the 2.5D subsection) on a 2D grid
+// (n[0] = 1): every selected (frequency, source) row contributes nky 2D
+// problems, one per Gauss-Legendre node k_i of [0, min(p_kc omega / v_min,
+// pi / h)], with model m - k_i^2 / omega^2; all rows x nodes are solved in
+// one batched solve per direction.  Receiver r of row (f, s) reads
+// sum_i (w_i / pi) cos(k_i (y_r - y_s)) u~_{f,s,i}(node_r).
+template <typename T>
+helm_status model25d_t(helm_ctx* ctx, const helm_grid* g, const void* m, int nfreq, const double* omega, int nky,
+                       double p_kc, double v_min, const PointSet& src, const double* src_y, const double* src_amp,
+                       const uint8_t* mask, const PointSet& rec, const double* rec_y, const void* d, double* f,
+                       void* grad, void* d_pred, int flags, const helm::SolveOpts& o, helm_solve_info* info,
+                       void* caller) {
+  using namespace helm;
+  hipStream_t st = solve_stream(ctx, caller);
+  const bool fwd_only = (flags & HELM_MG_FORWARD_ONLY) != 0;
+  const bool acc = (flags & HELM_MG_ACCUMULATE) != 0;
+  const int nsrc = src.n(), nrec = rec.n();
+  const int64_t N = (int64_t)g->n[0] * g->n[1] * g->n[2];
+  const int nall = nfreq * nsrc;
+  if (info)
+    for (int k = 0; k < 2 * nall * nky; ++k) to_info(SolveInfo(), info + k);
+  std::vector<int> rows;
+  for (int k = 0; k < nall; ++k)
+    if (!mask || mask[k]) rows.push_back(k);
+  const int nrow = (int)rows.size(), np = nrow * nky;
+  if (np == 0) {
+    if (f) *f = 0.0;
+    if (!fwd_only && !acc) HELM_HIP_CHECK(hipMemsetAsync(grad, 0, (size_t)N * sizeof(T), st));
+    HELM_HIP_CHECK(hipStreamSynchronize(st));
+    return HELM_OK;
+  }
+  const double scale = (flags & HELM_MG_RENORMALISE) ? 1.0 / nrow : 1.0;
+  std::vector<double> kq((size_t)nfreq * nky), wq((size_t)nfreq * nky);
+  for (int fi = 0; fi < nfreq; ++fi) {
+    const double K = std::min(p_kc * omega[fi] / v_min, M_PI / g->h);
+    gauss_legendre(nky, K, &kq[(size_t)fi * nky], &wq[(size_t)fi * nky]);
+    for (int i = 0; i < nky; ++i) wq[(size_t)fi * nky + i] /= M_PI;
+  }
+  std::vector<int> mslot(nfreq, -1);  // model set of each frequency with a selected row
+  int nmf = 0;
+  for (int k : rows)
+    if (mslot[k / nsrc] < 0) mslot[k / nsrc] = nmf++;
+  const int nm = nmf * nky;
+  std::vector<double> shift(nm);
+  for (int fi = 0; fi < nfreq; ++fi)
+    if (mslot[fi] >= 0)
+      for (int i = 0; i < nky; ++i) {
+        const double kk = kq[(size_t)fi * nky + i];
+        shift[(size_t)mslot[fi] * nky + i] = kk * kk / (omega[fi] * omega[fi]);
+      }
+  std::vector<int> src_of_pair(np);
+  std::vector<double2> amp(np);
+  std::vector<double> pk(np), pw(np), pys(np), wg(np);
+  std::vector<int64_t> drow(nrow), uoff(np);
+  for (int r = 0; r < nrow; ++r) {
+    const int k = rows[r], fi = k / nsrc, s = k % nsrc;
+    drow[r] = k;
+    for (int i = 0; i < nky; ++i) {
+      const int p = r * nky + i;
+      src_of_pair[p] = s;
+      amp[p] = src_amp ? make_double2(src_amp[2 * (size_t)k], src_amp[2 * (size_t)k + 1]) : make_double2(1.0, 0.0);
+      pk[p] = kq[(size_t)fi * nky + i];
+      pw[p] = wq[(size_t)fi * nky + i];
+      pys[p] = src_y[s];
+      wg[p] = omega[fi] * omega[fi] * scale;
+      uoff[p] = (int64_t)p * N;
+    }
+  }
+  // receiver node lists (distinct nodes ascending, each with its (receiver,
+  // weight) entries in receiver order: a fixed summation order)
+  const int nent = (int)rec.lin.size();
+  std::vector<int> ent(nent), ent_rec(nent);
+  for (int k = 0; k < nrec; ++k)
+    for (int e = rec.ptr[k]; e < rec.ptr[k + 1]; ++e) ent_rec[e] = k;
+  for (int e = 0; e < nent; ++e) ent[e] = e;
+  std::stable_sort(ent.begin(), ent.end(), [&](int x, int y) { return rec.lin[x] < rec.lin[y]; });
+  std::vector<int64_t> node_lin;
+  std::vector<int> node_ptr, node_rec(nent);
+  std::vector<double> node_w(nent);
+  for (int i = 0; i < nent; ++i) {
+    const int e = ent[i];
+    if (node_lin.empty() || node_lin.back() != rec.lin[e]) {
+      node_lin.push_back(rec.lin[e]);
+      node_ptr.push_back(i);
+    }
+    node_rec[i] = ent_rec[e];
+    node_w[i] = rec.w[e];
+  }
+  node_ptr.push_back(nent);
+  const int nnode = (int)node_lin.size();
+  const int rblk = (int)ceil_div(nrec, 256);
+  int smax = 1;
+  for (int k = 0; k < nsrc; ++k) smax = std::max(smax, src.ptr[k + 1] - src.ptr[k]);
+  const int nsent = (int)src.lin.size();
+  // small device tables
+  auto r256 = [](size_t b) { return (b + 255) / 256 * 256; };
+  struct Up {
+    const void* h;
+    size_t b;
+    void** d;
+  };
+  int *d_src_of_pair, *d_sptr, *d_rptr, *d_nptr, *d_nrec;
+  double2* d_amp;
+  double *d_pk, *d_pw, *d_pys, *d_wg, *d_shift, *d_sw, *d_rw, *d_nw, *d_recy, *d_part;
+  int64_t *d_drow, *d_uoff, *d_slin, *d_rlin, *d_node;
+  cx<T>* d_res;
+  std::vector<Up> ups = {
+      {src_of_pair.data(), np * sizeof(int), (void**)&d_src_of_pair},
+      {amp.data(), np * sizeof(double2), (void**)&d_amp},
+      {pk.data(), np * sizeof(double), (void**)&d_pk},
+      {pw.data(), np * sizeof(double), (void**)&d_pw},
+      {pys.data(), np * sizeof(double), (void**)&d_pys},
+      {wg.data(), np * sizeof(double), (void**)&d_wg},
+      {shift.data(), nm * sizeof(double), (void**)&d_shift},
+      {drow.data(), nrow * sizeof(int64_t), (void**)&d_drow},
+      {uoff.data(), np * sizeof(int64_t), (void**)&d_uoff},
+      {src.ptr.data(), (nsrc + 1) * sizeof(int), (void**)&d_sptr},
+      {src.lin.data(), nsent * sizeof(int64_t), (void**)&d_slin},
+      {src.w.data(), nsent * sizeof(double), (void**)&d_sw},
+      {rec.ptr.data(), (nrec + 1) * sizeof(int), (void**)&d_rptr},
+      {rec.lin.data(), nent * sizeof(int64_t), (void**)&d_rlin},
+      {rec.w.data(), nent * sizeof(double), (void**)&d_rw},
+      {node_lin.data(), nnode * sizeof(int64_t), (void**)&d_node},
+      {node_ptr.data(), (nnode + 1) * sizeof(int), (void**)&d_nptr},
+      {node_rec.data(), nent * sizeof(int), (void**)&d_nrec},
+      {node_w.data(), nent * sizeof(double), (void**)&d_nw},
+      {rec_y, nrec * sizeof(double), (void**)&d_recy},
+      {nullptr, (size_t)nrow * nrec * sizeof(cx<T>), (void**)&d_res},
+      {nullptr, (size_t)nrow * rblk * sizeof(double), (void**)&d_part}};
+  size_t small = 0;
+  for (const Up& u : ups) small += r256(u.b);
+  ctx->fwi_small.ensure(small);
+  char* sp = (char*)ctx->fwi_small.p;
+  for (const Up& u : ups) {
+    *u.d = sp;
+    if (u.h && u.b) HELM_HIP_CHECK(hipMemcpyAsync(sp, u.h, u.b, hipMemcpyHostToDevice, st));
+    sp += r256(u.b);
+  }
+  // large buffers: the shifted models, then Q, U, V (pairs contiguous)
+  const size_t mb = r256((size_t)nm * N * sizeof(T)), fb = r256((size_t)np * N * sizeof(cx<T>));
+  ctx->fwi_buf.ensure(mb + 3 * fb);
+  char* base = (char*)ctx->fwi_buf.p;
+  T* models = (T*)base;
+  cx<T>* Q = (cx<T>*)(base + mb);
+  cx<T>* U = (cx<T>*)(base + mb + fb);
+  cx<T>* V = (cx<T>*)(base + mb + 2 * fb);
+  hipLaunchKernelGGL((k_shift_models<T>), dim3(std::min<unsigned>(1024, ceil_div(N, 256)), nm), dim3(256), 0, st,
+                     (const T*)m, N, (const double*)d_shift, models);
+  HELM_HIP_CHECK(hipGetLastError());
+  std::vector<ProblemSpec> probs;
+  for (int r = 0; r < nrow; ++r) {
+    const int fi = rows[r] / nsrc;
+    for (int i = 0; i < nky; ++i)
+      probs.push_back(shared_problems(g, models + ((size_t)mslot[fi] * nky + i) * N, omega[fi], 0, 1)[0]);
+  }
+  // the host tables above go out of scope with the function: copies must be done
+  HELM_HIP_CHECK(hipStreamSynchronize(st));
+  Solver<T>& S = solver_for<T>(ctx, probs, o, st);
+  std::vector<SolveInfo> inf(np);
+  int worst = 0;
+  const double inv_h2 = 1.0 / (g->h * g->h);
+  hipLaunchKernelGGL((k_fill_zero<T>), dim3(std::min<unsigned>(65536, ceil_div((int64_t)np * N, 256))), dim3(256), 0,
+                     st, Q, (int64_t)np * N);
+  hipLaunchKernelGGL((k_point_sources<T>), dim3((unsigned)ceil_div(smax, 256), np), dim3(256), 0, st, Q, N,
+                     (const int*)d_src_of_pair, (const int*)d_sptr, (const int64_t*)d_slin, (const double*)d_sw,
+                     (const double2*)d_amp, inv_h2);
+  HELM_HIP_CHECK(hipGetLastError());
+  worst = std::max(worst, S.solve(0, Q, U, inf.data()));
+  auto put_info = [&](int which) {
+    if (!info) return;
+    for (int r = 0; r < nrow; ++r)
+      for (int i = 0; i < nky; ++i)
+        to_info(inf[r * nky + i], info + (size_t)which * nall * nky + (size_t)rows[r] * nky + i);
+  };
+  put_info(0);
+  const Quad25 q{d_pk, d_pw, d_pys};
+  hipLaunchKernelGGL((k_synth25d<T>), dim3(rblk, nrow), dim3(256), 0, st, S.iterate(), N, nky, q,
+                     (const int*)d_rptr, (const int64_t*)d_rlin, (const double*)d_rw, (const double*)d_recy, nrec,
+                     (const cx<T>*)d, (const int64_t*)d_drow, d_res, (cx<T>*)d_pred, d_part);
+  HELM_HIP_CHECK(hipGetLastError());
+  std::vector<double> hpart((size_t)nrow * rblk);
+  HELM_HIP_CHECK(hipMemcpyAsync(hpart.data(), d_part, hpart.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HELM_HIP_CHECK(hipStreamSynchronize(st));
+  double fsum = 0.0;
+  for (double v : hpart) fsum += v;
+  if (f) *f = 0.5 * fsum * scale;
+  if (fwd_only) return (helm_status)worst;
+  hipLaunchKernelGGL((k_fill_zero<T>), dim3(std::min<unsigned>(65536, ceil_div((int64_t)np * N, 256))), dim3(256), 0,
+                     st, Q, (int64_t)np * N);
+  hipLaunchKernelGGL((k_adjoint25d<T>), dim3((unsigned)ceil_div(nnode, 256), np), dim3(256), 0, st, Q, N, nky, q,
+                     (const int64_t*)d_node, (const int*)d_nptr, (const int*)d_nrec, (const double*)d_nw, nnode,
+                     (const double*)d_recy, (const cx<T>*)d_res, nrec);
+  HELM_HIP_CHECK(hipGetLastError());
+  worst = std::max(worst, S.solve(1, Q, V, inf.data()));
+  put_info(1);
+  hipLaunchKernelGGL((k_gradient<T, T, T, false>), dim3(std::min<unsigned>(4096, ceil_div(N, 256))), dim3(256), 0, st,
+                     (const cx<T>*)U, (const int64_t*)d_uoff, (const cx<T>*)V, np, g->n[0], g->n[1], g->n[2],
+                     (const double*)d_wg, 1.0, 0.0, 0.0, 0.0, (T*)grad, acc);
+  HELM_HIP_CHECK(hipGetLastError());
+  HELM_HIP_CHECK(hipStreamSynchronize(st));
+  return (helm_status)worst;
+}
+
 void check_pair_args(const helm_grid* g, const void* m, int nfreq, const double* omega, int nsrc, int nrec) {
   check_grid(g);
   HELM_REQUIRE(m, "null model pointer");
@@ -1398,6 +1641,50 @@ helm_status wri_misfit_gradient(helm_ctx* ctx, const helm_grid* g, const void* m
                           flags, so, info, stream);
     return wri_t<double>(ctx, g, m, nfreq, omega, S, src_amp, mask, R, d, lambda, cg_tol, cg_max, f, grad, u_store,
                          flags, so, info, stream);
+  });
+}
+
+helm_status misfit_gradient_25d(helm_ctx* ctx, const helm_grid* g, const void* m, int nfreq,
+                                const double* omega, int nky, double p_kc, double v_min, int nsrc,
+                                const int32_t* src_idx, const double* src_y, const double* src_amp,
+                                const uint8_t* mask, int nrec, const int32_t* rec_idx, const double* rec_y,
+                                const void* d, double* f, void* grad, void* d_pred, int flags,
+                                const helm_solver_opts* o, helm_solve_info* info, void* stream) {
+  return guarded(ctx, [&]() -> helm_status {
+    check_pair_args(g, m, nfreq, omega, nsrc, nrec);
+    HELM_REQUIRE(g->n[0] == 1, "2.5D modelling runs on a 2D grid (n[0] = 1)");
+    HELM_REQUIRE(nky >= 1 && nky <= 4096, "nky must be in 1..4096");
+    HELM_REQUIRE(p_kc > 0.0 && std::isfinite(p_kc), "p_kc must be positive");
+    HELM_REQUIRE(v_min > 0.0 && std::isfinite(v_min), "v_min must be positive");
+    HELM_REQUIRE(src_idx && rec_idx && src_y && rec_y && f, "null pointer argument");
+    HELM_REQUIRE((flags & ~(HELM_MG_FORWARD_ONLY | HELM_MG_ACCUMULATE | HELM_MG_RENORMALISE)) == 0,
+                 "unknown or unsupported flag bits");
+    HELM_REQUIRE(d || (flags & HELM_MG_FORWARD_ONLY), "observed data needed for the gradient");
+    HELM_REQUIRE((flags & HELM_MG_FORWARD_ONLY) || grad, "null gradient");
+    for (int k = 0; k < nsrc; ++k) HELM_REQUIRE(std::isfinite(src_y[k]), "non-finite source coordinate");
+    for (int k = 0; k < nrec; ++k) HELM_REQUIRE(std::isfinite(rec_y[k]), "non-finite receiver coordinate");
+    std::vector<int32_t> s3(3 * (size_t)nsrc), r3(3 * (size_t)nrec);
+    for (int k = 0; k < nsrc; ++k) {
+      s3[3 * k] = 0;
+      s3[3 * k + 1] = src_idx[2 * k];
+      s3[3 * k + 2] = src_idx[2 * k + 1];
+    }
+    for (int k = 0; k < nrec; ++k) {
+      r3[3 * k] = 0;
+      r3[3 * k + 1] = rec_idx[2 * k];
+      r3[3 * k + 2] = rec_idx[2 * k + 1];
+    }
+    check_nodes(g, nsrc, s3.data(), "source outside the grid");
+    check_nodes(g, nrec, r3.data(), "receiver outside the grid");
+    HELM_REQUIRE((int64_t)nfreq * nsrc * nky < ((int64_t)1 << 20), "too many 2D problems");
+    const helm::SolveOpts so = opts_of(o);
+    check_coarse_sizes(g, so);
+    const PointSet S = on_node_points(g, nsrc, s3.data()), R = on_node_points(g, nrec, r3.data());
+    if (g->dtype == HELM_C64)
+      return model25d_t<float>(ctx, g, m, nfreq, omega, nky, p_kc, v_min, S, src_y, src_amp, mask, R, rec_y, d, f,
+                               grad, d_pred, flags, so, info, stream);
+    return model25d_t<double>(ctx, g, m, nfreq, omega, nky, p_kc, v_min, S, src_y, src_amp, mask, R, rec_y, d, f,
+                              grad, d_pred, flags, so, info, stream);
   });
 }
 

@@ -170,6 +170,14 @@ __global__ void k_layer_tables(cx<double>* tabd, cx<float>* tabf, int n0, int n1
     auto cp = [&](int k) { return table_coef(h, smax, npml, nf, stride, omega, (double)k, 0.5); };
     auto cm = [&](int k) { return table_coef(h, smax, npml, nf, stride, omega, (double)k, -0.5); };
     const cx<double> z = czero<double>();
+    if (na == 1) {  // the absent axis of a 2D grid: no coupling, no diagonal term
+      for (int r = 0; r < 6; ++r) {
+        const int64_t o = (r >= 3 ? tdir : 0) + pre + (r % 3) * na + i;
+        tabd[o] = z;
+        tabf[o] = cast<float>(z);
+      }
+      continue;
+    }
     const cx<double> cpi = cp(i), cmi = cm(i);
     const cx<double> al = (i + 1 < na) ? cpi : z;
     const cx<double> be = (i > 0) ? cmi : z;

@@ -60,7 +60,9 @@ __global__ __launch_bounds__(256) void k_restrict(const Seg* __restrict__ fsegs,
     }
   }
   const T s = rs ? (T)rs[sid] : T(1);
-  rc[C.off + pc] = (s * T(0.125)) * acc;
+  // 1/2 per coarsened axis: 1/8, or 1/4 on a 2D grid (an axis of one node)
+  const T w = (nfx > 1 ? T(0.5) : T(1)) * (nfy > 1 ? T(0.5) : T(1)) * (nfz > 1 ? T(0.5) : T(1));
+  rc[C.off + pc] = (s * w) * acc;
 }
 
 // xf += P xc; lanes own fine points
