@@ -173,7 +173,8 @@ def extras(hx, torch, workloads, dev):
     * WRI objective + gradient over 16 sources (receiver-space CG capped at 4
       steps: 1 + 2 x 4 solves per source);
     * the inversion driver (fwi_invert): 2 frequencies in one band, 2 draws
-      of 16 of the 64 sources, r_sub = 1 (4 L-BFGS iterations per draw)."""
+      of 16 of the 64 sources, r_sub = 1 (4 L-BFGS iterations per draw);
+    * 2.5D misfit + gradient on a 400 x 200 plane (extras_25d)."""
     w = workloads.c3_fwi()
     grid = hx.Grid(n=w.n, h=w.h, npml=w.npml, v_ref=w.v_ref, dtype="c64")
     opts = hx.SolverOpts(tol=1e-6, max_cycles=30)
@@ -234,6 +235,8 @@ def extras(hx, torch, workloads, dev):
     out["wri_misfit_gradient"] = {"sources": 16, "lambda": lam, "cg_steps_max": max(i.cycles for i in sel),
                                   "cg_relres_max": max(i.relres_fp64 for i in sel), "solves": int(nsol),
                                   "s": round(dt, 3), "solves_per_s": round(nsol / dt, 3)}
+    progress("extras: 2.5D modelling, misfit and gradient")
+    out["misfit_gradient_25d"] = extras_25d(hx, torch, workloads, dev, timed)
     progress("extras: inversion driver")
     lo, hi = 1.0 / 4500.0 ** 2, 1.0 / 1500.0 ** 2
     m_run = m_t.clone()
@@ -249,6 +252,35 @@ def extras(hx, torch, workloads, dev):
                          "solves_per_s": round(evals * 2 * 2 * 16 / dt, 3),
                          "f_first": draws[0]["f_start"], "f_last": draws[-1]["f_end"]}
     return out
+
+
+def extras_25d(hx, torch, workloads, dev, timed):
+    """2.5D misfit + gradient on a 400 x 200 plane (h = 10 m, layer 20, 8 Hz,
+    layered 1500-4000 m/s with 4 % perturbations): 32 sources and 96
+    receivers on the plane's top rows at their own offsets along the
+    invariant axis, 30 k_y nodes up to 1.5 omega / v_min, so 960 2D problems
+    per batched solve (forward and adjoint)."""
+    n1, n2, h, npml, f = 400, 200, 10.0, 20, 8.0
+    rng = np.random.default_rng(workloads.SEED_BASE + 25)
+    depth = np.linspace(0.0, 1.0, n2)
+    v = (1500.0 + 2500.0 * depth)[None, None, :] * (1.0 + 0.04 * workloads.gaussian_random_field(rng, (1, n1, n2), 3.0))
+    v = np.clip(v, 1500.0, 4500.0)
+    grid = hx.Grid(n=(1, n1, n2), h=h, npml=npml, v_ref=float(v.max()), dtype="c64")
+    m_t = torch.tensor(1.0 / v ** 2, dtype=torch.float32, device=dev)
+    src = np.column_stack([np.linspace(npml + 5, n1 - npml - 6, 32).astype(int), np.full(32, npml + 2)])
+    rec = np.column_stack([np.linspace(npml + 2, n1 - npml - 3, 96).astype(int), np.full(96, npml + 1)])
+    src_y = np.zeros(32)
+    rec_y = np.tile([0.0, 50.0, 100.0], 32)
+    om = 2 * np.pi * f
+    opts = hx.SolverOpts(tol=1e-6, max_cycles=30)
+    kw = dict(nky=30, p_kc=1.5, v_min=1500.0, opts=opts, raise_on_failure=False)
+    _, _, d_obs, _ = hx.misfit_gradient_25d(grid, m_t * 1.02, om, src, src_y, rec, rec_y, None, **kw)
+    d_obs = d_obs.contiguous()
+    dt, (fv, _, _, infos) = timed(lambda: hx.misfit_gradient_25d(grid, m_t, om, src, src_y, rec, rec_y, d_obs, **kw))
+    nsol = 2 * 32 * 30
+    return {"plane": [n1, n2], "sources": 32, "receivers": 96, "nky": 30, "problems_per_solve": 32 * 30,
+            "solves": nsol, "s": round(dt, 3), "solves_per_s": round(nsol / dt, 2),
+            "max_relres_fp64": max(i.relres_fp64 for i in infos), "misfit": fv}
 
 
 def _c4_member(p):
