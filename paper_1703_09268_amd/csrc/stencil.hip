@@ -652,9 +652,14 @@ __global__ __launch_bounds__(256) void k_h27p(const Seg* __restrict__ segs, cons
   // Consume plane ip from its window w.  OUT: the plane lies outside the
   // grid (all its values are zero); EMIT: output plane ip - 1 is complete
   // after it.
-  auto step = [&](const int ip, const Win& w, auto out_c, auto emit_c) __attribute__((always_inline)) {
+  // DEFER: leave the output pair in `pend` (stored by the caller after the
+  // plane's barrier, so its store overlaps the next plane instead of the
+  // barrier's wait for every outstanding memory operation).
+  c32x2 pend = {0.f, 0.f, 0.f, 0.f};
+  auto step = [&](const int ip, const Win& w, auto out_c, auto emit_c, auto defer_c) __attribute__((always_inline)) {
     constexpr bool OUT = decltype(out_c)::value;
     constexpr bool EMIT = decltype(emit_c)::value;
+    constexpr bool DEFER = decltype(defer_c)::value;
     c32 X[3][4];
     float M[3][4];
 #pragma unroll
@@ -748,7 +753,8 @@ __global__ __launch_bounds__(256) void k_h27p(const Seg* __restrict__ segs, cons
       if (pad1) o1 = czero<float>();
       c32x2 ov;
       ov.a = o0.re; ov.b = o0.im; ov.c = o1.re; ov.d = o1.im;
-      pst_c2(ov, plane_rsrc(reinterpret_cast<char*>(out + S.off) + pob, pbytes), obo);
+      if (DEFER) pend = ov;
+      else pst_c2(ov, plane_rsrc(reinterpret_cast<char*>(out + S.off) + pob, pbytes), obo);
       if (NORM)
         nrm += wn * ((double)o0.re * (double)o0.re + (double)o0.im * (double)o0.im +
                      ((double)o1.re * (double)o1.re + (double)o1.im * (double)o1.im));
@@ -856,33 +862,39 @@ __global__ __launch_bounds__(256) void k_h27p(const Seg* __restrict__ segs, cons
       wait_vmem();
       __syncthreads();
     };
+    auto flush = [&](const int ipo) __attribute__((always_inline)) {  // the deferred output plane ipo
+      pst_c2(pend, plane_rsrc(reinterpret_cast<char*>(out + S.off) + (int64_t)ipo * plane * 8, (uint32_t)plane * 8u),
+             obo);
+    };
     uint32_t cur = 0;
     fill(ip0, cur);
     settle();
     int ip = ip0;
     for (; ip <= i0; ++ip) {
       if (ip + 1 < nx) fill(ip + 1, bstride - cur);
-      step(ip, read_win(cur), std::false_type{}, std::false_type{});
+      step(ip, read_win(cur), std::false_type{}, std::false_type{}, std::false_type{});
       settle();
       cur = bstride - cur;
     }
     for (; ip < i1; ++ip) {
       if (ip + 1 < nx) fill(ip + 1, bstride - cur);
-      step(ip, read_win(cur), std::false_type{}, std::true_type{});
+      step(ip, read_win(cur), std::false_type{}, std::true_type{}, std::true_type{});
       settle();
+      flush(ip - 1);  // after the barrier
       cur = bstride - cur;
     }
     if (i1 < nx)
-      step(i1, read_win(cur), std::false_type{}, std::true_type{});
+      step(i1, read_win(cur), std::false_type{}, std::true_type{}, std::false_type{});
     else
-      step(i1, zero_win(), std::true_type{}, std::true_type{});
+      step(i1, zero_win(), std::true_type{}, std::true_type{}, std::false_type{});
   } else {
-    for (int ip = ip0; ip <= i0; ++ip) step(ip, load(ip), std::false_type{}, std::false_type{});
-    for (int ip = i0 + 1; ip < i1; ++ip) step(ip, load(ip), std::false_type{}, std::true_type{});
+    for (int ip = ip0; ip <= i0; ++ip) step(ip, load(ip), std::false_type{}, std::false_type{}, std::false_type{});
+    for (int ip = i0 + 1; ip < i1; ++ip)
+      step(ip, load(ip), std::false_type{}, std::true_type{}, std::false_type{});
     if (i1 < nx)
-      step(i1, load(i1), std::false_type{}, std::true_type{});
+      step(i1, load(i1), std::false_type{}, std::true_type{}, std::false_type{});
     else
-      step(i1, zero_win(), std::true_type{}, std::true_type{});
+      step(i1, zero_win(), std::true_type{}, std::true_type{}, std::false_type{});
   }
   if (NORM) {
     const double s = block_sum(nrm, red);
