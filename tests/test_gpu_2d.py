@@ -94,3 +94,30 @@ def test_2d_grid_rules():
     x2 = torch.zeros((2, 20, 20), dtype=torch.complex64, device=DEV)
     with pytest.raises(hx.HelmError):  # a first axis of two nodes is neither 2D nor 3D
         hx.helm_apply(hx.Grid(n=(2, 20, 20), h=10.0, npml=0, v_ref=2000.0), m2, 1.0, x2)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_2d_noalloc_matches_apply(dtype):
+    """helm_apply_noalloc on 2D grids, two calls in a row (the second
+    smaller), against helm_apply and the oracle's 2D assembly."""
+    cdt = torch.complex64 if dtype == "c64" else torch.complex128
+    rdt = torch.float32 if dtype == "c64" else torch.float64
+    tol = 1e-5 if dtype == "c64" else 1e-12
+    for k, (n, npml, nrhs) in enumerate((((90, 64), 6, 3), ((40, 30), 3, 2))):
+        print(f"case 2d noalloc {dtype} call {k} n={n}", flush=True)
+        rng, m, vref, omega, h = _case(n, npml, seed=91 + k)
+        grid = hx.Grid(n=(1,) + n, h=h, npml=npml, v_ref=vref, dtype=dtype)
+        m_t = torch.tensor(m, dtype=rdt, device=DEV)
+        x_t = torch.tensor(rng.standard_normal((nrhs, 1) + n) + 1j * rng.standard_normal((nrhs, 1) + n), dtype=cdt,
+                           device=DEV)
+        y_ref = hx.helm_apply(grid, m_t, omega, x_t)
+        y_na = torch.full_like(x_t, float("nan"))
+        hx.helm_apply_noalloc(grid, m_t, omega, x_t, y_na)
+        torch.cuda.synchronize()
+        a = y_na.cpu().numpy().astype(np.complex128)
+        b = y_ref.cpu().numpy().astype(np.complex128)
+        assert np.all(np.isfinite(a)) and np.linalg.norm(a - b) <= tol * np.linalg.norm(b)
+        g = ops.make_grid((1,) + n, h, npml, omega, vref)
+        H = m25.assemble2d(g, m_t.cpu().numpy().astype(np.float64), 0.0)
+        ref = H @ x_t[-1].cpu().numpy().astype(np.complex128).ravel()
+        assert np.linalg.norm(a[-1].ravel() - ref) <= tol * np.linalg.norm(ref)
