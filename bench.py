@@ -516,7 +516,7 @@ def stencil_timing(hx, torch, grid, m_t, w, S, reps, dev):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (one process per GPU; the "
+        print("bench.py: this benchmark measures one GPU only (one process per GPU; the "
               "multi-GPU sharding over (source, frequency) pairs is not part of it). "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)

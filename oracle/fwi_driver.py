@@ -12,8 +12,8 @@ r_sub * ceil(N_s / p) iterations per subproblem; the approximate minimiser
 warm-starts the next draw, T draws; |I_k| grows by a fixed amount when a line
 search fails; the 3D example clamps the water layer to the true model, i.e.
 per-point bounds).  The paper calls an external box-constrained quasi-Newton
-code without describing its steps; the projected L-BFGS below is this
-build's reading, written out in full:
+code without describing its steps; the projected L-BFGS below is the
+reading taken here, written out in full:
 
 At x with gradient g the free set F leaves out variables at a bound whose
 gradient points out of the box (x <= lo with g > 0, or x >= hi with g < 0).
