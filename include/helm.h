@@ -44,8 +44,11 @@
  * Errors: every entry point returns a helm_status; nothing throws or aborts
  * across the ABI.  On an error return helm_last_error(ctx) describes it.
  * Invalid arguments (null pointers, sizes < 3, npml >= n/2, omega <= 0,
- * nrhs < 1, out-of-grid source or receiver nodes, unknown enums) return
- * HELM_E_INVAL before any device work is enqueued.
+ * nrhs < 1, out-of-grid source or receiver nodes, unknown enums, more than
+ * 65535 (frequency, source) pairs, or more than 65535 2D problems
+ * nfreq*nsrc*nky in the 2.5D entry point) return HELM_E_INVAL before any
+ * device work is enqueued.  The pair limit is that of a launch's second grid
+ * dimension, which the per-pair kernels index by pair.
  */
 #ifndef HELM_H
 #define HELM_H

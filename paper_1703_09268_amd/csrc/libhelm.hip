@@ -1273,13 +1273,17 @@ helm_status model25d_t(helm_ctx* ctx, const helm_grid* g, const void* m, int nfr
   return (helm_status)worst;
 }
 
+// Per-pair kernels take the pair from blockIdx.y, whose extent HIP bounds by
+// 65536 blocks.
+constexpr int64_t kMaxPairs = 65535;
+
 void check_pair_args(const helm_grid* g, const void* m, int nfreq, const double* omega, int nsrc, int nrec) {
   check_grid(g);
   HELM_REQUIRE(m, "null model pointer");
   HELM_REQUIRE(nfreq >= 1 && omega, "nfreq must be >= 1 with an omega array");
   for (int k = 0; k < nfreq; ++k) HELM_REQUIRE(omega[k] > 0.0 && std::isfinite(omega[k]), "omega must be positive");
   HELM_REQUIRE(nsrc >= 1 && nrec >= 1, "nsrc and nrec must be >= 1");
-  HELM_REQUIRE((int64_t)nfreq * nsrc <= (1 << 20), "too many (frequency, source) pairs");
+  HELM_REQUIRE((int64_t)nfreq * nsrc <= kMaxPairs, "more than 65535 (frequency, source) pairs");
 }
 
 void check_nodes(const helm_grid* g, int n, const int32_t* idx, const char* what) {
@@ -1676,7 +1680,7 @@ helm_status misfit_gradient_25d(helm_ctx* ctx, const helm_grid* g, const void* m
     }
     check_nodes(g, nsrc, s3.data(), "source outside the grid");
     check_nodes(g, nrec, r3.data(), "receiver outside the grid");
-    HELM_REQUIRE((int64_t)nfreq * nsrc * nky < ((int64_t)1 << 20), "too many 2D problems");
+    HELM_REQUIRE((int64_t)nfreq * nsrc * nky <= kMaxPairs, "more than 65535 2D problems (nfreq*nsrc*nky)");
     const helm::SolveOpts so = opts_of(o);
     check_coarse_sizes(g, so);
     const PointSet S = on_node_points(g, nsrc, s3.data()), R = on_node_points(g, nrec, r3.data());

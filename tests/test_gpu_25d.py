@@ -102,3 +102,9 @@ def test_25d_argument_checks():
     m3 = torch.ones(tuple(g3.n), dtype=torch.float32, device=DEV) * 1e-7
     with pytest.raises(hx.HelmError):
         hx.misfit_gradient_25d(g3, m3, OMEGAS, P["src"], P["src_y"], P["rec"], P["rec_y"], P["d_t"])
+    # 2 frequencies x 8 sources x 4096 nodes = 65536 2D problems: one more
+    # than the second grid dimension of the per-problem kernels holds
+    src8, y8 = np.repeat(P["src"][:1], 8, axis=0), np.zeros(8)
+    d8 = torch.zeros((2, 8, len(P["rec"])), dtype=P["d_t"].dtype, device=DEV)
+    with pytest.raises(hx.HelmError, match="65535"):
+        hx.misfit_gradient_25d(P["grid"], P["m_t"], OMEGAS, src8, y8, P["rec"], P["rec_y"], d8, nky=4096)

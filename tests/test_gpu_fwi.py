@@ -122,6 +122,12 @@ def test_accumulate_and_forward_only_flags():
         bad = np.array(w.rec)
         bad[0, 0] = w.n[0]
         hx.misfit_gradient(grid, m_t, w.omega, w.src, bad, d_t, opts=opts)
+    # the per-pair kernels index pairs by the second grid dimension: 65536
+    # (frequency, source) pairs are refused before any device work
+    many = np.repeat(np.asarray(w.src)[:1], 65536, axis=0)
+    d_many = torch.zeros((1, 65536, len(w.rec)), dtype=d_t.dtype, device=DEV)
+    with pytest.raises(hx.HelmError, match="65535"):
+        hx.misfit_gradient(grid, m_t, w.omega, many, w.rec, d_many, opts=opts)
 
 
 @pytest.mark.parametrize("stencil", ["7pt", "27pt"])
