@@ -247,7 +247,7 @@ struct LevelSet {
   int nsblk = 0, nvblk = 0, ntblk = 0;
   int sblk_bound = 1;  // stencil workgroups at the smallest x chunk
   int xchunk = 0;      // current x chunk of the stencil tiles
-  int interleave = 0;  // 1: the segments of a tile get consecutive workgroups (segment fastest)
+  int group = 1;       // segments per tile group (1: segment-major; see layout_stencil)
   bool pair = false;   // every segment uses pair stencil tiles
   int stage27 = 0;     // LDS bytes per workgroup of the staged 27-point pass (0: register path)
   int64_t total = 0;  // vector length (sum of N)
@@ -482,14 +482,17 @@ class Hierarchy {
 
   // Stencil workgroup layout of level l for x chunk `xchunk`: segment ranges,
   // workgroup -> (segment, tile) maps, uploaded.  When every segment of a
-  // small level has the same geometry and model (the sources of one
-  // frequency), the segments of one tile get consecutive workgroup ids
-  // (segment fastest), so they run together on one XCD and read that tile of
-  // the model once into its L2.
-  // interleave: -1 chooses (the size rule below, or HELM_INTERLEAVE), 0 / 1
-  // forces segment-major / segment-fastest order where the segments share
-  // grid and model (segment-major otherwise).
-  void layout_stencil(int l, int xchunk, int interleave = -1) {
+  // level has the same geometry and model (the sources of one frequency), the
+  // segments may be taken in groups of `group`: inside a group the segments
+  // of one tile get consecutive workgroup ids (segment fastest), so they run
+  // together on one XCD and read that tile of the model once into its L2;
+  // the groups follow one another.  group 1 is segment-major order (one
+  // right-hand side's neighbouring tiles together, the model read once per
+  // XCD and segment), group >= the segment count interleaves all of them.
+  // group: -1 chooses (the size rule below, or HELM_INTERLEAVE /
+  // HELM_TILE_GROUP); segment-major wherever the segments do not share grid
+  // and model.
+  void layout_stencil(int l, int xchunk, int group = -1) {
     LevelSet& L = *lev_[l];
     const int ns = (int)L.host.size();
     xchunk = std::max(xchunk, kMinXchunk);
@@ -506,18 +509,24 @@ class Hierarchy {
     L.nsblk = sb;
     L.xchunk = xchunk;
     std::vector<int> smap(std::max(sb, 1)), slocal(std::max(sb, 1));
-    // (measured: pays on small levels, where the model tile is most of a
-    // tile's distinct data; on 128^3 and larger, keeping one right-hand
-    // side's neighbouring tiles on one XCD is worth more)
-    const char* il = std::getenv("HELM_INTERLEAVE");  // 1 / 0: force on / off (tile experiments)
-    const bool want = interleave >= 0 ? interleave == 1
-                                      : (il ? il[0] == '1' : L.host[0].N <= ((int64_t)1 << 20));
-    const bool shared = want && can_interleave(l);
-    L.interleave = shared ? 1 : 0;
+    // (measured: full interleaving pays on small levels, where the model
+    // tile is most of a tile's distinct data; on 128^3 and larger, keeping
+    // one right-hand side's neighbouring tiles on one XCD is worth more)
+    if (group < 0) {
+      group = L.host[0].N <= ((int64_t)1 << 20) ? ns : 1;
+      if (const char* il = std::getenv("HELM_INTERLEAVE"))  // 1 / 0: all / none (tile experiments)
+        group = il[0] == '1' ? ns : 1;
+      if (const char* tg = std::getenv("HELM_TILE_GROUP"))  // segments per group (tile experiments)
+        if (std::atoi(tg) >= 1) group = std::atoi(tg);
+    }
+    group = can_interleave(l) ? std::max(1, std::min(group, ns)) : 1;
+    L.group = group;
     for (int s = 0; s < ns; ++s) {
       const Seg& S = L.host[s];
+      // group g = s / group holds segments [s0, s0 + gs), all with snblk tiles
+      const int s0 = s - s % group, gs = std::min(group, ns - s0);
       for (int b = 0; b < S.snblk; ++b) {
-        const int wg = shared ? b * ns + s : S.sblk0 + b;
+        const int wg = group == 1 ? S.sblk0 + b : S.sblk0 - (s - s0) * S.snblk + b * gs + (s - s0);
         smap[wg] = s;
         slocal[wg] = b;
       }
@@ -683,15 +692,15 @@ int launch_h(const LevelSet& L, const cx<TX>* x, const double* xs, const cx<TB>*
   return launch_h<TC, TX, TM, TB, TO, RESID, NORM>(L.view(), x, xs, b, bs, out, part, active, st);
 }
 
-// Tile choice of one level: x chunk of the stencil march and segment order.
+// Tile choice of one level: x chunk of the stencil march and segment group.
 struct TileChoice {
   int xchunk = 0;
-  int interleave = 0;
+  int group = 1;
 };
 
 // On-disk record of tile choices, so that a problem set gets the same tiles
 // (hence bitwise the same results) in every process on the same kind of GPU:
-// one line "key<TAB>xchunk<TAB>interleave" per choice, in the file named by
+// one line "key<TAB>xchunk<TAB>group" per choice, in the file named by
 // HELM_TUNE_CACHE (set but empty: no file), else
 // $XDG_CACHE_HOME/helm/tiles.tsv or $HOME/.cache/helm/tiles.tsv.  Keys carry
 // the record format and the device (architecture, compute units).  A file
@@ -716,8 +725,7 @@ inline void tune_cache_load(const std::string& path, std::map<std::string, TileC
     if (!t1) continue;
     *t1 = '\0';
     TileChoice c;
-    if (std::sscanf(t1 + 1, "%d\t%d", &c.xchunk, &c.interleave) == 2 && c.xchunk >= kMinXchunk &&
-        (c.interleave == 0 || c.interleave == 1))
+    if (std::sscanf(t1 + 1, "%d\t%d", &c.xchunk, &c.group) == 2 && c.xchunk >= kMinXchunk && c.group >= 1)
       cache[line] = c;
   }
   std::fclose(f);
@@ -734,7 +742,7 @@ inline void tune_cache_store(const std::string& path, const std::string& key, co
   }
   FILE* f = std::fopen(path.c_str(), "a");
   if (!f) return;
-  std::fprintf(f, "%s\t%d\t%d\n", key.c_str(), c.xchunk, c.interleave);
+  std::fprintf(f, "%s\t%d\t%d\n", key.c_str(), c.xchunk, c.group);
   std::fclose(f);
 }
 
@@ -768,7 +776,7 @@ void tune_tiles(Hierarchy& H, const std::string& kind, Run run, hipStream_t st) 
     tune_cache_load(path, cache);
     loaded_from = path;
   }
-  const std::string prefix = "tiles2|" + device_tag() + "|" + kind + "|";
+  const std::string prefix = "tiles3|" + device_tag() + "|" + kind + "|";
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HELM_HIP_CHECK(hipEventCreate(&e0));
   HELM_HIP_CHECK(hipEventCreate(&e1));
@@ -778,8 +786,8 @@ void tune_tiles(Hierarchy& H, const std::string& kind, Run run, hipStream_t st) 
       const std::string key = prefix + H.tile_key(l);
       auto it = cache.find(key);
       if (it != cache.end()) {
-        if (it->second.xchunk != H.level(l).xchunk || it->second.interleave != H.level(l).interleave)
-          H.layout_stencil(l, it->second.xchunk, it->second.interleave);
+        if (it->second.xchunk != H.level(l).xchunk || it->second.group != H.level(l).group)
+          H.layout_stencil(l, it->second.xchunk, it->second.group);
         continue;
       }
       int nxm = 0;
@@ -788,9 +796,14 @@ void tune_tiles(Hierarchy& H, const std::string& kind, Run run, hipStream_t st) 
       std::vector<int> cand = {H.level(l).xchunk, nxm, (nxm + 1) / 2, (nxm + 3) / 4, 32, 16, 8, kMinXchunk};
       std::sort(cand.begin(), cand.end());
       cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
-      std::vector<int> orders = {H.level(l).interleave};
-      if (H.can_interleave(l)) orders.push_back(1 - H.level(l).interleave);
-      TileChoice best{H.level(l).xchunk, H.level(l).interleave};
+      // segment orders: the heuristic's first, then segment-major, groups of
+      // 2 and 4, all segments (where the segments share grid and model)
+      const int ns = (int)H.level(l).host.size();
+      std::vector<int> orders = {H.level(l).group};
+      if (H.can_interleave(l))
+        for (int gr : {1, 2, 4, ns})
+          if (gr <= ns && std::find(orders.begin(), orders.end(), gr) == orders.end()) orders.push_back(gr);
+      TileChoice best{H.level(l).xchunk, H.level(l).group};
       float best_ms = 1e30f;
       const bool verbose = std::getenv("HELM_VERBOSE") != nullptr;
       std::string trace;
@@ -807,17 +820,18 @@ void tune_tiles(Hierarchy& H, const std::string& kind, Run run, hipStream_t st) 
           float ms = 0.f;
           HELM_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
           if (verbose)
-            trace += " " + std::to_string(c) + (order ? "i" : "") + ":" + std::to_string(ms / reps * 1e3f) + "us";
+            trace += " " + std::to_string(c) + "g" + std::to_string(L.group) + ":" + std::to_string(ms / reps * 1e3f) +
+                     "us";
           if (ms < best_ms) {
             best_ms = ms;
-            best = TileChoice{c, L.interleave};
+            best = TileChoice{c, L.group};
           }
         }
       }
       if (verbose)
-        fprintf(stderr, "helm tiles %s level %d -> x chunk %d%s (%s)\n", kind.c_str(), l, best.xchunk,
-                best.interleave ? " interleaved" : "", trace.c_str());
-      H.layout_stencil(l, best.xchunk, best.interleave);
+        fprintf(stderr, "helm tiles %s level %d -> x chunk %d, segment group %d (%s)\n", kind.c_str(), l, best.xchunk,
+                best.group, trace.c_str());
+      H.layout_stencil(l, best.xchunk, best.group);
       cache[key] = best;
       tune_cache_store(path, key, best);
     }

@@ -155,8 +155,8 @@ def test_tile_choice_recorded_on_disk(tmp_path, monkeypatch):
     torch.cuda.synchronize()
     lines = [ln.split("\t") for ln in path.read_text().splitlines()]
     mine = [ln for ln in lines if "41x29x34" in ln[0]]
-    assert len(mine) == 1 and mine[0][0].startswith("tiles2|gfx") and "|apply|" in mine[0][0]
-    assert int(mine[0][1]) >= 4 and mine[0][2] in ("0", "1")
+    assert len(mine) == 1 and mine[0][0].startswith("tiles3|gfx") and "|apply|" in mine[0][0]
+    assert int(mine[0][1]) >= 4 and mine[0][2] in ("1", "2", "3")  # segments per tile group
     monkeypatch.setenv("HELM_AUTOTUNE", "0")
     # another operator in between, so that the next call rebuilds this one
     # (now with the heuristic tiles) instead of reusing the tuned one
@@ -165,3 +165,26 @@ def test_tile_choice_recorded_on_disk(tmp_path, monkeypatch):
     torch.cuda.synchronize()
     assert torch.equal(y1, y3)
     assert y2.shape == y1.shape
+
+
+@pytest.mark.parametrize("stencil", ["7pt", "27pt"])
+def test_tile_groups_give_the_same_values(stencil, monkeypatch):
+    """Five right-hand sides sharing grid and model, their tiles taken
+    segment-major, in groups of 2 (the last group ragged), of 3 and all
+    interleaved: only the workgroup order changes, so the operator's values
+    are bitwise those of the segment-major order."""
+    n = (23, 19, 36)
+    rng, m, vref, omega, h = _case(n, 3, seed=91)
+    grid = hx.Grid(n=n, h=h, npml=3, v_ref=vref, dtype="c64", stencil=stencil)
+    m_t = _to_dev(m, torch.float32)
+    x_t = _to_dev(workloads.random_complex(rng, (5,) + n), torch.complex64)
+    monkeypatch.setenv("HELM_AUTOTUNE", "0")
+    ys = []
+    for group in ("1", "2", "3", "5"):
+        print(f"case tile group {group} {stencil}", flush=True)
+        monkeypatch.setenv("HELM_TILE_GROUP", group)
+        hx.helm_apply(grid, m_t, omega * (1 + 1e-15), x_t)  # evicts the cached operator
+        ys.append(hx.helm_apply(grid, m_t, omega, x_t))
+    torch.cuda.synchronize()
+    for y in ys[1:]:
+        assert torch.equal(y, ys[0])

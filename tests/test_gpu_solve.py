@@ -225,3 +225,26 @@ def test_27pt_adjoint_after_forward_on_one_solver():
     for s in range(len(w.src)):
         ue = lu(q[s], adjoint=True)
         assert np.linalg.norm(u[s] - ue) <= 1e-5 * np.linalg.norm(ue)
+
+
+def test_tile_groups_leave_the_solve_bitwise_unchanged(monkeypatch):
+    """The inner-product partials of the fused stencil passes are indexed by
+    (segment, tile), not by workgroup, and summed in a fixed order: a
+    multi-source solve gives bitwise the same fields and cycle counts whatever
+    the segment grouping of the stencil tiles."""
+    w = workloads.c1_small()
+    grid, g, m_t, m_used, cdt = _setup(w, "c64")
+    src = [(8 + 2 * k, 10 + k, 9 + 3 * k) for k in range(5)]
+    q, q_t = _sources(g, src, cdt)
+    monkeypatch.setenv("HELM_AUTOTUNE", "0")
+    outs = []
+    for group in ("1", "2", "5"):
+        print(f"case solve tile group {group}", flush=True)
+        monkeypatch.setenv("HELM_TILE_GROUP", group)
+        hx.helm_solve(grid, m_t, w.omega * (1 + 1e-15), q_t[:1], opts=hx.SolverOpts(max_cycles=1),
+                      raise_on_failure=False)  # evicts the cached solver
+        outs.append(hx.helm_solve(grid, m_t, w.omega, q_t, opts=hx.SolverOpts(tol=1e-6)))
+    torch.cuda.synchronize()
+    for u, info in outs[1:]:
+        assert torch.equal(u, outs[0][0])
+        assert [i.cycles for i in info] == [i.cycles for i in outs[0][1]]
