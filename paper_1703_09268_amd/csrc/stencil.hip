@@ -866,19 +866,25 @@ __global__ __launch_bounds__(256) void k_h27p(const Seg* __restrict__ segs, cons
       pst_c2(pend, plane_rsrc(reinterpret_cast<char*>(out + S.off) + (int64_t)ipo * plane * 8, (uint32_t)plane * 8u),
              obo);
     };
+    // Each plane's window is read from LDS before the next plane's fill is
+    // issued: an LDS read after the fill would wait for it (the fill may
+    // write any LDS address as far as the compiler knows), so this order
+    // lets the plane's arithmetic run while its wave's fill is in flight.
     uint32_t cur = 0;
     fill(ip0, cur);
     settle();
     int ip = ip0;
     for (; ip <= i0; ++ip) {
+      const Win w = read_win(cur);
       if (ip + 1 < nx) fill(ip + 1, bstride - cur);
-      step(ip, read_win(cur), std::false_type{}, std::false_type{}, std::false_type{});
+      step(ip, w, std::false_type{}, std::false_type{}, std::false_type{});
       settle();
       cur = bstride - cur;
     }
     for (; ip < i1; ++ip) {
+      const Win w = read_win(cur);
       if (ip + 1 < nx) fill(ip + 1, bstride - cur);
-      step(ip, read_win(cur), std::false_type{}, std::true_type{}, std::true_type{});
+      step(ip, w, std::false_type{}, std::true_type{}, std::true_type{});
       settle();
       flush(ip - 1);  // after the barrier
       cur = bstride - cur;
