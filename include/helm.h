@@ -49,6 +49,13 @@
  * nfreq*nsrc*nky in the 2.5D entry point) return HELM_E_INVAL before any
  * device work is enqueued.  The pair limit is that of a launch's second grid
  * dimension, which the per-pair kernels index by pair.
+ * Non-finite inputs: with the environment variable HELM_CHECK=1 every call
+ * but helm_apply_noalloc first scans its device inputs -- the model, the
+ * operator input or right-hand sides, initial guesses (warm_start), the
+ * derivative input, and the data rows of the selected (frequency, source)
+ * pairs -- and returns HELM_E_INVAL naming the array that holds a NaN or
+ * Inf; the scan runs on `stream` and synchronises it.  Without it such
+ * values propagate (a solve then returns HELM_BREAKDOWN).
  */
 #ifndef HELM_H
 #define HELM_H

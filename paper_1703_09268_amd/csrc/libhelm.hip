@@ -42,6 +42,7 @@ struct helm_ctx {
   helm::DevBuf fwi_small;
   helm::DevBuf batch_buf;        // concatenated q / u of a batched solve
   helm::DevBuf drv_buf;          // L-BFGS vectors of the inversion driver
+  helm::DevBuf chk;              // flags of the input scan (HELM_CHECK=1)
   CachedSolver solver;
   std::unique_ptr<helm::Hierarchy> apply_h;  // operator of the last helm_apply
   std::string apply_key;
@@ -1350,6 +1351,98 @@ helm_status derivative_common(helm_ctx* ctx, int mode, const helm_grid* g, const
 
 #include "driver.hip"
 
+// Opt-in input scan (environment HELM_CHECK=1): a NaN or Inf in a caller's
+// input array returns HELM_E_INVAL naming the array.  One pass per array on
+// the caller's stream and a synchronisation of that stream, before the
+// call's own work; rows of unselected (frequency, source) pairs, which the
+// calls do not read, are not scanned.
+bool input_check_on() {
+  const char* e = std::getenv("HELM_CHECK");
+  return e && e[0] == '1';
+}
+
+// flag[blockIdx.y * gridDim.x + blockIdx.x] = 1 if any of the n scalars of
+// row blockIdx.y (at a + row_off[blockIdx.y], or at a without row_off) is
+// not finite
+template <typename T>
+__global__ __launch_bounds__(256) void k_nonfinite(const T* __restrict__ a, const int64_t* __restrict__ row_off,
+                                                   int64_t n, int* __restrict__ flag) {
+  const T* r = a + (row_off ? row_off[blockIdx.y] : 0);
+  int bad = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    bad |= isfinite(r[i]) ? 0 : 1;
+  bad = __syncthreads_or(bad);
+  if (threadIdx.x == 0) flag[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = bad;
+}
+
+// n scalars (double with dbl, else float) per row; rows at the scalar
+// offsets `off` (at most 65535 of them), or one row at a when off is NULL
+void scan_finite(helm_ctx* ctx, const void* a, int64_t n, const std::vector<int64_t>* off, bool dbl,
+                 const std::string& what, void* stream) {
+  if (!a || n <= 0 || (off && off->empty())) return;
+  hipStream_t st = (hipStream_t)stream;
+  const int nrow = off ? (int)off->size() : 1;
+  const unsigned nb = (unsigned)std::min<int64_t>(off ? 16 : 1024, helm::ceil_div(n, 256));
+  const size_t fb = ((size_t)nrow * nb * sizeof(int) + 255) / 256 * 256;
+  ctx->chk.ensure(fb + (off ? off->size() * sizeof(int64_t) : 0));
+  int* flag = (int*)ctx->chk.p;
+  int64_t* doff = off ? (int64_t*)((char*)ctx->chk.p + fb) : nullptr;
+  if (doff)
+    HELM_HIP_CHECK(hipMemcpyAsync(doff, off->data(), off->size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  if (dbl)
+    hipLaunchKernelGGL(k_nonfinite<double>, dim3(nb, nrow), dim3(256), 0, st, (const double*)a,
+                       (const int64_t*)doff, n, flag);
+  else
+    hipLaunchKernelGGL(k_nonfinite<float>, dim3(nb, nrow), dim3(256), 0, st, (const float*)a,
+                       (const int64_t*)doff, n, flag);
+  HELM_HIP_CHECK(hipGetLastError());
+  std::vector<int> h((size_t)nrow * nb);
+  HELM_HIP_CHECK(hipMemcpyAsync(h.data(), flag, h.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+  HELM_HIP_CHECK(hipStreamSynchronize(st));
+  for (int v : h) HELM_REQUIRE(v == 0, "non-finite value (NaN or Inf) in " + what + " (HELM_CHECK=1)");
+}
+
+int64_t grid_points(const helm_grid* g) { return (int64_t)g->n[0] * g->n[1] * g->n[2]; }
+
+// the model and, over the selected (frequency, source) rows, an array of
+// nrec complex values per pair (data, or the adjoint Jacobian's input)
+void scan_model(helm_ctx* ctx, const helm_grid* g, const void* m, void* stream) {
+  scan_finite(ctx, m, grid_points(g), nullptr, g->dtype == HELM_C128, "the model m", stream);
+}
+void scan_pair_rows(helm_ctx* ctx, const helm_grid* g, int nfreq, int nsrc, const uint8_t* mask, int nrec,
+                    const void* a, const std::string& what, void* stream) {
+  std::vector<int64_t> off;
+  for (int k = 0; k < nfreq * nsrc; ++k)
+    if (!mask || mask[k]) off.push_back((int64_t)k * nrec * 2);
+  scan_finite(ctx, a, (int64_t)nrec * 2, &off, g->dtype == HELM_C128, what, stream);
+}
+
+void scan_misfit_inputs(helm_ctx* ctx, const helm_grid* g, const void* m, int nfreq, int nsrc, const uint8_t* mask,
+                        int nrec, const void* d, void* stream) {
+  if (!input_check_on()) return;
+  scan_model(ctx, g, m, stream);
+  scan_pair_rows(ctx, g, nfreq, nsrc, mask, nrec, d, "the data d", stream);
+}
+
+void scan_derivative_inputs(helm_ctx* ctx, int mode, const helm_grid* g, const void* m, int nfreq, int nsrc,
+                            const uint8_t* mask, int nrec, const void* input, const void* d, void* stream) {
+  if (!input_check_on()) return;
+  scan_model(ctx, g, m, stream);
+  if (mode == HELM_JACOB_ADJ)
+    scan_pair_rows(ctx, g, nfreq, nsrc, mask, nrec, input, "the input y", stream);
+  else
+    scan_finite(ctx, input, grid_points(g), nullptr, g->dtype == HELM_C128, "the input dm", stream);
+  if (mode == HELM_HESS) scan_pair_rows(ctx, g, nfreq, nsrc, mask, nrec, d, "the data d", stream);
+}
+
+// (the bounds may be infinite; a NaN bound is rejected by the driver itself)
+void scan_fwi_inputs(helm_ctx* ctx, const helm_grid* g, const void* m, int nfreq, int nsrc, int nrec, const void* d,
+                     void* stream) {
+  if (!input_check_on()) return;
+  scan_model(ctx, g, m, stream);
+  scan_finite(ctx, d, 2 * (int64_t)nfreq * nsrc * nrec, nullptr, g->dtype == HELM_C128, "the data d", stream);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1440,6 +1533,10 @@ helm_status helm_apply(helm_ctx* ctx, const helm_grid* g, const void* m, double 
     HELM_REQUIRE(omega > 0.0 && std::isfinite(omega), "omega must be positive");
     HELM_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
     HELM_REQUIRE(x != y, "x and y must not overlap");
+    if (input_check_on()) {
+      scan_model(ctx, g, m, stream);
+      scan_finite(ctx, x, 2 * grid_points(g) * nrhs, nullptr, g->dtype == HELM_C128, "the input x", stream);
+    }
     hipStream_t st = (hipStream_t)stream;
     auto probs = shared_problems(g, m, omega, adjoint ? 1 : 0, nrhs);
     const helm::SolveOpts so = opts_of(nullptr);
@@ -1495,6 +1592,12 @@ helm_status helm_solve(helm_ctx* ctx, const helm_grid* g, const void* m, double 
     HELM_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
     const helm::SolveOpts so = opts_of(o);
     check_coarse_sizes(g, so);
+    if (input_check_on()) {
+      const bool dbl = g->dtype == HELM_C128;
+      scan_model(ctx, g, m, stream);
+      scan_finite(ctx, q, 2 * grid_points(g) * nrhs, nullptr, dbl, "the right-hand side q", stream);
+      if (so.warm_start) scan_finite(ctx, u, 2 * grid_points(g) * nrhs, nullptr, dbl, "the initial guess u", stream);
+    }
     if (g->dtype == HELM_C64) return solve_t<float>(ctx, g, m, omega, adjoint ? 1 : 0, nrhs, q, u, so, info, stream);
     return solve_t<double>(ctx, g, m, omega, adjoint ? 1 : 0, nrhs, q, u, so, info, stream);
   });
@@ -1513,6 +1616,16 @@ helm_status helm_solve_batched(helm_ctx* ctx, int nprob, const helm_problem* pro
       HELM_REQUIRE(probs[i].grid.dtype == probs[0].grid.dtype, "all problems must have the same dtype");
       HELM_REQUIRE(probs[i].grid.stencil == probs[0].grid.stencil, "all problems must use the same stencil");
     }
+    if (input_check_on())
+      for (int i = 0; i < nprob; ++i) {
+        const helm_grid* gi = &probs[i].grid;
+        const bool dbl = gi->dtype == HELM_C128;
+        const std::string pre = "problem " + std::to_string(i) + ": ";
+        scan_finite(ctx, probs[i].m, grid_points(gi), nullptr, dbl, pre + "the model m", stream);
+        scan_finite(ctx, probs[i].q, 2 * grid_points(gi), nullptr, dbl, pre + "the right-hand side q", stream);
+        if (so.warm_start)
+          scan_finite(ctx, probs[i].u, 2 * grid_points(gi), nullptr, dbl, pre + "the initial guess u", stream);
+      }
     if (probs[0].grid.dtype == HELM_C64)
       return solve_batched_t<float>(ctx, nprob, probs, adjoint ? 1 : 0, so, info, stream);
     return solve_batched_t<double>(ctx, nprob, probs, adjoint ? 1 : 0, so, info, stream);
@@ -1528,6 +1641,7 @@ helm_status misfit_gradient(helm_ctx* ctx, const helm_grid* g, const void* m, in
     HELM_REQUIRE(src_idx && rec_idx, "null source / receiver index array");
     check_nodes(g, nsrc, src_idx, "source outside the grid");
     check_nodes(g, nrec, rec_idx, "receiver outside the grid");
+    scan_misfit_inputs(ctx, g, m, nfreq, nsrc, mask, nrec, d, stream);
     return misfit_common(ctx, g, m, nfreq, omega, on_node_points(g, nsrc, src_idx), src_amp, mask,
                          on_node_points(g, nrec, rec_idx), d, f, grad, u_store, flags, o, info, stream);
   });
@@ -1542,6 +1656,7 @@ helm_status misfit_gradient_offgrid(helm_ctx* ctx, const helm_grid* g, const voi
     check_pair_args(g, m, nfreq, omega, nsrc, nrec);
     HELM_REQUIRE(src_pos && rec_pos, "null source / receiver position array");
     check_sinc(g, nsrc, src_pos, nrec, rec_pos, radius, kaiser_b);
+    scan_misfit_inputs(ctx, g, m, nfreq, nsrc, mask, nrec, d, stream);
     return misfit_common(ctx, g, m, nfreq, omega, sinc_points(g, nsrc, src_pos, radius, kaiser_b), src_amp, mask,
                          sinc_points(g, nrec, rec_pos, radius, kaiser_b), d, f, grad, u_store, flags, o, info,
                          stream);
@@ -1558,6 +1673,7 @@ helm_status pde_derivative(helm_ctx* ctx, int mode, const helm_grid* g, const vo
     HELM_REQUIRE(src_idx && rec_idx, "null source / receiver index array");
     check_nodes(g, nsrc, src_idx, "source outside the grid");
     check_nodes(g, nrec, rec_idx, "receiver outside the grid");
+    scan_derivative_inputs(ctx, mode, g, m, nfreq, nsrc, mask, nrec, input, d, stream);
     return derivative_common(ctx, mode, g, m, nfreq, omega, on_node_points(g, nsrc, src_idx), src_amp, mask,
                              on_node_points(g, nrec, rec_idx), input, d, output, u_store, flags, o, info, stream);
   });
@@ -1572,6 +1688,7 @@ helm_status pde_derivative_offgrid(helm_ctx* ctx, int mode, const helm_grid* g, 
     check_pair_args(g, m, nfreq, omega, nsrc, nrec);
     HELM_REQUIRE(src_pos && rec_pos, "null source / receiver position array");
     check_sinc(g, nsrc, src_pos, nrec, rec_pos, radius, kaiser_b);
+    scan_derivative_inputs(ctx, mode, g, m, nfreq, nsrc, mask, nrec, input, d, stream);
     return derivative_common(ctx, mode, g, m, nfreq, omega, sinc_points(g, nsrc, src_pos, radius, kaiser_b),
                              src_amp, mask, sinc_points(g, nrec, rec_pos, radius, kaiser_b), input, d, output,
                              u_store, flags, o, info, stream);
@@ -1598,6 +1715,7 @@ helm_status fwi_invert(helm_ctx* ctx, const helm_grid* g, void* m, const double*
     HELM_REQUIRE(src_idx && rec_idx, "null source / receiver index array");
     check_nodes(g, nsrc, src_idx, "source outside the grid");
     check_nodes(g, nrec, rec_idx, "receiver outside the grid");
+    scan_fwi_inputs(ctx, g, m, nfreq, nsrc, nrec, d, stream);
     return fwi_common(ctx, g, m, lo, hi, nfreq, omega, on_node_points(g, nsrc, src_idx), src_amp,
                       on_node_points(g, nrec, rec_idx), d, p, o, draws, sources, recs, rec_cap, nrecs, stream);
   });
@@ -1613,6 +1731,7 @@ helm_status fwi_invert_offgrid(helm_ctx* ctx, const helm_grid* g, void* m, const
     check_pair_args(g, m, nfreq, omega, nsrc, nrec);
     HELM_REQUIRE(src_pos && rec_pos, "null source / receiver position array");
     check_sinc(g, nsrc, src_pos, nrec, rec_pos, radius, kaiser_b);
+    scan_fwi_inputs(ctx, g, m, nfreq, nsrc, nrec, d, stream);
     return fwi_common(ctx, g, m, lo, hi, nfreq, omega, sinc_points(g, nsrc, src_pos, radius, kaiser_b), src_amp,
                       sinc_points(g, nrec, rec_pos, radius, kaiser_b), d, p, o, draws, sources, recs, rec_cap, nrecs,
                       stream);
@@ -1639,6 +1758,7 @@ helm_status wri_misfit_gradient(helm_ctx* ctx, const helm_grid* g, const void* m
     HELM_REQUIRE(cg_max >= 0, "cg_max must be >= 0");
     const helm::SolveOpts so = opts_of(o);
     check_coarse_sizes(g, so);
+    scan_misfit_inputs(ctx, g, m, nfreq, nsrc, mask, nrec, d, stream);
     const PointSet S = on_node_points(g, nsrc, src_idx), R = on_node_points(g, nrec, rec_idx);
     if (g->dtype == HELM_C64)
       return wri_t<float>(ctx, g, m, nfreq, omega, S, src_amp, mask, R, d, lambda, cg_tol, cg_max, f, grad, u_store,
@@ -1683,6 +1803,7 @@ helm_status misfit_gradient_25d(helm_ctx* ctx, const helm_grid* g, const void* m
     HELM_REQUIRE((int64_t)nfreq * nsrc * nky <= kMaxPairs, "more than 65535 2D problems (nfreq*nsrc*nky)");
     const helm::SolveOpts so = opts_of(o);
     check_coarse_sizes(g, so);
+    scan_misfit_inputs(ctx, g, m, nfreq, nsrc, mask, nrec, d, stream);
     const PointSet S = on_node_points(g, nsrc, s3.data()), R = on_node_points(g, nrec, r3.data());
     if (g->dtype == HELM_C64)
       return model25d_t<float>(ctx, g, m, nfreq, omega, nky, p_kc, v_min, S, src_y, src_amp, mask, R, rec_y, d, f,
