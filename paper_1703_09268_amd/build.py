@@ -27,6 +27,10 @@ HIP_FLAGS = [
     "-Wno-unused-function",
     "-Wno-unused-variable",
     "-Wno-unused-result",
+    # roctx ranges (host markers of the API calls, solves and outer cycles)
+    "-L/opt/rocm/lib",
+    "-lrocprofiler-sdk-roctx",
+    "-Wl,-rpath,/opt/rocm/lib",
 ]
 
 

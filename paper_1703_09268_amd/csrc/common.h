@@ -5,8 +5,10 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <cstdint>
+#include <cstdlib>
 #include <string>
 
 namespace helm {
@@ -111,5 +113,22 @@ struct Error {
   } while (0)
 
 inline unsigned ceil_div(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+// A roctx range over a scope (host time from the first enqueue to the
+// synchronisation that ends the phase), shown by rocprofv3 --marker-trace.
+struct Range {
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
+
+// HELM_LOG=1: one line per outer cycle of every solve on stderr (active
+// right-hand sides, largest and smallest FP64 relative residual); 2: also
+// every right-hand side's residual.
+inline int log_level() {
+  const char* e = std::getenv("HELM_LOG");
+  return e ? std::atoi(e) : 0;
+}
 
 }  // namespace helm

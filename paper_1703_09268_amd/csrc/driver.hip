@@ -135,6 +135,7 @@ helm_status fwi_t(helm_ctx* ctx, const helm_grid* g, void* m, const double* lo, 
   std::vector<uint8_t> mask((size_t)nfreq * nsrc);
   for (int bi = 0; bi < (int)bands.size(); ++bi) {
     for (int t = 0; t < p.subproblems; ++t, ++ndraw) {
+      const Range rdraw("helm fwi draw");
       std::vector<int> sel(nsrc);
       for (int i = 0; i < nsrc; ++i) sel[i] = i;
       if (psz < nsrc) {

@@ -941,6 +941,7 @@ helm_status wri_t(helm_ctx* ctx, const helm_grid* g, const void* m, int nfreq, c
   }
   const unsigned fblk = std::min<unsigned>(1024, ceil_div(N, 256));
   for (int it = 0; it < cg_max; ++it) {
+    const Range rcg("helm wri CG step");
     int n_active = 0;
     for (int p = 0; p < np; ++p) n_active += active[p];
     if (n_active == 0) break;
@@ -1528,6 +1529,7 @@ size_t helm_workspace_bytes(const helm_grid* g, const helm_solver_opts* o, int n
 helm_status helm_apply(helm_ctx* ctx, const helm_grid* g, const void* m, double omega, int adjoint, int nrhs,
                        const void* x, void* y, void* stream) {
   return guarded(ctx, [&]() -> helm_status {
+    const helm::Range range_("helm_apply");
     check_grid(g);
     HELM_REQUIRE(m && x && y, "null device pointer");
     HELM_REQUIRE(omega > 0.0 && std::isfinite(omega), "omega must be positive");
@@ -1586,6 +1588,7 @@ helm_status helm_apply_noalloc(helm_ctx* ctx, const helm_grid* g, const void* m,
 helm_status helm_solve(helm_ctx* ctx, const helm_grid* g, const void* m, double omega, int adjoint, int nrhs,
                        const void* q, void* u, const helm_solver_opts* o, helm_solve_info* info, void* stream) {
   return guarded(ctx, [&]() -> helm_status {
+    const helm::Range range_("helm_solve");
     check_grid(g);
     HELM_REQUIRE(m && q && u, "null device pointer");
     HELM_REQUIRE(omega > 0.0 && std::isfinite(omega), "omega must be positive");
@@ -1606,6 +1609,7 @@ helm_status helm_solve(helm_ctx* ctx, const helm_grid* g, const void* m, double 
 helm_status helm_solve_batched(helm_ctx* ctx, int nprob, const helm_problem* probs, int adjoint,
                                const helm_solver_opts* o, helm_solve_info* info, void* stream) {
   return guarded(ctx, [&]() -> helm_status {
+    const helm::Range range_("helm_solve_batched");
     HELM_REQUIRE(nprob >= 1 && probs, "need at least one problem");
     const helm::SolveOpts so = opts_of(o);
     for (int i = 0; i < nprob; ++i) {
@@ -1637,6 +1641,7 @@ helm_status misfit_gradient(helm_ctx* ctx, const helm_grid* g, const void* m, in
                             const int32_t* rec_idx, const void* d, double* f, void* grad, void* u_store, int flags,
                             const helm_solver_opts* o, helm_solve_info* info, void* stream) {
   return guarded(ctx, [&]() -> helm_status {
+    const helm::Range range_("misfit_gradient");
     check_pair_args(g, m, nfreq, omega, nsrc, nrec);
     HELM_REQUIRE(src_idx && rec_idx, "null source / receiver index array");
     check_nodes(g, nsrc, src_idx, "source outside the grid");
@@ -1653,6 +1658,7 @@ helm_status misfit_gradient_offgrid(helm_ctx* ctx, const helm_grid* g, const voi
                                     double kaiser_b, const void* d, double* f, void* grad, void* u_store, int flags,
                                     const helm_solver_opts* o, helm_solve_info* info, void* stream) {
   return guarded(ctx, [&]() -> helm_status {
+    const helm::Range range_("misfit_gradient_offgrid");
     check_pair_args(g, m, nfreq, omega, nsrc, nrec);
     HELM_REQUIRE(src_pos && rec_pos, "null source / receiver position array");
     check_sinc(g, nsrc, src_pos, nrec, rec_pos, radius, kaiser_b);
@@ -1669,6 +1675,7 @@ helm_status pde_derivative(helm_ctx* ctx, int mode, const helm_grid* g, const vo
                            void* output, void* u_store, int flags, const helm_solver_opts* o, helm_solve_info* info,
                            void* stream) {
   return guarded(ctx, [&]() -> helm_status {
+    const helm::Range range_("pde_derivative");
     check_pair_args(g, m, nfreq, omega, nsrc, nrec);
     HELM_REQUIRE(src_idx && rec_idx, "null source / receiver index array");
     check_nodes(g, nsrc, src_idx, "source outside the grid");
@@ -1685,6 +1692,7 @@ helm_status pde_derivative_offgrid(helm_ctx* ctx, int mode, const helm_grid* g, 
                                    const void* input, const void* d, void* output, void* u_store, int flags,
                                    const helm_solver_opts* o, helm_solve_info* info, void* stream) {
   return guarded(ctx, [&]() -> helm_status {
+    const helm::Range range_("pde_derivative_offgrid");
     check_pair_args(g, m, nfreq, omega, nsrc, nrec);
     HELM_REQUIRE(src_pos && rec_pos, "null source / receiver position array");
     check_sinc(g, nsrc, src_pos, nrec, rec_pos, radius, kaiser_b);
@@ -1711,6 +1719,7 @@ helm_status fwi_invert(helm_ctx* ctx, const helm_grid* g, void* m, const double*
                        helm_fwi_draw* draws, int32_t* sources, helm_fwi_record* recs, int rec_cap, int* nrecs,
                        void* stream) {
   return guarded(ctx, [&]() -> helm_status {
+    const helm::Range range_("fwi_invert");
     check_pair_args(g, m, nfreq, omega, nsrc, nrec);
     HELM_REQUIRE(src_idx && rec_idx, "null source / receiver index array");
     check_nodes(g, nsrc, src_idx, "source outside the grid");
@@ -1728,6 +1737,7 @@ helm_status fwi_invert_offgrid(helm_ctx* ctx, const helm_grid* g, void* m, const
                                helm_fwi_draw* draws, int32_t* sources, helm_fwi_record* recs, int rec_cap,
                                int* nrecs, void* stream) {
   return guarded(ctx, [&]() -> helm_status {
+    const helm::Range range_("fwi_invert_offgrid");
     check_pair_args(g, m, nfreq, omega, nsrc, nrec);
     HELM_REQUIRE(src_pos && rec_pos, "null source / receiver position array");
     check_sinc(g, nsrc, src_pos, nrec, rec_pos, radius, kaiser_b);
@@ -1744,6 +1754,7 @@ helm_status wri_misfit_gradient(helm_ctx* ctx, const helm_grid* g, const void* m
                                 double cg_tol, int cg_max, double* f, void* grad, void* u_store, int flags,
                                 const helm_solver_opts* o, helm_solve_info* info, void* stream) {
   return guarded(ctx, [&]() -> helm_status {
+    const helm::Range range_("wri_misfit_gradient");
     check_pair_args(g, m, nfreq, omega, nsrc, nrec);
     HELM_REQUIRE(src_idx && rec_idx, "null source / receiver index array");
     check_nodes(g, nsrc, src_idx, "source outside the grid");
@@ -1775,6 +1786,7 @@ helm_status misfit_gradient_25d(helm_ctx* ctx, const helm_grid* g, const void* m
                                 const void* d, double* f, void* grad, void* d_pred, int flags,
                                 const helm_solver_opts* o, helm_solve_info* info, void* stream) {
   return guarded(ctx, [&]() -> helm_status {
+    const helm::Range range_("misfit_gradient_25d");
     check_pair_args(g, m, nfreq, omega, nsrc, nrec);
     HELM_REQUIRE(g->n[0] == 1, "2.5D modelling runs on a 2D grid (n[0] = 1)");
     HELM_REQUIRE(nky >= 1 && nky <= 4096, "nky must be in 1..4096");

@@ -21,6 +21,8 @@
 #pragma once
 
 #include <algorithm>
+#include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <memory>
 #include <vector>
@@ -104,6 +106,9 @@ class Solver {
   // level-0 vectors (segment s at offset Seg::off).  Returns the worst status.
   int solve(int dir, const cx<T>* q, cx<T>* u, SolveInfo* info) {
     HELM_REQUIRE(dir == 0 || dir == 1, "direction must be 0 (H) or 1 (H^H)");
+    const Range range(dir ? "helm solve H^H" : "helm solve H");
+    const int lg = log_level();
+    const char* const dname = dir ? "H^H" : "H";
     dir_ = dir;
     H_->set_dir(dir);
     H_->refresh_fine_models();
@@ -144,7 +149,10 @@ class Solver {
     }
     upload_active(act);
     fine_mv_ = 0;
+    int last_cycle = 0;
     for (int cyc = 0;; ++cyc) {
+      const Range rc("helm outer cycle");
+      last_cycle = cyc;
       // true residual in FP64, stored (rounded) as the first basis vector
       const int rng = launch_h<double, double, T, T, T, true, true>(L, X_, nullptr, q, nullptr, outer_.V[0],
                                                                     part_, active_, st_);
@@ -153,10 +161,15 @@ class Solver {
                          (const double*)nullptr, beta_dev_, (const int*)active_);
       HELM_HIP_CHECK(hipMemcpyAsync(beta.data(), beta_dev_, nseg_ * sizeof(double), hipMemcpyDeviceToHost, st_));
       HELM_HIP_CHECK(hipStreamSynchronize(st_));
-      int n_active = 0;
+      int n_active = 0, n_seen = 0;
+      double rmax = 0.0, rmin = HUGE_VAL;
       for (int s = 0; s < nseg_; ++s) {
         if (!act[s]) continue;
         const double rel = beta[s] / qn[s];
+        ++n_seen;
+        rmax = std::isnan(rel) ? rel : std::max(rmax, rel);
+        rmin = std::min(rmin, rel);
+        if (lg >= 2) std::fprintf(stderr, "helm:   rhs %d rel.res %.3e\n", s, rel);
         info[s].relres = rel;
         info[s].cycles = cyc;
         info[s].matvecs = fine_mv_;
@@ -173,6 +186,9 @@ class Solver {
           ++n_active;
         }
       }
+      if (lg >= 1)
+        std::fprintf(stderr, "helm: solve %s cycle %d: %d of %d right-hand sides checked, rel.res max %.3e min %.3e, %d "
+                     "continue\n", dname, cyc, n_seen, nseg_, rmax, n_seen ? rmin : 0.0, n_active);
       upload_active(act);
       if (n_active == 0) break;
       run_cycle_body();
@@ -184,8 +200,14 @@ class Solver {
                        (const cx<double>*)X_, u, L.total);
     HELM_HIP_CHECK(hipGetLastError());
     HELM_HIP_CHECK(hipStreamSynchronize(st_));
-    int worst = 0;
-    for (int s = 0; s < nseg_; ++s) worst = std::max(worst, info[s].status);
+    int worst = 0, nst[3] = {0, 0, 0};
+    for (int s = 0; s < nseg_; ++s) {
+      worst = std::max(worst, info[s].status);
+      nst[std::min(std::max(info[s].status, 0), 2)]++;
+    }
+    if (lg >= 1)
+      std::fprintf(stderr, "helm: solve %s done after %d cycles: %d converged, %d not converged, %d breakdown\n",
+                   dname, last_cycle, nst[0], nst[1], nst[2]);
     return worst;
   }
 

@@ -248,3 +248,24 @@ def test_tile_groups_leave_the_solve_bitwise_unchanged(monkeypatch):
     for u, info in outs[1:]:
         assert torch.equal(u, outs[0][0])
         assert [i.cycles for i in info] == [i.cycles for i in outs[0][1]]
+
+
+def test_helm_log_traces_every_outer_cycle(monkeypatch, capfd):
+    """HELM_LOG=2: one line per outer-cycle check (cycle 0 = the initial
+    residual) with the largest FP64 relative residual, the per-right-hand-side
+    residuals, and a closing line; the last check's residual is the one the
+    solve reports."""
+    import re
+    w = workloads.c1_small()
+    grid, g, m_t, m_used, cdt = _setup(w, "c64")
+    q, q_t = _sources(g, [(16, 16, 16), (10, 12, 20)], cdt)
+    capfd.readouterr()
+    monkeypatch.setenv("HELM_LOG", "2")
+    u_t, info = hx.helm_solve(grid, m_t, w.omega, q_t, opts=hx.SolverOpts(tol=1e-6))
+    torch.cuda.synchronize()
+    err = capfd.readouterr().err
+    lines = [ln for ln in err.splitlines() if ln.startswith("helm: solve H cycle")]
+    assert len(lines) == max(i.cycles for i in info) + 1, err
+    last = float(re.search(r"rel\.res max ([0-9.e+-]+)", lines[-1]).group(1))
+    assert abs(last - max(i.relres_fp64 for i in info if i.cycles == max(j.cycles for j in info))) <= 1e-3 * last
+    assert "rhs 1 rel.res" in err and "done after" in err and "2 converged" in err
