@@ -656,7 +656,24 @@ __global__ __launch_bounds__(256) void k_h27p(const Seg* __restrict__ segs, cons
   // plane's barrier, so its store overlaps the next plane instead of the
   // barrier's wait for every outstanding memory operation).
   c32x2 pend = {0.f, 0.f, 0.f, 0.f};
-  auto step = [&](const int ip, const Win& w, auto out_c, auto emit_c, auto defer_c) __attribute__((always_inline)) {
+  // the residual's right-hand side and the Arnoldi basis vectors at an output
+  // plane, loaded ahead (staged path: before the next plane's fill, so that
+  // waiting for them does not also wait for the fill)
+  struct Pre {
+    c32x2 bv;
+    c32x2 dv[NMEM > 0 ? NMEM : 1];
+  };
+  auto preload = [&](const int ipo) __attribute__((always_inline)) {
+    Pre pr;
+    const int64_t pob = (int64_t)ipo * plane * 8;
+    if (RESID) pr.bv = pld_c2(plane_rsrc(reinterpret_cast<const char*>(b + S.off) + pob, (uint32_t)plane * 8u), obo);
+#pragma unroll
+    for (int t = 0; t < NMEM; ++t)
+      pr.dv[t] = *reinterpret_cast<const c32x2*>(reinterpret_cast<const char*>(Vd.v[t] + S.off) + pob + obo);
+    return pr;
+  };
+  auto step = [&](const int ip, const Win& w, auto out_c, auto emit_c, auto defer_c,
+                  const Pre* pre = nullptr) __attribute__((always_inline)) {
     constexpr bool OUT = decltype(out_c)::value;
     constexpr bool EMIT = decltype(emit_c)::value;
     constexpr bool DEFER = decltype(defer_c)::value;
@@ -746,7 +763,7 @@ __global__ __launch_bounds__(256) void k_h27p(const Seg* __restrict__ segs, cons
       const int64_t pob = (int64_t)(ip - 1) * plane * 8;
       const uint32_t pbytes = (uint32_t)plane * 8u;
       if (RESID) {
-        const c32x2 bv = pld_c2(plane_rsrc(reinterpret_cast<const char*>(b + S.off) + pob, pbytes), obo);
+        const c32x2 bv = pre ? pre->bv : pld_c2(plane_rsrc(reinterpret_cast<const char*>(b + S.off) + pob, pbytes), obo);
         o0 = sb * mk(bv.a, bv.b) - o0;
         o1 = sb * mk(bv.c, bv.d) - o1;
       }
@@ -765,8 +782,9 @@ __global__ __launch_bounds__(256) void k_h27p(const Seg* __restrict__ segs, cons
           const c32x2 v =
               (SELF && t == ND - 1)
                   ? xself
-                  : *reinterpret_cast<const c32x2*>(reinterpret_cast<const char*>(Vd.v[t < NMEM ? t : 0] + S.off) +
-                                                     pob + obo);
+                  : (pre ? pre->dv[t < NMEM ? t : 0]
+                         : *reinterpret_cast<const c32x2*>(
+                               reinterpret_cast<const char*>(Vd.v[t < NMEM ? t : 0] + S.off) + pob + obo));
           dr[t] += (double)v.a * u0.re + (double)v.b * u0.im + ((double)v.c * u1.re + (double)v.d * u1.im);
           di[t] += (double)v.a * u0.im - (double)v.b * u0.re + ((double)v.c * u1.im - (double)v.d * u1.re);
         }
@@ -883,8 +901,14 @@ __global__ __launch_bounds__(256) void k_h27p(const Seg* __restrict__ segs, cons
     }
     for (; ip < i1; ++ip) {
       const Win w = read_win(cur);
-      if (ip + 1 < nx) fill(ip + 1, bstride - cur);
-      step(ip, w, std::false_type{}, std::true_type{}, std::true_type{});
+      if (RESID || NMEM > 0) {
+        const Pre pr = preload(ip - 1);
+        if (ip + 1 < nx) fill(ip + 1, bstride - cur);
+        step(ip, w, std::false_type{}, std::true_type{}, std::true_type{}, &pr);
+      } else {
+        if (ip + 1 < nx) fill(ip + 1, bstride - cur);
+        step(ip, w, std::false_type{}, std::true_type{}, std::true_type{});
+      }
       settle();
       flush(ip - 1);  // after the barrier
       cur = bstride - cur;
